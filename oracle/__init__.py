@@ -1,0 +1,243 @@
+"""FP64 CPU oracle for the 6DGS renderer -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_2410_04974_amd``) and neither imports the other; the only common input
+is the seeded generator module ``synth``.
+
+Pieces:
+
+* ``liboracle6dgs.so`` (``oracle6dgs.c``): the brute-force renderer, its
+  analytic backward, the slice and the SH basis, all in double precision.
+* ``binning``: the integer stage (tile rectangles, (tile, depth) keys, stable
+  sort, per-tile ranges) as its plain definition in numpy, taking its decisions
+  in float32 as the GPU does.
+* ``l1_loss`` and ``adam_step``: textbook definitions in float64.
+
+Readings of the paper where it is silent or ambiguous are listed in the module
+docstring of ``oracle6dgs.c`` and in the project's design notes.
+
+Parity status: every function here is pinned by a ``-m "not gpu"`` test
+(closed forms, library routines, finite differences, brute force).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle6dgs.c")
+_LIB = os.path.join(_HERE, "liboracle6dgs.so")
+
+NROWS = 76
+NREC = 37
+NG2D = 9
+FIELDS = {
+    "alive": (0, 1), "mu_cond": (1, 3), "sigma_cond": (4, 6), "alpha": (10, 1), "f": (11, 1),
+    "D": (12, 1), "alpha_cond": (13, 1), "rgb": (14, 3), "p": (17, 3), "depth": (20, 1),
+    "u": (21, 1), "v": (22, 1), "cov2d": (23, 3), "conic": (26, 3), "ex": (29, 1), "ey": (30, 1),
+    "dir": (31, 3), "sh_dir": (34, 3),
+}
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (double precision, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("width", ctypes.c_int64), ("height", ctypes.c_int64)]
+
+
+class _Set(ctypes.Structure):
+    _fields_ = [("lambda_opa", ctypes.c_double), ("z_near", ctypes.c_double), ("bg", ctypes.c_double * 3),
+                ("jac_guard", ctypes.c_double), ("dilation", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("alpha_min", ctypes.c_double), ("t_min", ctypes.c_double), ("amb_alpha_min", ctypes.c_double),
+                ("amb_alpha_max", ctypes.c_double), ("amb_t_min", ctypes.c_double), ("amb_depth", ctypes.c_double),
+                ("amb_impact", ctypes.c_double)]
+
+
+@dataclass
+class Settings:
+    """Renderer settings.  lambda_opa = 0.35 is the paper's value (Sec. 5.1);
+    the rasteriser constants are the 3D Gaussian splatting ones (Sec. 4.4 says
+    the pipeline after the slice is that of 3DGS but does not print them)."""
+
+    lambda_opa: float = 0.35
+    z_near: float = 0.2
+    bg: tuple = (0.0, 0.0, 0.0)
+    jac_guard: float = 1.3
+    dilation: float = 0.3
+    alpha_max: float = 0.99
+    alpha_min: float = 1.0 / 255.0
+    t_min: float = 1e-4
+    # Margins within which a float32 renderer may legitimately take a threshold
+    # decision the other way; pixels with such a decision are flagged ambiguous.
+    amb_alpha_min: float = 2e-6
+    amb_alpha_max: float = 1e-5
+    amb_t_min: float = 1e-7
+    amb_depth: float = 5e-7
+    amb_impact: float = 2.5e-5
+
+    def _c(self) -> _Set:
+        return _Set(self.lambda_opa, self.z_near, (ctypes.c_double * 3)(*self.bg), self.jac_guard,
+                    self.dilation, self.alpha_max, self.alpha_min, self.t_min, self.amb_alpha_min,
+                    self.amb_alpha_max, self.amb_t_min, self.amb_depth, self.amb_impact)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        _lib.orc_preprocess.argtypes = [I64, P, P, P, P]
+        _lib.orc_render.argtypes = [I64, P, P, P, I64, P, P, P, P, P, ctypes.c_int]
+        _lib.orc_backward.argtypes = [I64, P, P, P, I64, P, P, P, P, ctypes.c_int]
+        _lib.orc_slice.argtypes = [I64, P, P, ctypes.c_double, P]
+        _lib.orc_sh_basis.argtypes = [I64, P, P]
+        _lib.orc_record_vjp.argtypes = [I64, P, P, P, P, P]
+        _lib.orc_num_threads.argtypes = [ctypes.c_int]
+        _lib.orc_render.restype = ctypes.c_int
+        _lib.orc_backward.restype = ctypes.c_int
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _params64(params) -> np.ndarray:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    assert p.ndim == 2 and p.shape[0] == NROWS
+    return p
+
+
+def _cam(cam) -> _Cam:
+    c = _Cam()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float64).reshape(9)]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float64).reshape(3)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def num_threads(req: int = 0) -> int:
+    return int(lib().orc_num_threads(req))
+
+
+def preprocess(params, cam, settings: Settings = Settings()) -> dict:
+    """Per-Gaussian record for one camera: slice, colour, projection, extents."""
+    p = _params64(params)
+    n = p.shape[1]
+    rec = np.zeros((n, NREC), np.float64)
+    c, s = _cam(cam), settings._c()
+    lib().orc_preprocess(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), _ptr(rec))
+    out = {}
+    for k, (o, w) in FIELDS.items():
+        out[k] = rec[:, o] if w == 1 else rec[:, o:o + w]
+    out["alive"] = out["alive"] != 0
+    return out
+
+
+def render(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0):
+    """Brute-force render.  Returns (color, T_final, n_contrib, ambiguous); with
+    ``pixels=None`` color is [3, H, W] and the others [H, W]; otherwise color is
+    [npix, 3] and the others [npix] for the listed row-major pixel ids."""
+    p = _params64(params)
+    n = p.shape[1]
+    c, s = _cam(cam), settings._c()
+    full = pixels is None
+    npix = cam.width * cam.height if full else len(pixels)
+    pix = None if full else np.ascontiguousarray(np.asarray(pixels, np.int64))
+    color = np.zeros((npix, 3), np.float64)
+    T = np.zeros(npix, np.float64)
+    nc = np.zeros(npix, np.int64)
+    amb = np.zeros(npix, np.int32)
+    rc = lib().orc_render(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), npix,
+                          None if full else _ptr(pix), _ptr(color), _ptr(T), _ptr(nc), _ptr(amb), nthreads)
+    if rc != 0:
+        raise MemoryError("oracle render failed")
+    if full:
+        H, W = cam.height, cam.width
+        return color.T.reshape(3, H, W), T.reshape(H, W), nc.reshape(H, W), amb.reshape(H, W).astype(bool)
+    return color, T, nc, amb.astype(bool)
+
+
+def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=None, nthreads: int = 0):
+    """Analytic gradient of sum(dl_dimage * image) w.r.t. the 76 raw parameter
+    rows.  ``dl_dimage`` is [3, H, W] (pixels=None) or [npix, 3].  Returns
+    (grad [76, N], g2d [N, 9]) with g2d the per-Gaussian screen-space gradients
+    (du, dv, dQxx, dQxy, dQyy, dalpha_cond, dr, dg, db)."""
+    p = _params64(params)
+    n = p.shape[1]
+    c, s = _cam(cam), settings._c()
+    full = pixels is None
+    if full:
+        npix = cam.width * cam.height
+        dl = np.ascontiguousarray(np.asarray(dl_dimage, np.float64).reshape(3, -1).T)
+        pix = None
+    else:
+        npix = len(pixels)
+        pix = np.ascontiguousarray(np.asarray(pixels, np.int64))
+        dl = np.ascontiguousarray(np.asarray(dl_dimage, np.float64).reshape(npix, 3))
+    grad = np.zeros((NROWS, n), np.float64)
+    g2d = np.zeros((n, NG2D), np.float64)
+    rc = lib().orc_backward(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), npix, None if full else _ptr(pix),
+                            _ptr(dl), _ptr(grad), _ptr(g2d), nthreads)
+    if rc != 0:
+        raise MemoryError("oracle backward failed")
+    return grad, g2d
+
+
+def slice_gaussians(params, dirs, lambda_opa: float):
+    """Slice every Gaussian at its own unit direction (dirs [N, 3]).  Returns
+    (mu_cond [N,3], sigma_cond [N,3,3], D [N], f [N], alpha_cond [N])."""
+    p = _params64(params)
+    n = p.shape[1]
+    d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(n, 3))
+    out = np.zeros((n, 12), np.float64)
+    lib().orc_slice(n, _ptr(p), _ptr(d), float(lambda_opa), _ptr(out))
+    s = out[:, 3:9]
+    sig = np.stack([s[:, [0, 1, 2]], s[:, [1, 3, 4]], s[:, [2, 4, 5]]], axis=1)
+    return out[:, 0:3], sig, out[:, 9], out[:, 10], out[:, 11]
+
+
+def sh_basis(dirs) -> np.ndarray:
+    """Real SH basis, degree 3 (16 values) at unit directions [M, 3]."""
+    d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 3))
+    out = np.zeros((d.shape[0], 16), np.float64)
+    lib().orc_sh_basis(d.shape[0], _ptr(d), _ptr(out))
+    return out
+
+
+def record_vjp(params, cam, g2d, settings: Settings = Settings()) -> np.ndarray:
+    """Gradient w.r.t. raw parameters of sum(g2d * (u, v, Q, alpha_cond, rgb))."""
+    p = _params64(params)
+    n = p.shape[1]
+    g = np.ascontiguousarray(np.asarray(g2d, np.float64).reshape(n, NG2D))
+    grad = np.zeros((NROWS, n), np.float64)
+    c, s = _cam(cam), settings._c()
+    lib().orc_record_vjp(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), _ptr(g), _ptr(grad))
+    return grad
+
+
+from .binning import bin_records, tile_grid  # noqa: E402
+from .train import adam_step, l1_loss, densify_stats  # noqa: E402
+
+__all__ = ["Settings", "build", "preprocess", "render", "backward", "slice_gaussians", "sh_basis",
+           "record_vjp", "bin_records", "tile_grid", "adam_step", "l1_loss", "densify_stats", "num_threads"]

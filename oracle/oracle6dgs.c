@@ -1,0 +1,767 @@
+/*
+ * oracle6dgs.c -- plain, slow FP64 CPU reference renderer for view-conditioned
+ * 6D Gaussians.  TEST INFRASTRUCTURE ONLY: it exists so that tests, the smoke
+ * check and the benchmark's CPU-baseline leg can check and time the GPU path.
+ * It shares no code, header, table or constant with the GPU library and must
+ * never be called by the product path.
+ *
+ * What it computes, step by step, and where each step comes from:
+ *   - Cholesky parameterisation Sigma = L L^T, exp on the diagonal, a value in
+ *     (-1, 1) off the diagonal, read here as 2*sigmoid(r) - 1 (Sec. 3.1);
+ *     opacity alpha = sigmoid(logit) (Sec. 3.1 names an opacity; its activation
+ *     is not stated and is read as the sigmoid).
+ *   - block partition of Sigma into Sigma_p, Sigma_pd, Sigma_d (Sec. 3.2, eq. 1;
+ *     Algorithm 1 steps 1-2).
+ *   - conditional mean and Schur-complement covariance (Sec. 3.2, eq:mu and
+ *     eq:sigma; Algorithm 1 step 3).
+ *   - directional opacity f = exp(-lambda (d-mu_d)^T Sigma_d^-1 (d-mu_d)),
+ *     alpha_cond = alpha f, with no factor 1/2 as printed (Sec. 4.2 eq:pdfv2,
+ *     Sec. 3.2 eq:alpha).  The view direction d is the unit vector from the
+ *     camera centre to mu_p.
+ *   - colour = sigmoid of a degree-3 real SH expansion with 48 coefficients
+ *     (Sec. 4.2), evaluated at the unit vector from the camera centre to
+ *     mu_cond; textbook real SH without the Condon-Shortley phase.
+ *   - after the slice the renderer is the 3D Gaussian splatting rasteriser
+ *     (Sec. 4.4): EWA projection with the 1.3 Jacobian guard and 0.3 screen
+ *     dilation, per-pixel front-to-back compositing with alpha clamped at 0.99,
+ *     contributions below 1/255 skipped and the walk stopped before the
+ *     transmittance would fall below 1e-4.  Here every alive Gaussian is
+ *     evaluated at every pixel, in one global (depth, index) order.
+ *   - backward: the analytic derivative of the above, written out by hand
+ *     (reverse compositing, then projection, SH, slice, Cholesky, activations).
+ *
+ * Everything is double precision; compile with -O2 -ffp-contract=off and no
+ * fast-math.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define NROWS 76
+#define ROW_MU_P 0
+#define ROW_MU_D 3
+#define ROW_L 6
+#define ROW_SH 27
+#define ROW_OPA 75
+
+/* Record fields (per Gaussian, per camera), double, row length NREC. */
+enum {
+  F_ALIVE = 0,
+  F_MUC = 1,      /* 3: conditional mean */
+  F_SIGC = 4,     /* 6: conditional covariance xx, xy, xz, yy, yz, zz */
+  F_ALPHA = 10,   /* base opacity sigmoid(logit) */
+  F_F = 11,       /* directional factor f */
+  F_D = 12,       /* Mahalanobis distance D */
+  F_ALPHAC = 13,  /* alpha_cond */
+  F_RGB = 14,     /* 3 */
+  F_P = 17,       /* 3: camera-space mean */
+  F_DEPTH = 20,
+  F_U = 21,
+  F_V = 22,
+  F_COV2D = 23,   /* 3: xx, xy, yy */
+  F_CONIC = 26,   /* 3: xx, xy, yy of the inverse 2D covariance */
+  F_EX = 29,
+  F_EY = 30,
+  F_DIR = 31,     /* 3: slice direction d */
+  F_SHDIR = 34,   /* 3: SH direction */
+  NREC = 37
+};
+
+typedef struct {
+  double R[9];
+  double t[3];
+  double fx, fy, cx, cy;
+  int64_t width, height;
+} orc_camera;
+
+typedef struct {
+  double lambda_opa;
+  double z_near;
+  double bg[3];
+  double jac_guard;  /* 1.3 */
+  double dilation;   /* 0.3 */
+  double alpha_max;  /* 0.99 */
+  double alpha_min;  /* 1/255 */
+  double t_min;      /* 1e-4 */
+  /* ambiguity margins: a pixel is flagged when a decision of the walk lies
+   * within these of its threshold, where float32 rounding could flip it */
+  double amb_alpha_min; /* |a - alpha_min| */
+  double amb_alpha_max; /* |alpha_raw - alpha_max| (kink of the clamp) */
+  double amb_t_min;     /* |T' - t_min| */
+  double amb_depth;     /* relative depth gap between consecutive contributors */
+  double amb_impact;    /* smallest colour change a flip at the 1/255 cut must be able to make */
+} orc_settings;
+
+static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* ---------------------------------------------------------------- algebra */
+static void inv3(const double a[3][3], double out[3][3], double *det_out) {
+  /* adjugate over determinant */
+  double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+  double c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+  double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+  double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+  double id = 1.0 / det;
+  out[0][0] = c00 * id;
+  out[1][0] = c01 * id;
+  out[2][0] = c02 * id;
+  out[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) * id;
+  out[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) * id;
+  out[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) * id;
+  out[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) * id;
+  out[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) * id;
+  out[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) * id;
+  if (det_out) *det_out = det;
+}
+
+static void mm3(const double a[3][3], const double b[3][3], double o[3][3]) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0;
+      for (int k = 0; k < 3; k++) s += a[i][k] * b[k][j];
+      o[i][j] = s;
+    }
+}
+
+static void mm3t(const double a[3][3], const double b[3][3], double o[3][3]) { /* a b^T */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0;
+      for (int k = 0; k < 3; k++) s += a[i][k] * b[j][k];
+      o[i][j] = s;
+    }
+}
+
+static void mtm3(const double a[3][3], const double b[3][3], double o[3][3]) { /* a^T b */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0;
+      for (int k = 0; k < 3; k++) s += a[k][i] * b[k][j];
+      o[i][j] = s;
+    }
+}
+
+/* ------------------------------------------------------------ SH (Sec 4.2) */
+/* Normalisation constants of the real spherical harmonics, from their closed
+ * forms sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the polynomial factors. */
+static double SHK[16];
+static int sh_ready = 0;
+static void sh_init(void) {
+  if (sh_ready) return;
+  const double pi = 3.14159265358979323846;
+  SHK[0] = 0.5 * sqrt(1.0 / pi);
+  SHK[1] = SHK[2] = SHK[3] = sqrt(3.0 / (4.0 * pi));
+  SHK[4] = 0.5 * sqrt(15.0 / pi);   /* xy */
+  SHK[5] = 0.5 * sqrt(15.0 / pi);   /* yz */
+  SHK[6] = 0.25 * sqrt(5.0 / pi);   /* 3z^2-1 */
+  SHK[7] = 0.5 * sqrt(15.0 / pi);   /* xz */
+  SHK[8] = 0.25 * sqrt(15.0 / pi);  /* x^2-y^2 */
+  SHK[9] = 0.25 * sqrt(35.0 / (2.0 * pi));   /* y(3x^2-y^2) */
+  SHK[10] = 0.5 * sqrt(105.0 / pi);          /* xyz */
+  SHK[11] = 0.25 * sqrt(21.0 / (2.0 * pi));  /* y(5z^2-1) */
+  SHK[12] = 0.25 * sqrt(7.0 / pi);           /* z(5z^2-3) */
+  SHK[13] = 0.25 * sqrt(21.0 / (2.0 * pi));  /* x(5z^2-1) */
+  SHK[14] = 0.25 * sqrt(105.0 / pi);         /* z(x^2-y^2) */
+  SHK[15] = 0.25 * sqrt(35.0 / (2.0 * pi));  /* x(x^2-3y^2) */
+  sh_ready = 1;
+}
+
+/* Basis values at unit direction (x, y, z); optional gradient w.r.t. (x, y, z)
+ * of the polynomials as written. */
+static void sh_eval(const double s[3], double Y[16], double dY[16][3]) {
+  double x = s[0], y = s[1], z = s[2];
+  const double *K = SHK;
+  Y[0] = K[0];
+  Y[1] = K[1] * y;
+  Y[2] = K[2] * z;
+  Y[3] = K[3] * x;
+  Y[4] = K[4] * x * y;
+  Y[5] = K[5] * y * z;
+  Y[6] = K[6] * (3 * z * z - 1);
+  Y[7] = K[7] * x * z;
+  Y[8] = K[8] * (x * x - y * y);
+  Y[9] = K[9] * y * (3 * x * x - y * y);
+  Y[10] = K[10] * x * y * z;
+  Y[11] = K[11] * y * (5 * z * z - 1);
+  Y[12] = K[12] * z * (5 * z * z - 3);
+  Y[13] = K[13] * x * (5 * z * z - 1);
+  Y[14] = K[14] * z * (x * x - y * y);
+  Y[15] = K[15] * x * (x * x - 3 * y * y);
+  if (!dY) return;
+  memset(dY, 0, sizeof(double) * 48);
+  dY[1][1] = K[1];
+  dY[2][2] = K[2];
+  dY[3][0] = K[3];
+  dY[4][0] = K[4] * y; dY[4][1] = K[4] * x;
+  dY[5][1] = K[5] * z; dY[5][2] = K[5] * y;
+  dY[6][2] = K[6] * 6 * z;
+  dY[7][0] = K[7] * z; dY[7][2] = K[7] * x;
+  dY[8][0] = K[8] * 2 * x; dY[8][1] = -K[8] * 2 * y;
+  dY[9][0] = K[9] * 6 * x * y; dY[9][1] = K[9] * (3 * x * x - 3 * y * y);
+  dY[10][0] = K[10] * y * z; dY[10][1] = K[10] * x * z; dY[10][2] = K[10] * x * y;
+  dY[11][1] = K[11] * (5 * z * z - 1); dY[11][2] = K[11] * 10 * y * z;
+  dY[12][2] = K[12] * (15 * z * z - 3);
+  dY[13][0] = K[13] * (5 * z * z - 1); dY[13][2] = K[13] * 10 * x * z;
+  dY[14][0] = K[14] * 2 * x * z; dY[14][1] = -K[14] * 2 * y * z; dY[14][2] = K[14] * (x * x - y * y);
+  dY[15][0] = K[15] * (3 * x * x - 3 * y * y); dY[15][1] = -K[15] * 6 * x * y;
+}
+
+void orc_sh_basis(int64_t m, const double *dirs, double *out) {
+  sh_init();
+  for (int64_t i = 0; i < m; i++) sh_eval(dirs + 3 * i, out + 16 * i, NULL);
+}
+
+/* ----------------------------------------------------------- the 6D model */
+typedef struct {
+  double L[6][6];
+  double Sp[3][3], Spd[3][3], Sd[3][3];
+  double A[3][3];  /* Sigma_d^-1 */
+  double K[3][3];  /* Sigma_pd A */
+  double Sc[3][3]; /* Sigma_cond */
+  double mu_p[3], mu_d[3];
+  double alpha;
+} g6;
+
+static double P(const double *params, int64_t n, int row, int64_t i) { return params[(int64_t)row * n + i]; }
+
+/* Steps 1-2 of Algorithm 1 plus the direction-independent part of step 3. */
+static void load_g6(const double *params, int64_t n, int64_t i, g6 *g) {
+  memset(g, 0, sizeof(*g));
+  for (int r = 0; r < 6; r++)
+    for (int c = 0; c <= r; c++) {
+      double raw = P(params, n, ROW_L + r * (r + 1) / 2 + c, i);
+      g->L[r][c] = (r == c) ? exp(raw) : 2.0 * sigm(raw) - 1.0;
+    }
+  double S[6][6];
+  for (int r = 0; r < 6; r++)
+    for (int c = 0; c < 6; c++) {
+      double s = 0;
+      for (int k = 0; k < 6; k++) s += g->L[r][k] * g->L[c][k];
+      S[r][c] = s;
+    }
+  for (int r = 0; r < 3; r++)
+    for (int c = 0; c < 3; c++) {
+      g->Sp[r][c] = S[r][c];
+      g->Spd[r][c] = S[r][3 + c];
+      g->Sd[r][c] = S[3 + r][3 + c];
+    }
+  inv3(g->Sd, g->A, NULL);
+  mm3(g->Spd, g->A, g->K);
+  double KSt[3][3];
+  mm3t(g->K, g->Spd, KSt);
+  for (int r = 0; r < 3; r++)
+    for (int c = 0; c < 3; c++) g->Sc[r][c] = g->Sp[r][c] - KSt[r][c];
+  for (int k = 0; k < 3; k++) {
+    g->mu_p[k] = P(params, n, ROW_MU_P + k, i);
+    g->mu_d[k] = P(params, n, ROW_MU_D + k, i);
+  }
+  g->alpha = sigm(P(params, n, ROW_OPA, i));
+}
+
+/* Direction-dependent part of step 3: mu_cond, D, f, alpha_cond for direction d. */
+static void slice_dir(const g6 *g, const double d[3], double lambda, double mu_c[3], double x[3],
+                      double *D, double *f, double *alpha_c) {
+  double Ax[3];
+  for (int k = 0; k < 3; k++) x[k] = d[k] - g->mu_d[k];
+  for (int r = 0; r < 3; r++) {
+    Ax[r] = g->A[r][0] * x[0] + g->A[r][1] * x[1] + g->A[r][2] * x[2];
+    mu_c[r] = g->mu_p[r] + g->K[r][0] * x[0] + g->K[r][1] * x[1] + g->K[r][2] * x[2];
+  }
+  *D = x[0] * Ax[0] + x[1] * Ax[1] + x[2] * Ax[2];
+  *f = exp(-lambda * (*D));
+  *alpha_c = g->alpha * (*f);
+}
+
+/* Slice for arbitrary unit directions: out[i] = mu_cond(3), Sigma_cond(6), D, f, alpha_cond. */
+void orc_slice(int64_t n, const double *params, const double *dirs, double lambda, double *out) {
+  for (int64_t i = 0; i < n; i++) {
+    g6 g;
+    load_g6(params, n, i, &g);
+    double mu_c[3], x[3], D, f, ac;
+    slice_dir(&g, dirs + 3 * i, lambda, mu_c, x, &D, &f, &ac);
+    double *o = out + 12 * i;
+    o[0] = mu_c[0]; o[1] = mu_c[1]; o[2] = mu_c[2];
+    o[3] = g.Sc[0][0]; o[4] = g.Sc[0][1]; o[5] = g.Sc[0][2];
+    o[6] = g.Sc[1][1]; o[7] = g.Sc[1][2]; o[8] = g.Sc[2][2];
+    o[9] = D; o[10] = f; o[11] = ac;
+  }
+}
+
+static void cam_center(const orc_camera *c, double C[3]) {
+  for (int k = 0; k < 3; k++) C[k] = -(c->R[0 + k] * c->t[0] + c->R[3 + k] * c->t[1] + c->R[6 + k] * c->t[2]);
+}
+
+/* Per-Gaussian record for one camera (the whole pre-rasterisation pipeline). */
+static void record_one(const double *params, int64_t n, int64_t i, const orc_camera *cam,
+                       const orc_settings *s, double *rec) {
+  memset(rec, 0, sizeof(double) * NREC);
+  g6 g;
+  load_g6(params, n, i, &g);
+  double C[3];
+  cam_center(cam, C);
+  double d[3], nd = 0;
+  for (int k = 0; k < 3; k++) { d[k] = g.mu_p[k] - C[k]; nd += d[k] * d[k]; }
+  nd = sqrt(nd);
+  for (int k = 0; k < 3; k++) d[k] /= nd;
+  double mu_c[3], x[3], D, f, ac;
+  slice_dir(&g, d, s->lambda_opa, mu_c, x, &D, &f, &ac);
+  for (int k = 0; k < 3; k++) { rec[F_MUC + k] = mu_c[k]; rec[F_DIR + k] = d[k]; }
+  rec[F_SIGC + 0] = g.Sc[0][0]; rec[F_SIGC + 1] = g.Sc[0][1]; rec[F_SIGC + 2] = g.Sc[0][2];
+  rec[F_SIGC + 3] = g.Sc[1][1]; rec[F_SIGC + 4] = g.Sc[1][2]; rec[F_SIGC + 5] = g.Sc[2][2];
+  rec[F_ALPHA] = g.alpha; rec[F_F] = f; rec[F_D] = D; rec[F_ALPHAC] = ac;
+  /* colour */
+  double sdir[3], ns = 0;
+  for (int k = 0; k < 3; k++) { sdir[k] = mu_c[k] - C[k]; ns += sdir[k] * sdir[k]; }
+  ns = sqrt(ns);
+  for (int k = 0; k < 3; k++) { sdir[k] /= ns; rec[F_SHDIR + k] = sdir[k]; }
+  double Y[16];
+  sh_eval(sdir, Y, NULL);
+  for (int c = 0; c < 3; c++) {
+    double acc = 0;
+    for (int k = 0; k < 16; k++) acc += P(params, n, ROW_SH + 3 * k + c, i) * Y[k];
+    rec[F_RGB + c] = sigm(acc);
+  }
+  /* camera transform and projection */
+  double p[3];
+  for (int r = 0; r < 3; r++)
+    p[r] = cam->R[3 * r] * mu_c[0] + cam->R[3 * r + 1] * mu_c[1] + cam->R[3 * r + 2] * mu_c[2] + cam->t[r];
+  for (int k = 0; k < 3; k++) rec[F_P + k] = p[k];
+  rec[F_DEPTH] = p[2];
+  if (!(p[2] > s->z_near)) return;
+  double z = p[2];
+  rec[F_U] = cam->fx * p[0] / z + cam->cx;
+  rec[F_V] = cam->fy * p[1] / z + cam->cy;
+  double limx = s->jac_guard * (0.5 * (double)cam->width) / cam->fx;
+  double limy = s->jac_guard * (0.5 * (double)cam->height) / cam->fy;
+  double xt = fmin(limx, fmax(-limx, p[0] / z));
+  double yt = fmin(limy, fmax(-limy, p[1] / z));
+  double J[2][3] = {{cam->fx / z, 0, -cam->fx * xt / z}, {0, cam->fy / z, -cam->fy * yt / z}};
+  double T[2][3];
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 3; c++) T[r][c] = J[r][0] * cam->R[c] + J[r][1] * cam->R[3 + c] + J[r][2] * cam->R[6 + c];
+  double TS[2][3];
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 3; c++) TS[r][c] = T[r][0] * g.Sc[0][c] + T[r][1] * g.Sc[1][c] + T[r][2] * g.Sc[2][c];
+  double cxx = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + s->dilation;
+  double cxy = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+  double cyy = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + s->dilation;
+  rec[F_COV2D + 0] = cxx; rec[F_COV2D + 1] = cxy; rec[F_COV2D + 2] = cyy;
+  double det = cxx * cyy - cxy * cxy;
+  if (!(det > 0)) return;
+  rec[F_CONIC + 0] = cyy / det;
+  rec[F_CONIC + 1] = -cxy / det;
+  rec[F_CONIC + 2] = cxx / det;
+  if (!(ac * 255.0 >= 1.0)) return;
+  double qmax = 2.0 * log(255.0 * ac);
+  rec[F_EX] = sqrt(qmax * cxx);
+  rec[F_EY] = sqrt(qmax * cyy);
+  rec[F_ALIVE] = 1.0;
+}
+
+void orc_preprocess(int64_t n, const double *params, const orc_camera *cam, const orc_settings *s, double *rec) {
+  sh_init();
+  for (int64_t i = 0; i < n; i++) record_one(params, n, i, cam, s, rec + NREC * i);
+}
+
+/* ------------------------------------------------------- global depth order */
+typedef struct { double depth; int64_t idx; } order_item;
+static int cmp_order(const void *a, const void *b) {
+  const order_item *x = a, *y = b;
+  if (x->depth < y->depth) return -1;
+  if (x->depth > y->depth) return 1;
+  return (x->idx < y->idx) ? -1 : (x->idx > y->idx);
+}
+
+/* Alive Gaussians sorted by (depth, index); returns their count. */
+static int64_t global_order(int64_t n, const double *rec, int64_t *order) {
+  order_item *it = malloc(sizeof(order_item) * (n > 0 ? n : 1));
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i++)
+    if (rec[NREC * i + F_ALIVE] != 0.0) { it[m].depth = rec[NREC * i + F_DEPTH]; it[m].idx = i; m++; }
+  qsort(it, m, sizeof(order_item), cmp_order);
+  for (int64_t k = 0; k < m; k++) order[k] = it[k].idx;
+  free(it);
+  return m;
+}
+
+/* Compact view of the sorted alive records, so the per-pixel walk reads one array. */
+typedef struct { double u, v, qa, qb, qc, ac, r, g, b, depth; } sorted_rec;
+
+static sorted_rec *make_sorted(const double *rec, const int64_t *order, int64_t m) {
+  sorted_rec *sr = malloc(sizeof(sorted_rec) * (m > 0 ? m : 1));
+  for (int64_t k = 0; k < m; k++) {
+    const double *r = rec + NREC * order[k];
+    sr[k].u = r[F_U]; sr[k].v = r[F_V];
+    sr[k].qa = r[F_CONIC]; sr[k].qb = r[F_CONIC + 1]; sr[k].qc = r[F_CONIC + 2];
+    sr[k].ac = r[F_ALPHAC];
+    sr[k].r = r[F_RGB]; sr[k].g = r[F_RGB + 1]; sr[k].b = r[F_RGB + 2];
+    sr[k].depth = r[F_DEPTH];
+  }
+  return sr;
+}
+
+/* ----------------------------------------------------- per-pixel compositing */
+/* Walks one pixel; fills colour, final T, contributor count and the ambiguity
+ * flag; if clist != NULL stores the contributors' sorted positions, their alpha
+ * before the clamp and the transmittance in front of them. */
+typedef struct {
+  double color[3];
+  double T;
+  int64_t ncontrib;
+  int ambiguous;
+} pix_out;
+
+static void walk_pixel(const sorted_rec *sr, int64_t m, double px, double py, const orc_settings *s,
+                       pix_out *o, int64_t *clist, double *araw_list, double *T_list) {
+  double T = 1.0, C[3] = {0, 0, 0};
+  int64_t nc = 0;
+  int amb = 0;
+  double last_depth = 0.0, last_wt = 0.0; /* depth and a*T of the previous contributor */
+  for (int64_t k = 0; k < m; k++) {
+    const sorted_rec *g = sr + k;
+    double dx = px - g->u, dy = py - g->v;
+    double q = g->qa * dx * dx + 2.0 * g->qb * dx * dy + g->qc * dy * dy;
+    double araw = g->ac * exp(-0.5 * q);
+    double a = fmin(s->alpha_max, araw);
+    /* including or skipping a Gaussian right at the 1/255 cut changes this
+     * pixel by at most about 2 T a; only flag where that is not negligible */
+    if (fabs(a - s->alpha_min) < s->amb_alpha_min && 2.0 * T * a > s->amb_impact) amb = 1;
+    if (a < s->alpha_min) continue;
+    if (fabs(araw - s->alpha_max) < s->amb_alpha_max) amb = 1;
+    /* swapping two consecutive contributors changes the pixel by at most
+     * T_prev a_prev a (colours lie in [0, 1]) */
+    if (nc > 0 && fabs(g->depth - last_depth) < s->amb_depth * fmax(fabs(g->depth), fabs(last_depth)) &&
+        last_wt * a > s->amb_impact)
+      amb = 1;
+    double Tn = T * (1.0 - a);
+    if (fabs(Tn - s->t_min) < s->amb_t_min) amb = 1;
+    if (Tn < s->t_min) break;
+    C[0] += g->r * a * T;
+    C[1] += g->g * a * T;
+    C[2] += g->b * a * T;
+    if (clist) { clist[nc] = k; araw_list[nc] = araw; T_list[nc] = T; }
+    last_wt = a * T;
+    T = Tn;
+    nc++;
+    last_depth = g->depth;
+  }
+  for (int c = 0; c < 3; c++) o->color[c] = C[c] + T * s->bg[c];
+  o->T = T;
+  o->ncontrib = nc;
+  o->ambiguous = amb;
+}
+
+static int num_threads(int req) {
+  if (req > 0) return req;
+  long c = sysconf(_SC_NPROCESSORS_ONLN);
+  return c > 0 ? (int)c : 1;
+}
+
+int orc_num_threads(int req) { return num_threads(req); }
+
+typedef struct {
+  const sorted_rec *sr;
+  int64_t m;
+  const orc_camera *cam;
+  const orc_settings *s;
+  int64_t npix;
+  const int64_t *pix;
+  int nthreads, tid;
+  /* forward outputs */
+  double *color, *Tf;
+  int64_t *ncontrib;
+  int32_t *amb;
+  /* backward */
+  const double *dl_dc;   /* [npix][3] */
+  const double *rec;     /* sorted positions -> per Gaussian via order */
+  const int64_t *order;
+  double *g2d;           /* this thread's [n][9] accumulator */
+} job;
+
+static void pixel_xy(const job *j, int64_t k, double *px, double *py) {
+  int64_t id = j->pix ? j->pix[k] : k;
+  int64_t W = j->cam->width;
+  *px = (double)(id % W) + 0.5;
+  *py = (double)(id / W) + 0.5;
+}
+
+static void *fwd_worker(void *arg) {
+  job *j = arg;
+  for (int64_t k = j->tid; k < j->npix; k += j->nthreads) {
+    double px, py;
+    pixel_xy(j, k, &px, &py);
+    pix_out o;
+    walk_pixel(j->sr, j->m, px, py, j->s, &o, NULL, NULL, NULL);
+    for (int c = 0; c < 3; c++) j->color[3 * k + c] = o.color[c];
+    j->Tf[k] = o.T;
+    j->ncontrib[k] = o.ncontrib;
+    j->amb[k] = o.ambiguous;
+  }
+  return NULL;
+}
+
+/* Render the listed pixels (row-major ids j*W+i; all pixels if pix == NULL). */
+int orc_render(int64_t n, const double *params, const orc_camera *cam, const orc_settings *s, int64_t npix,
+               const int64_t *pix, double *color, double *T_final, int64_t *ncontrib, int32_t *ambiguous,
+               int nthreads_req) {
+  sh_init();
+  double *rec = malloc(sizeof(double) * NREC * (n > 0 ? n : 1));
+  int64_t *order = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+  if (!rec || !order) return -1;
+  orc_preprocess(n, params, cam, s, rec);
+  int64_t m = global_order(n, rec, order);
+  sorted_rec *sr = make_sorted(rec, order, m);
+  int nt = num_threads(nthreads_req);
+  pthread_t *th = malloc(sizeof(pthread_t) * nt);
+  job *jobs = malloc(sizeof(job) * nt);
+  for (int t = 0; t < nt; t++) {
+    job jb = {sr, m, cam, s, npix, pix, nt, t, color, T_final, ncontrib, ambiguous, NULL, NULL, NULL, NULL};
+    jobs[t] = jb;
+    pthread_create(&th[t], NULL, fwd_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+  free(th); free(jobs); free(sr); free(order); free(rec);
+  return 0;
+}
+
+/* ----------------------------------------------------- backward: compositing */
+/* 2D gradient slots per Gaussian: du, dv, dQxx, dQxy, dQyy, dalpha_c, dr, dg, db.
+ * dQ is the full-matrix gradient: dL = dQxx dQ_xx + 2 dQxy dQ_xy + dQyy dQ_yy. */
+enum { G_U = 0, G_V, G_QXX, G_QXY, G_QYY, G_AC, G_R, G_G, G_B, NG2D };
+
+static void *bwd_worker(void *arg) {
+  job *j = arg;
+  int64_t *clist = malloc(sizeof(int64_t) * (j->m > 0 ? j->m : 1));
+  double *alist = malloc(sizeof(double) * (j->m > 0 ? j->m : 1));
+  double *tlist = malloc(sizeof(double) * (j->m > 0 ? j->m : 1));
+  const orc_settings *s = j->s;
+  for (int64_t k = j->tid; k < j->npix; k += j->nthreads) {
+    double px, py;
+    pixel_xy(j, k, &px, &py);
+    pix_out o;
+    walk_pixel(j->sr, j->m, px, py, s, &o, clist, alist, tlist);
+    const double *dc = j->dl_dc + 3 * k;
+    /* colour behind the current Gaussian, starting with the background seen through T_final */
+    double behind[3] = {o.T * s->bg[0], o.T * s->bg[1], o.T * s->bg[2]};
+    for (int64_t c = o.ncontrib - 1; c >= 0; c--) {
+      const sorted_rec *g = j->sr + clist[c];
+      double araw = alist[c];
+      double a = fmin(s->alpha_max, araw);
+      double Tk = tlist[c];
+      double col[3] = {g->r, g->g, g->b};
+      double *acc = j->g2d + NG2D * j->order[clist[c]];
+      double dl_da = 0;
+      for (int ch = 0; ch < 3; ch++) {
+        acc[G_R + ch] += dc[ch] * a * Tk;
+        dl_da += dc[ch] * (col[ch] * Tk - behind[ch] / (1.0 - a));
+        behind[ch] += col[ch] * a * Tk;
+      }
+      if (araw > s->alpha_max) continue; /* clamped: a does not depend on alpha_c or q */
+      double G = exp(-0.5 * (g->qa * (px - g->u) * (px - g->u) + 2.0 * g->qb * (px - g->u) * (py - g->v) +
+                             g->qc * (py - g->v) * (py - g->v)));
+      acc[G_AC] += dl_da * G;
+      double dl_dq = dl_da * (-0.5 * araw);
+      double dx = px - g->u, dy = py - g->v;
+      acc[G_U] += dl_dq * (-2.0) * (g->qa * dx + g->qb * dy);
+      acc[G_V] += dl_dq * (-2.0) * (g->qb * dx + g->qc * dy);
+      acc[G_QXX] += dl_dq * dx * dx;
+      acc[G_QXY] += dl_dq * dx * dy;
+      acc[G_QYY] += dl_dq * dy * dy;
+    }
+  }
+  free(clist); free(alist); free(tlist);
+  return NULL;
+}
+
+/* ------------------------------------------- backward: per-Gaussian chain rule */
+/* Vector-Jacobian product of one Gaussian's record (u, v, conic, alpha_c, rgb)
+ * with respect to its 76 raw parameters; adds into grad ([76][n]). */
+static void record_vjp(const double *params, int64_t n, int64_t i, const orc_camera *cam, const orc_settings *s,
+                       const double *g2, double *grad) {
+  double rec[NREC];
+  record_one(params, n, i, cam, s, rec);
+  if (rec[F_ALIVE] == 0.0) return;
+  g6 g;
+  load_g6(params, n, i, &g);
+  double C[3];
+  cam_center(cam, C);
+  double z = rec[F_P + 2], px = rec[F_P], py = rec[F_P + 1];
+  double fx = cam->fx, fy = cam->fy;
+  const double *R = cam->R;
+  /* conic -> 2D covariance: G_S = -Q G_Q Q */
+  double Q[2][2] = {{rec[F_CONIC], rec[F_CONIC + 1]}, {rec[F_CONIC + 1], rec[F_CONIC + 2]}};
+  double GQ[2][2] = {{g2[G_QXX], g2[G_QXY]}, {g2[G_QXY], g2[G_QYY]}};
+  double QG[2][2], GS[2][2];
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 2; c++) QG[r][c] = Q[r][0] * GQ[0][c] + Q[r][1] * GQ[1][c];
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 2; c++) GS[r][c] = -(QG[r][0] * Q[0][c] + QG[r][1] * Q[1][c]);
+  /* Sigma2D = T Sigma_c T^T + dil I, T = J R */
+  double limx = s->jac_guard * (0.5 * (double)cam->width) / fx;
+  double limy = s->jac_guard * (0.5 * (double)cam->height) / fy;
+  double rx = px / z, ry = py / z;
+  int clx = (rx < -limx) || (rx > limx);
+  int cly = (ry < -limy) || (ry > limy);
+  double xt = fmin(limx, fmax(-limx, rx));
+  double yt = fmin(limy, fmax(-limy, ry));
+  double J[2][3] = {{fx / z, 0, -fx * xt / z}, {0, fy / z, -fy * yt / z}};
+  double T[2][3];
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 3; c++) T[r][c] = J[r][0] * R[c] + J[r][1] * R[3 + c] + J[r][2] * R[6 + c];
+  double Gc[3][3]; /* T^T G_S T */
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      double acc = 0;
+      for (int r = 0; r < 2; r++)
+        for (int c = 0; c < 2; c++) acc += T[r][a] * GS[r][c] * T[c][b];
+      Gc[a][b] = acc;
+    }
+  double dT[2][3]; /* 2 G_S T Sigma_c */
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 3; c++) {
+      double acc = 0;
+      for (int k = 0; k < 2; k++)
+        for (int m = 0; m < 3; m++) acc += GS[r][k] * T[k][m] * g.Sc[m][c];
+      dT[r][c] = 2.0 * acc;
+    }
+  double dJ[2][3]; /* dT R^T */
+  for (int r = 0; r < 2; r++)
+    for (int c = 0; c < 3; c++) dJ[r][c] = dT[r][0] * R[3 * c] + dT[r][1] * R[3 * c + 1] + dT[r][2] * R[3 * c + 2];
+  double dp[3] = {0, 0, 0};
+  dp[2] += dJ[0][0] * (-fx / (z * z)) + dJ[1][1] * (-fy / (z * z));
+  if (!clx) { dp[0] += dJ[0][2] * (-fx / (z * z)); dp[2] += dJ[0][2] * (2.0 * fx * px / (z * z * z)); }
+  else { dp[2] += dJ[0][2] * (fx * xt / (z * z)); }
+  if (!cly) { dp[1] += dJ[1][2] * (-fy / (z * z)); dp[2] += dJ[1][2] * (2.0 * fy * py / (z * z * z)); }
+  else { dp[2] += dJ[1][2] * (fy * yt / (z * z)); }
+  /* u, v */
+  dp[0] += g2[G_U] * fx / z;
+  dp[1] += g2[G_V] * fy / z;
+  dp[2] += -g2[G_U] * fx * px / (z * z) - g2[G_V] * fy * py / (z * z);
+  /* p = R mu_c + t */
+  double gmu[3];
+  for (int k = 0; k < 3; k++) gmu[k] = R[k] * dp[0] + R[3 + k] * dp[1] + R[6 + k] * dp[2];
+  /* SH colour */
+  double sv[3], ns = 0;
+  for (int k = 0; k < 3; k++) { sv[k] = rec[F_MUC + k] - C[k]; ns += sv[k] * sv[k]; }
+  ns = sqrt(ns);
+  double sh[3] = {sv[0] / ns, sv[1] / ns, sv[2] / ns};
+  double Y[16], dY[16][3];
+  sh_eval(sh, Y, dY);
+  double gs[3] = {0, 0, 0};
+  for (int c = 0; c < 3; c++) {
+    double rgb = rec[F_RGB + c];
+    double dsc = g2[G_R + c] * rgb * (1.0 - rgb);
+    for (int k = 0; k < 16; k++) {
+      grad[(int64_t)(ROW_SH + 3 * k + c) * n + i] += dsc * Y[k];
+      double beta = P(params, n, ROW_SH + 3 * k + c, i);
+      for (int m = 0; m < 3; m++) gs[m] += dsc * beta * dY[k][m];
+    }
+  }
+  double sdot = sh[0] * gs[0] + sh[1] * gs[1] + sh[2] * gs[2];
+  for (int k = 0; k < 3; k++) gmu[k] += (gs[k] - sh[k] * sdot) / ns;
+  /* slice */
+  double x[3], Ax[3];
+  for (int k = 0; k < 3; k++) x[k] = rec[F_DIR + k] - g.mu_d[k];
+  for (int r = 0; r < 3; r++) Ax[r] = g.A[r][0] * x[0] + g.A[r][1] * x[1] + g.A[r][2] * x[2];
+  double ac = rec[F_ALPHAC], gac = g2[G_AC], lam = s->lambda_opa;
+  double dD = -lam * ac * gac;
+  double gx[3];
+  for (int k = 0; k < 3; k++)
+    gx[k] = g.K[0][k] * gmu[0] + g.K[1][k] * gmu[1] + g.K[2][k] * gmu[2] + 2.0 * dD * Ax[k];
+  double GSp[3][3], GSpd[3][3], GA[3][3];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) GSp[a][b] = Gc[a][b];
+  double GcSpd[3][3], GcSpdA[3][3];
+  mm3(Gc, g.Spd, GcSpd);
+  mm3(GcSpd, g.A, GcSpdA);
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) GSpd[a][b] = gmu[a] * Ax[b] - 2.0 * GcSpdA[a][b];
+  double SpdTgmu[3];
+  for (int a = 0; a < 3; a++) SpdTgmu[a] = g.Spd[0][a] * gmu[0] + g.Spd[1][a] * gmu[1] + g.Spd[2][a] * gmu[2];
+  double SpdTGcSpd[3][3];
+  mtm3(g.Spd, GcSpd, SpdTGcSpd);
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++)
+      GA[a][b] = 0.5 * (SpdTgmu[a] * x[b] + SpdTgmu[b] * x[a]) - SpdTGcSpd[a][b] + dD * x[a] * x[b];
+  double AGA[3][3], tmp[3][3], GSd[3][3];
+  mm3(g.A, GA, tmp);
+  mm3(tmp, g.A, AGA);
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) GSd[a][b] = -AGA[a][b];
+  /* mu_d, mu_p (through d = (mu_p - C)/|mu_p - C|), alpha */
+  double dv[3], nd = 0;
+  for (int k = 0; k < 3; k++) { dv[k] = g.mu_p[k] - C[k]; nd += dv[k] * dv[k]; }
+  nd = sqrt(nd);
+  double dd[3] = {dv[0] / nd, dv[1] / nd, dv[2] / nd};
+  double ddot = dd[0] * gx[0] + dd[1] * gx[1] + dd[2] * gx[2];
+  for (int k = 0; k < 3; k++) {
+    grad[(int64_t)(ROW_MU_D + k) * n + i] += -gx[k];
+    grad[(int64_t)(ROW_MU_P + k) * n + i] += gmu[k] + (gx[k] - dd[k] * ddot) / nd;
+  }
+  double galpha = gac * rec[F_F];
+  grad[(int64_t)ROW_OPA * n + i] += galpha * g.alpha * (1.0 - g.alpha);
+  /* Sigma = L L^T: dL/dL = lower(2 G6 L), G6 = [[G_p, H/2], [H^T/2, G_d]] */
+  double G6[6][6];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      G6[a][b] = 0.5 * (GSp[a][b] + GSp[b][a]);
+      G6[3 + a][3 + b] = 0.5 * (GSd[a][b] + GSd[b][a]);
+      G6[a][3 + b] = 0.5 * GSpd[a][b];
+      G6[3 + b][a] = 0.5 * GSpd[a][b];
+    }
+  for (int r = 0; r < 6; r++)
+    for (int c = 0; c <= r; c++) {
+      double acc = 0;
+      for (int k = 0; k < 6; k++) acc += G6[r][k] * g.L[k][c];
+      double gl = 2.0 * acc;
+      double raw = P(params, n, ROW_L + r * (r + 1) / 2 + c, i);
+      double graw;
+      if (r == c) graw = gl * g.L[r][c];
+      else { double sg = sigm(raw); graw = gl * 2.0 * sg * (1.0 - sg); }
+      grad[(int64_t)(ROW_L + r * (r + 1) / 2 + c) * n + i] += graw;
+    }
+}
+
+/* Per-Gaussian VJP entry point: g2d is [n][9] (du, dv, dQxx, dQxy, dQyy, dalpha_c, dr, dg, db). */
+void orc_record_vjp(int64_t n, const double *params, const orc_camera *cam, const orc_settings *s,
+                    const double *g2d, double *grad) {
+  sh_init();
+  memset(grad, 0, sizeof(double) * NROWS * n);
+  for (int64_t i = 0; i < n; i++) record_vjp(params, n, i, cam, s, g2d + NG2D * i, grad);
+}
+
+/* Full backward for the listed pixels with upstream dL/dC ([npix][3]):
+ * writes grad ([76][n], overwritten) and, if g2d_out != NULL, the per-Gaussian
+ * 2D gradients ([n][9]). */
+int orc_backward(int64_t n, const double *params, const orc_camera *cam, const orc_settings *s, int64_t npix,
+                 const int64_t *pix, const double *dl_dc, double *grad, double *g2d_out, int nthreads_req) {
+  sh_init();
+  double *rec = malloc(sizeof(double) * NREC * (n > 0 ? n : 1));
+  int64_t *order = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+  if (!rec || !order) return -1;
+  orc_preprocess(n, params, cam, s, rec);
+  int64_t m = global_order(n, rec, order);
+  sorted_rec *sr = make_sorted(rec, order, m);
+  int nt = num_threads(nthreads_req);
+  pthread_t *th = malloc(sizeof(pthread_t) * nt);
+  job *jobs = malloc(sizeof(job) * nt);
+  double *acc = calloc((size_t)nt * NG2D * (n > 0 ? n : 1), sizeof(double));
+  if (!acc) return -1;
+  for (int t = 0; t < nt; t++) {
+    job jb = {sr, m, cam, s, npix, pix, nt, t, NULL, NULL, NULL, NULL, dl_dc, rec, order, acc + (size_t)t * NG2D * n};
+    jobs[t] = jb;
+    pthread_create(&th[t], NULL, bwd_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+  double *g2 = calloc((size_t)NG2D * (n > 0 ? n : 1), sizeof(double));
+  for (int t = 0; t < nt; t++)
+    for (int64_t k = 0; k < NG2D * n; k++) g2[k] += acc[(size_t)t * NG2D * n + k];
+  memset(grad, 0, sizeof(double) * NROWS * n);
+  for (int64_t i = 0; i < n; i++) record_vjp(params, n, i, cam, s, g2 + NG2D * i, grad);
+  if (g2d_out) memcpy(g2d_out, g2, sizeof(double) * NG2D * n);
+  free(g2); free(acc); free(th); free(jobs); free(sr); free(order); free(rec);
+  return 0;
+}
