@@ -1,0 +1,224 @@
+"""Benchmark: one full training step of the 6D Gaussian renderer on one MI355X.
+
+Workload: 300k view-conditioned 6D Gaussians on a noisy unit sphere with strong
+view dependence (spatial-direction Cholesky entries N(0, 0.3), direction means
+along the inward normals), one 800x800 camera.  A step is forward render, L1
+loss against a target render of a perturbed copy, backward to the 76 raw
+parameters and an Adam update -- every stage in lib6dgs.so on one stream.
+
+Prints one JSON line (see the README of the benchmark contract in the design
+notes): value = whole-step throughput in Mpixels/s, plus the roofline of the
+dominant kernel and the FP64 oracle timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpixels/sec & train steps/sec at 300k 6D Gaussians 800x800; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+# fp32 without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+# Algorithmic flops of the compositing kernels per contributing (pixel,
+# Gaussian) pair -- the pairs whose alpha reaches 1/255 before the pixel
+# saturates, the work any implementation must do: evaluating the Gaussian
+# (offset, quadratic form, exp2, opacity, clamp: 12) plus blending it (10) in
+# the forward, or plus the reverse step and its nine screen-space gradients
+# (40) in the backward.
+FWD_FLOPS_PER_CONTRIB = 12 + 10
+BWD_FLOPS_PER_CONTRIB = 12 + 40
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=8192)
+    return ap.parse_args()
+
+
+def source_digest(names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2410_04974_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this renderer has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2410_04974_amd import Renderer, Trainer, _lib
+
+    dev = torch.device("cuda:0")
+    w = synth.workload("c2")
+    cam = w.cameras[0]
+    params_np = synth.make_scene(w.scene)
+    n = params_np.shape[1]
+    px = cam.width * cam.height
+
+    tgt_r = Renderer()
+    target = tgt_r.forward(torch.from_numpy(synth.perturbed(params_np)).to(dev), [cam])
+    torch.cuda.synchronize()
+    del tgt_r
+
+    params = torch.from_numpy(params_np).to(dev)
+    r = Renderer()
+    tr = Trainer(params, r)
+    # first step in grow-on-demand mode, then a fixed pair capacity: no host waits per step
+    tr.step([cam], target)
+    torch.cuda.synchronize()
+    pairs = r.ctx.sizes()["pairs"]
+    r.configure(pair_capacity=int(pairs * 1.5) + 4096)
+    for _ in range(max(args.warmup - 1, 0)):
+        tr.step([cam], target)
+    torch.cuda.synchronize()
+
+    # which kernel dominates a step
+    r.ctx.set_timing(0x1F)
+    for _ in range(3):
+        tr.step([cam], target)
+    kt = {k: r.ctx.kernel_time(k)[0] / 3 for k in _lib.KERNEL_NAMES}
+    dom = max(kt, key=kt.get)
+
+    # timed region: only the dominant kernel is bracketed by events
+    r.ctx.set_timing(1 << dom)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        tr.step([cam], target)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r.ctx.check()  # raises if the fixed pair capacity overflowed
+    ms_step = e0.elapsed_time(e1) / args.steps
+    dom_ms, dom_launches = r.ctx.kernel_time(dom)
+    dom_avg_ms = dom_ms / max(dom_launches, 1)
+
+    # sizes of this workload for the algorithmic byte / flop counts
+    sz = r.ctx.sizes()
+    nb, P = sz["binned"], sz["pairs"]
+    tiles = sz["tiles"]
+    roof = roofline(r, dom, dom_avg_ms, n, nb, P, px, tiles, params, cam, target)
+
+    out = {
+        "metric": METRIC,
+        "value": round(px / (ms_step * 1e-3) / 1e6, 3),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator, random-init 6D Gaussians)",
+        "config": {"workload": "c2: 300k 6D Gaussians, noisy unit sphere, strong view dependence, "
+                               "800x800, L1 + Adam training step",
+                   "gaussians": n, "width": cam.width, "height": cam.height, "views_per_step": 1,
+                   "binned": nb, "pairs": P, "tiles": tiles, "tile": [r.ctx.settings.tile_w, r.ctx.settings.tile_h],
+                   "batch": r.ctx.settings.batch},
+        "train_steps_per_s": round(1e3 / ms_step, 2),
+        "wall_s_timed": round(wall, 3),
+        "kernel_ms": {_lib.KERNEL_NAMES[k]: round(v, 4) for k, v in kt.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(params_np, cam, args.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
+    import numpy as np
+    import torch
+    from paper_2410_04974_amd import _lib
+
+    name = _lib.KERNEL_NAMES[dom]
+    if dom in (_lib.K_BLEND_FWD, _lib.K_BLEND_BWD):
+        # count the contributing (pixel, Gaussian) pairs in one extra forward
+        cnt_r = Renderer_with_counts(r)
+        cnt_r.forward(params, [cam])
+        counts = float(cnt_r.ctx.export(_lib.EXPORT_COUNTS).astype(np.float64).sum())
+        per = FWD_FLOPS_PER_CONTRIB if dom == _lib.K_BLEND_FWD else BWD_FLOPS_PER_CONTRIB
+        achieved = per * counts / (avg_ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic(name),
+                "avg_ms": round(avg_ms, 4), "contributions_per_launch": counts, "flops_per_contribution": per}
+    if dom == _lib.K_PREPROCESS:
+        bytes_ = 304 * n + 4 * n + 48 * nb
+    elif dom == _lib.K_PREPROCESS_BWD:
+        bytes_ = 608 * n + 4 * n + 36 * nb
+    else:  # integer stage: depth keys and pair lists (sort passes read and write 8 B per item)
+        bytes_ = 4 * n + 8 * nb * 2 * 4 + 8 * P * 2 * 2 + 8 * tiles
+    achieved = bytes_ / (avg_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic(name), "avg_ms": round(avg_ms, 4)}
+
+
+def Renderer_with_counts(r):
+    from paper_2410_04974_amd import Renderer
+    s = r.ctx.settings
+    return Renderer(lambda_opa=s.lambda_opa, z_near=s.z_near, bg=tuple(s.bg), tile=(s.tile_w, s.tile_h),
+                    batch=s.batch, flags=1)
+
+
+def traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else null."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        e = t.get(kernel)
+        if not e or e.get("source_digest") != source_digest(e.get("sources", [])):
+            return None
+        return e.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(params_np, cam, npix):
+    """The FP64 oracle (forward + analytic backward) on a seeded pixel sample."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    pix = synth.pixel_subset(cam.width, cam.height, npix, seed=5)
+    dl = np.random.default_rng(6).normal(size=(len(pix), 3))
+    t0 = time.perf_counter()
+    oracle.render(params_np, cam, pixels=pix)
+    oracle.backward(params_np, cam, dl, pixels=pix)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(pix) / dt / 1e6, 6), "unit": "Mpixels/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"{len(pix)} seeded pixels of the same 800x800 view, forward + backward, "
+                      "brute force over all 300k Gaussians per pixel"}
+
+
+if __name__ == "__main__":
+    main()

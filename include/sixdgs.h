@@ -1,0 +1,201 @@
+/*
+ * sixdgs.h -- C ABI of the MI355X (gfx950) renderer for view-conditioned 6D
+ * Gaussians: forward render, its backward, an L1 loss and an Adam step.
+ *
+ * The method: each 6D Gaussian (position mu_p, direction mu_d, 6x6 covariance
+ * Sigma = L L^T, opacity, SH colour; Sec. 3.1 and Sec. 4.2) is sliced for the
+ * camera's view direction into a conditional 3D Gaussian (conditional mean,
+ * Schur-complement covariance, opacity scaled by
+ * exp(-lambda (d-mu_d)^T Sigma_d^-1 (d-mu_d)); Sec. 3.2 eq:mu, eq:sigma,
+ * eq:alpha, Sec. 4.2 eq:pdfv2, Algorithm 1) which the 3D Gaussian splatting
+ * rasteriser then draws (Sec. 4.4): EWA projection, binning into screen tiles
+ * ordered by (tile, depth), and front-to-back alpha compositing.
+ *
+ * Conventions shared by every entry point
+ *   - Parameters are one device buffer of float32 in structure-of-arrays
+ *     layout [76][n]: row r of Gaussian i at params[r*n + i].  Rows: 0-2 mu_p,
+ *     3-5 mu_d, 6-26 raw lower-triangular Cholesky entries of the 6x6 factor
+ *     (entry (i,j), j<=i, at row 6 + i(i+1)/2 + j; the diagonal goes through
+ *     exp, the rest through 2*sigmoid(r)-1), 27-74 SH coefficients (basis k,
+ *     channel c at row 27 + 3k + c; colour = sigmoid of the expansion), 75 the
+ *     opacity logit (opacity = sigmoid).
+ *   - Cameras are host structs: world -> camera p = R x + t (R row-major),
+ *     OpenCV axes (x right, y down, z forward), pinhole intrinsics; pixel
+ *     (i, j) has its centre at (i + 0.5, j + 0.5).
+ *   - Images are float32 [3][H][W] in device memory, one buffer per camera,
+ *     owned by the caller.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call that
+ *     takes a stream only enqueues work on it and returns; it does not wait
+ *     unless stated.
+ *   - Errors: every call returns a status; on failure nothing has been
+ *     enqueued (argument checks happen before any launch) unless the status is
+ *     SIXDGS_ERR_HIP.  sixdgs_last_error() gives a message.  No C++ exception
+ *     crosses this boundary.
+ *   - A context is used by one host thread at a time; calls on one context
+ *     must be issued on streams ordered with each other.
+ */
+#ifndef SIXDGS_H
+#define SIXDGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sixdgs_status;
+#define SIXDGS_OK 0
+#define SIXDGS_ERR_INVALID_ARG 1 /* bad pointer, size, camera or setting */
+#define SIXDGS_ERR_OOM 2         /* device allocation failed */
+#define SIXDGS_ERR_HIP 3         /* a HIP runtime call failed */
+#define SIXDGS_ERR_CAPACITY 4    /* fixed pair capacity was exceeded (output invalid) */
+#define SIXDGS_ERR_STATE 5       /* backward without a matching forward, etc. */
+
+#define SIXDGS_NROWS 76
+#define SIXDGS_ROW_MU_P 0
+#define SIXDGS_ROW_MU_D 3
+#define SIXDGS_ROW_L 6
+#define SIXDGS_ROW_SH 27
+#define SIXDGS_ROW_OPACITY 75
+#define SIXDGS_MAX_VIEWS 16 /* cameras per forward call */
+
+typedef struct sixdgs_ctx sixdgs_ctx;
+
+typedef struct {
+  float R[9];   /* world -> camera rotation, row-major */
+  float t[3];   /* world -> camera translation */
+  float fx, fy; /* focal lengths in pixels */
+  float cx, cy; /* principal point in pixels */
+  int32_t width, height;
+} sixdgs_camera;
+
+typedef struct {
+  float lambda_opa;    /* directional opacity strength (Sec. 4.2; paper uses 0.35), in [0, 1] */
+  float z_near;        /* camera-space depth below which a Gaussian is culled (0.2) */
+  float bg[3];         /* background colour */
+  int32_t tile_w;      /* screen tile width in pixels: 8, 16 or 32 */
+  int32_t tile_h;      /* screen tile height: tile_w * tile_h must be 256 */
+  int32_t batch;       /* Gaussians staged in LDS per tile batch: 32, 64, 128 or 256 */
+  int64_t pair_capacity; /* 0: grow the (tile, Gaussian) pair buffers on demand
+                            (sixdgs_forward then waits once on the stream to
+                            read the pair count); > 0: fixed capacity, no host
+                            waits (capturable), overflow reported as
+                            SIXDGS_ERR_CAPACITY by sixdgs_check(). */
+  int32_t flags;       /* SIXDGS_FLAG_* */
+} sixdgs_settings;
+
+#define SIXDGS_FLAG_COUNTS 1 /* forward also stores per-pixel contributor counts (debug export) */
+
+/* Fills `s` with the defaults: lambda 0.35, z_near 0.2, bg 0, 16x16 tiles,
+ * batch 256, pair_capacity 0, flags 0. */
+void sixdgs_default_settings(sixdgs_settings* s);
+
+/* Creates a context on the current HIP device.  It owns all scratch memory
+ * and the state one forward leaves for the matching backward.  `s` may be
+ * NULL (defaults).  Returns INVALID_ARG for unsupported settings. */
+sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s);
+
+/* Frees the context and its device memory (waits for the device first). */
+void sixdgs_destroy(sixdgs_ctx* ctx);
+
+/* Replaces the settings; takes effect at the next forward. */
+sixdgs_status sixdgs_set_settings(sixdgs_ctx* ctx, const sixdgs_settings* s);
+
+/* Message for the last failed call on this context (never NULL). */
+const char* sixdgs_last_error(const sixdgs_ctx* ctx);
+
+/* Forward render (Sec. 3.2 / Algorithm 1 slice, then the 3DGS rasteriser of
+ * Sec. 4.4) of n Gaussians into ncam (1..SIXDGS_MAX_VIEWS) cameras.
+ *   params  device [76][n], read only, must stay unchanged until the matching
+ *           backward has run.
+ *   cams    host array of ncam cameras.
+ *   images  host array of ncam device pointers, each [3][H][W], overwritten.
+ * Keeps, inside ctx, the per-view projected records, the sorted (tile,
+ * Gaussian) lists and the per-pixel final transmittance and last-contributor
+ * index that the backward consumes; they stay valid until the next forward or
+ * sixdgs_bin on this context. */
+sixdgs_status sixdgs_forward(sixdgs_ctx* ctx, const float* params, int64_t n, const sixdgs_camera* cams,
+                             int32_t ncam, float* const* images, void* stream);
+
+/* Backward of the last forward on this context: given dL/dI for each of its
+ * cameras (host array of ncam device pointers, each [3][H][W]), writes dL/d
+ * params into `grad` (device [76][n], overwritten).  `params` and `n` must be
+ * those of the forward.  If `densify` is not NULL (device [2][n]) it adds, per
+ * Gaussian, the norm of its screen-space mean gradient in normalised device
+ * units (row 0) and the number of views it was visible in (row 1) -- the
+ * statistics the adaptive density control of Sec. 4.3 consumes. */
+sixdgs_status sixdgs_backward(sixdgs_ctx* ctx, const float* params, int64_t n, const float* const* dl_dimages,
+                              float* grad, float* densify, void* stream);
+
+/* L1 photometric loss over nimg (1..SIXDGS_MAX_VIEWS) image pairs:
+ * loss = mean |I - I*| over every element of every image (written to the
+ * device float `loss`), and dL/dI = sign(I - I*) / total_count written to
+ * dl_dimages[k] (may alias nothing else).  numel[k] is the element count of
+ * image k (host array). */
+sixdgs_status sixdgs_l1_loss(sixdgs_ctx* ctx, int32_t nimg, const float* const* images, const float* const* targets,
+                             const int64_t* numel, float* const* dl_dimages, float* loss, void* stream);
+
+/* One Adam step (Kingma and Ba, bias-corrected) on params [76][n] in place,
+ * with moments m, v (device [76][n], updated in place; zero before step 1).
+ * lr[6] (host) holds the learning rate of the row groups mu_p, mu_d,
+ * Cholesky, SH degree 0, SH degree 1-3, opacity.  step counts from 1. */
+sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
+                          float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* The integer stage alone, on caller-given projected records: bins entries
+ * e = view*n + i (arrays of length n*ncam, device) with extents (u +- ex,
+ * v +- ey) into the cameras' tile grids, keyed by (tile, float32 depth bits,
+ * e), sorts and builds per-tile ranges, exactly as sixdgs_forward does after
+ * its projection.  alive[e] != 0 marks entries that take part.  Results are
+ * read back with sixdgs_export. */
+sixdgs_status sixdgs_bin(sixdgs_ctx* ctx, int64_t n, const sixdgs_camera* cams, int32_t ncam, const float* u,
+                         const float* v, const float* ex, const float* ey, const float* depth, const int32_t* alive,
+                         void* stream);
+
+/* What sixdgs_export copies out (synchronous: waits for the context's last
+ * stream).  Element types and counts:
+ *   RECORDS      float  [E][12]: u, v, Qxx, Qxy, Qyy, alpha_cond, ex, ey, r, g, b, depth
+ *                (E = n*ncam; rows of entries that are not binned are undefined)
+ *   TILES        int32  [E]: tiles touched per entry (0 = culled)
+ *   KEYS         uint64 [P]: sorted (global tile << 32 | depth bits)
+ *   VALUES       int32  [P]: entry ids in key order
+ *   RANGES       int32  [T][2]: per global tile [start, end) into KEYS
+ *   T_FINAL      float  [sum H*W]: final transmittance per pixel, views in order
+ *   LAST         int32  [sum H*W]: 1 + position (within its tile's range) of the
+ *                last contributor, 0 if none
+ *   COUNTS       int32  [sum H*W]: contributors per pixel (SIXDGS_FLAG_COUNTS)
+ *   SIZES        int64  [5]: E, P, T, number of binned entries, pixels */
+#define SIXDGS_EXPORT_RECORDS 0
+#define SIXDGS_EXPORT_TILES 1
+#define SIXDGS_EXPORT_KEYS 2
+#define SIXDGS_EXPORT_VALUES 3
+#define SIXDGS_EXPORT_RANGES 4
+#define SIXDGS_EXPORT_T_FINAL 5
+#define SIXDGS_EXPORT_LAST 6
+#define SIXDGS_EXPORT_COUNTS 7
+#define SIXDGS_EXPORT_SIZES 8
+/* Copies item `what` into host memory `dst` of `cap_bytes` bytes; *written
+ * receives the byte count.  Returns INVALID_ARG if it does not fit. */
+sixdgs_status sixdgs_export(sixdgs_ctx* ctx, int32_t what, void* dst, int64_t cap_bytes, int64_t* written);
+
+/* Waits for the context's last stream and reports a capacity overflow of the
+ * fixed-capacity mode (SIXDGS_ERR_CAPACITY, then the flag is cleared). */
+sixdgs_status sixdgs_check(sixdgs_ctx* ctx);
+
+/* Kernel timing with HIP events recorded on the launch stream around the
+ * chosen kernels (ids SIXDGS_K_*); off by default.  sixdgs_kernel_time waits
+ * for the stream and returns the summed milliseconds and launch count since
+ * the last reset. */
+#define SIXDGS_K_PREPROCESS 0
+#define SIXDGS_K_BLEND_FWD 1
+#define SIXDGS_K_BLEND_BWD 2
+#define SIXDGS_K_PREPROCESS_BWD 3
+#define SIXDGS_K_SORT 4 /* whole integer stage: compaction, both sorts, ranges */
+#define SIXDGS_K_COUNT 5
+sixdgs_status sixdgs_set_timing(sixdgs_ctx* ctx, int32_t kernel_mask);
+sixdgs_status sixdgs_kernel_time(sixdgs_ctx* ctx, int32_t kernel, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIXDGS_H */

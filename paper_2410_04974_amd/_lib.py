@@ -1,0 +1,266 @@
+"""ctypes binding of lib6dgs.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module turns torch tensors into
+device pointers and the current torch stream into a hipStream_t.  Loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib6dgs.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_STATE = range(6)
+MAX_VIEWS = 16
+FLAG_COUNTS = 1
+EXPORT_RECORDS, EXPORT_TILES, EXPORT_KEYS, EXPORT_VALUES, EXPORT_RANGES, EXPORT_T_FINAL, EXPORT_LAST, \
+    EXPORT_COUNTS, EXPORT_SIZES = range(9)
+K_PREPROCESS, K_BLEND_FWD, K_BLEND_BWD, K_PREPROCESS_BWD, K_SORT = range(5)
+KERNEL_NAMES = {K_PREPROCESS: "preprocess", K_BLEND_FWD: "blend_fwd", K_BLEND_BWD: "blend_bwd",
+                K_PREPROCESS_BWD: "preprocess_bwd", K_SORT: "binning"}
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("lambda_opa", ctypes.c_float), ("z_near", ctypes.c_float), ("bg", ctypes.c_float * 3),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("pair_capacity", ctypes.c_int64), ("flags", ctypes.c_int32)]
+
+
+class SixDGSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lib6dgs status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build, "
+                               "or paper_2410_04974_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.sixdgs_default_settings.argtypes = [ctypes.POINTER(Settings)]
+        L.sixdgs_default_settings.restype = None
+        L.sixdgs_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Settings)]
+        L.sixdgs_destroy.argtypes = [P]
+        L.sixdgs_destroy.restype = None
+        L.sixdgs_set_settings.argtypes = [P, ctypes.POINTER(Settings)]
+        L.sixdgs_last_error.argtypes = [P]
+        L.sixdgs_last_error.restype = ctypes.c_char_p
+        L.sixdgs_forward.argtypes = [P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
+        L.sixdgs_backward.argtypes = [P, P, I64, PP, P, P, P]
+        L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
+        L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
+        L.sixdgs_bin.argtypes = [P, I64, ctypes.POINTER(Camera), I32, P, P, P, P, P, P, P]
+        L.sixdgs_export.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
+        L.sixdgs_check.argtypes = [P]
+        L.sixdgs_set_timing.argtypes = [P, I32]
+        L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+        for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward", "sixdgs_l1_loss",
+                     "sixdgs_adam", "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing",
+                     "sixdgs_kernel_time"):
+            getattr(L, name).restype = I32
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
+            "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_l1_loss", "sixdgs_adam",
+            "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
+
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    lib().sixdgs_default_settings(ctypes.byref(s))
+    for k, v in kw.items():
+        if k == "bg":
+            s.bg[:] = [float(x) for x in v]
+        else:
+            setattr(s, k, v)
+    return s
+
+
+def to_camera(cam) -> Camera:
+    """Anything with R (3x3), t (3), fx, fy, cx, cy, width, height."""
+    c = Camera()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float32).reshape(9)]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float32).reshape(3)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def _ptrs(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for k, t in enumerate(tensors):
+        arr[k] = ctypes.c_void_p(t.data_ptr())
+    return arr
+
+
+def _check_f32_cuda(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+class Context:
+    """One library context: workspace plus the state one forward leaves for its backward."""
+
+    def __init__(self, settings: Settings | None = None, **kw):
+        s = settings if settings is not None else default_settings(**kw)
+        h = ctypes.c_void_p()
+        rc = lib().sixdgs_create(ctypes.byref(h), ctypes.byref(s))
+        if rc != OK:
+            raise SixDGSError(rc, "create failed (unsupported settings?)")
+        self._h = h
+        self.settings = s
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sixdgs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc):
+        if rc != OK:
+            raise SixDGSError(rc, lib().sixdgs_last_error(self._h).decode())
+
+    def set_settings(self, **kw):
+        for k, v in kw.items():
+            if k == "bg":
+                self.settings.bg[:] = [float(x) for x in v]
+            else:
+                setattr(self.settings, k, v)
+        self._rc(lib().sixdgs_set_settings(self._h, ctypes.byref(self.settings)))
+
+    # -- rendering -------------------------------------------------------------
+    def forward(self, params, cams, images, stream=None):
+        n = params.shape[1]
+        _check_f32_cuda(params, "params")
+        if params.dim() != 2 or params.shape[0] != 76:
+            raise ValueError("params must have shape [76, N]")
+        if len(images) != len(cams):
+            raise ValueError("one image per camera")
+        for im, c in zip(images, cams):
+            _check_f32_cuda(im, "image")
+            if im.numel() != 3 * int(c.width) * int(c.height):
+                raise ValueError("each image must hold 3*H*W floats")
+        ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
+        self._rc(lib().sixdgs_forward(self._h, ctypes.c_void_p(params.data_ptr()), n, ccams, len(cams),
+                                      _ptrs(images), ctypes.c_void_p(_stream(stream))))
+
+    def backward(self, params, dl_dimages, grad, densify=None, stream=None):
+        n = params.shape[1]
+        for t in dl_dimages:
+            _check_f32_cuda(t, "dl_dimage")
+        _check_f32_cuda(grad, "grad")
+        if grad.shape != params.shape:
+            raise ValueError("grad must have the shape of params")
+        if densify is not None:
+            _check_f32_cuda(densify, "densify")
+            if densify.numel() != 2 * n:
+                raise ValueError("densify must hold [2, N] floats")
+        dens = ctypes.c_void_p(densify.data_ptr()) if densify is not None else None
+        self._rc(lib().sixdgs_backward(self._h, ctypes.c_void_p(params.data_ptr()), n, _ptrs(dl_dimages),
+                                       ctypes.c_void_p(grad.data_ptr()), dens, ctypes.c_void_p(_stream(stream))))
+
+    def l1_loss(self, images, targets, dl_dimages, loss, stream=None):
+        for a, b, g in zip(images, targets, dl_dimages):
+            for t in (a, b, g):
+                _check_f32_cuda(t, "image")
+            if not (a.numel() == b.numel() == g.numel()):
+                raise ValueError("image, target and gradient sizes differ")
+        _check_f32_cuda(loss, "loss")
+        numel = (ctypes.c_int64 * len(images))(*[t.numel() for t in images])
+        self._rc(lib().sixdgs_l1_loss(self._h, len(images), _ptrs(images), _ptrs(targets), numel,
+                                      _ptrs(dl_dimages), ctypes.c_void_p(loss.data_ptr()),
+                                      ctypes.c_void_p(_stream(stream))))
+
+    def bin(self, n, cams, u, v, ex, ey, depth, alive, stream=None):
+        import torch
+        for t in (u, v, ex, ey, depth):
+            _check_f32_cuda(t, "record array")
+            if t.numel() != n * len(cams):
+                raise ValueError("record arrays must hold n * ncam entries")
+        if not (alive.is_cuda and alive.dtype == torch.int32 and alive.numel() == n * len(cams)):
+            raise ValueError("alive must be an int32 CUDA tensor of n * ncam entries")
+        ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
+        self._rc(lib().sixdgs_bin(self._h, n, ccams, len(cams), *[ctypes.c_void_p(t.data_ptr()) for t in
+                                                                   (u, v, ex, ey, depth, alive)],
+                                  ctypes.c_void_p(_stream(stream))))
+
+    def check(self):
+        self._rc(lib().sixdgs_check(self._h))
+
+    # -- read-back (synchronous) ----------------------------------------------------
+    def sizes(self):
+        out = np.zeros(5, np.int64)
+        w = ctypes.c_int64()
+        self._rc(lib().sixdgs_export(self._h, EXPORT_SIZES, out.ctypes.data_as(ctypes.c_void_p), 40, ctypes.byref(w)))
+        return {"entries": int(out[0]), "pairs": int(out[1]), "tiles": int(out[2]), "binned": int(out[3]),
+                "pixels": int(out[4])}
+
+    def export(self, what):
+        sz = self.sizes()
+        E, P, T, X = sz["entries"], sz["pairs"], sz["tiles"], sz["pixels"]
+        spec = {EXPORT_RECORDS: (np.float32, (E, 12)), EXPORT_TILES: (np.int32, (E,)),
+                EXPORT_KEYS: (np.uint64, (P,)), EXPORT_VALUES: (np.int32, (P,)),
+                EXPORT_RANGES: (np.int32, (T, 2)), EXPORT_T_FINAL: (np.float32, (X,)),
+                EXPORT_LAST: (np.int32, (X,)), EXPORT_COUNTS: (np.int32, (X,))}
+        dt, shape = spec[what]
+        out = np.zeros(shape, dt)
+        w = ctypes.c_int64()
+        self._rc(lib().sixdgs_export(self._h, what, out.ctypes.data_as(ctypes.c_void_p), out.nbytes,
+                                     ctypes.byref(w)))
+        return out
+
+    # -- timing ----------------------------------------------------------------------
+    def set_timing(self, mask):
+        self._rc(lib().sixdgs_set_timing(self._h, int(mask)))
+
+    def kernel_time(self, kernel):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._rc(lib().sixdgs_kernel_time(self._h, kernel, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """One fused Adam step over [76, N] in place."""
+    for t, nm in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _check_f32_cuda(t, nm)
+        if t.shape != params.shape:
+            raise ValueError("params, grad, m and v must share one shape")
+    lrs = (ctypes.c_float * 6)(*[float(x) for x in lr])
+    rc = lib().sixdgs_adam(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                           ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), params.shape[1], lrs,
+                           beta1, beta2, eps, int(step), ctypes.c_void_p(_stream(stream)))
+    if rc != OK:
+        raise SixDGSError(rc, "adam failed (bad arguments)")

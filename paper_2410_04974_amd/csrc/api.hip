@@ -1,0 +1,601 @@
+// C ABI of the renderer: argument checks, workspace ownership, the order of the
+// stages on the caller's stream, and read-back for tests.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sixdgs;
+
+namespace {
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  int64_t cap = 0;
+  // Grows to at least `count` elements (contents are not kept).
+  bool ensure(int64_t count, double slack = 1.0) {
+    if (count <= cap) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    int64_t want = (int64_t)std::ceil((double)count * slack);
+    if (want < 1) want = 1;
+    if (hipMalloc((void**)&p, (size_t)want * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    cap = want;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct TimedLaunch {
+  int kernel;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct sixdgs_ctx {
+  sixdgs_settings s;
+  std::string err;
+  // per-entry workspace
+  DevBuf<Rec> rec;
+  DevBuf<uint32_t> tiles, dkey0, dkey1, dval0, dval1, poff;
+  // per-pair workspace
+  DevBuf<uint32_t> pkey0, pkey1, pval0, pval1;
+  DevBuf<uint2> ranges;
+  // per-pixel state
+  DevBuf<float> T_final;
+  DevBuf<uint32_t> last, counts;
+  // backward and loss
+  DevBuf<float> g2d, l1_partial;
+  // scratch
+  DevBuf<uint32_t> scan_blocks, hist, counters;
+  uint32_t* host_counters = nullptr;  // pinned
+  // state of the last forward
+  bool have_fwd = false;
+  bool counts_valid = false;
+  const float* fwd_params = nullptr;
+  int64_t fwd_n = 0;
+  int64_t fwd_E = 0;
+  int64_t fwd_px = 0;
+  ViewTable vt{};
+  SortBuffers sb{};
+  hipStream_t stream = nullptr;
+  // timing
+  int32_t timing_mask = 0;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> free_events;
+  double ms[SIXDGS_K_COUNT] = {0};
+  int64_t launches[SIXDGS_K_COUNT] = {0};
+};
+
+namespace {
+
+sixdgs_status fail(sixdgs_ctx* c, sixdgs_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+bool valid_settings(const sixdgs_settings* s, std::string& why) {
+  if (!(s->lambda_opa >= 0.f && s->lambda_opa <= 1.f)) { why = "lambda_opa must lie in [0, 1]"; return false; }
+  if (!(s->z_near > 0.f) || !std::isfinite(s->z_near)) { why = "z_near must be positive"; return false; }
+  for (int k = 0; k < 3; k++)
+    if (!std::isfinite(s->bg[k])) { why = "bg must be finite"; return false; }
+  const int tw = s->tile_w, th = s->tile_h;
+  if (!((tw == 8 || tw == 16 || tw == 32) && tw * th == 256)) {
+    why = "tile shape must be 8x32, 16x16 or 32x8";
+    return false;
+  }
+  if (!(s->batch == 32 || s->batch == 64 || s->batch == 128 || s->batch == 256)) {
+    why = "batch must be 32, 64, 128 or 256";
+    return false;
+  }
+  if (s->pair_capacity < 0 || s->pair_capacity > 0xFFFFFFF0ll) { why = "pair_capacity out of range"; return false; }
+  return true;
+}
+
+int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) r++;
+  return r;
+}
+
+// Builds the camera table; returns an empty string or the reason the cameras are rejected.
+std::string build_views(const sixdgs_settings& s, int64_t n, const sixdgs_camera* cams, int ncam, ViewTable& vt,
+                        int64_t& total_px) {
+  if (!cams) return "cams is NULL";
+  if (ncam < 1 || ncam > kMaxViews) return "ncam must be in [1, SIXDGS_MAX_VIEWS]";
+  std::memset(&vt, 0, sizeof(vt));
+  vt.nview = ncam;
+  vt.tile_w = s.tile_w;
+  vt.tile_h = s.tile_h;
+  vt.tile_shift_x = ilog2(s.tile_w);
+  vt.tile_shift_y = ilog2(s.tile_h);
+  vt.n = n;
+  int64_t tiles = 0;
+  total_px = 0;
+  for (int k = 0; k < ncam; k++) {
+    const sixdgs_camera& c = cams[k];
+    for (int i = 0; i < 9; i++)
+      if (!std::isfinite(c.R[i])) return "camera rotation is not finite";
+    for (int i = 0; i < 3; i++)
+      if (!std::isfinite(c.t[i])) return "camera translation is not finite";
+    if (!(c.fx > 0.f && c.fy > 0.f) || !std::isfinite(c.fx) || !std::isfinite(c.fy) || !std::isfinite(c.cx) ||
+        !std::isfinite(c.cy))
+      return "camera intrinsics must be finite with positive focal lengths";
+    if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384) return "image size out of range";
+    ViewDesc& d = vt.v[k];
+    for (int i = 0; i < 9; i++) d.R[i] = c.R[i];
+    for (int i = 0; i < 3; i++) d.t[i] = c.t[i];
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    for (int i = 0; i < 3; i++)
+      d.C[i] = (float)(-((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]));
+    d.limx = (float)(1.3 * (0.5 * (double)c.width) / (double)c.fx);
+    d.limy = (float)(1.3 * (0.5 * (double)c.height) / (double)c.fy);
+    d.W = c.width;
+    d.H = c.height;
+    d.ntx = (c.width + s.tile_w - 1) / s.tile_w;
+    d.nty = (c.height + s.tile_h - 1) / s.tile_h;
+    d.tile_base = (int32_t)tiles;
+    d.pix_base = total_px;
+    tiles += (int64_t)d.ntx * d.nty;
+    total_px += (int64_t)c.width * c.height;
+  }
+  if (tiles >= (1ll << 24)) return "too many screen tiles";
+  vt.total_tiles = (int32_t)tiles;
+  if (n < 0) return "n must be >= 0";
+  if (n * (int64_t)ncam >= (1ll << 32) - 1) return "n * ncam too large";
+  return "";
+}
+
+DevSettings dev_settings(const sixdgs_settings& s) {
+  DevSettings d;
+  d.lambda_opa = s.lambda_opa;
+  d.z_near = s.z_near;
+  for (int k = 0; k < 3; k++) d.bg[k] = s.bg[k];
+  return d;
+}
+
+constexpr int64_t kSortChunk = 2048;  // items per workgroup in the integer stage
+
+bool ensure_entries(sixdgs_ctx* c, int64_t E) {
+  const int64_t e1 = E > 0 ? E : 1;
+  return c->rec.ensure(e1) && c->tiles.ensure(e1) && c->dkey0.ensure(e1) && c->dkey1.ensure(e1) &&
+         c->dval0.ensure(e1) && c->dval1.ensure(e1) && c->poff.ensure(e1) && c->counters.ensure(4);
+}
+
+bool ensure_scratch(sixdgs_ctx* c, int64_t E, int64_t pcap) {
+  const int64_t bound = std::max<int64_t>(std::max<int64_t>(E, pcap), 1);
+  const int64_t nb = (bound + kSortChunk - 1) / kSortChunk;
+  const int64_t hist = 256 * nb;
+  const int64_t sblocks = std::max((hist + kSortChunk - 1) / kSortChunk, nb) + 1;
+  return c->hist.ensure(hist) && c->scan_blocks.ensure(sblocks);
+}
+
+bool ensure_pairs(sixdgs_ctx* c, int64_t P, double slack) {
+  const int64_t p1 = P > 0 ? P : 1;
+  return c->pkey0.ensure(p1, slack) && c->pkey1.ensure(p1, slack) && c->pval0.ensure(p1, slack) &&
+         c->pval1.ensure(p1, slack);
+}
+
+void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
+  SortBuffers& b = c->sb;
+  b.E = E;
+  b.tiles = c->tiles.p;
+  b.rec = c->rec.p;
+  b.dkey[0] = c->dkey0.p;
+  b.dkey[1] = c->dkey1.p;
+  b.dval[0] = c->dval0.p;
+  b.dval[1] = c->dval1.p;
+  b.poff = c->poff.p;
+  b.pcap = std::min(std::min(c->pkey0.cap, c->pkey1.cap), std::min(c->pval0.cap, c->pval1.cap));
+  b.pkey[0] = c->pkey0.p;
+  b.pkey[1] = c->pkey1.p;
+  b.pval[0] = c->pval0.p;
+  b.pval[1] = c->pval1.p;
+  b.ranges = c->ranges.p;
+  b.scan_blocks = c->scan_blocks.p;
+  b.scan_blocks_cap = c->scan_blocks.cap;
+  b.hist = c->hist.p;
+  b.hist_cap = c->hist.cap;
+  b.counters = c->counters.p;
+}
+
+hipEvent_t get_event(sixdgs_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct Timer {
+  sixdgs_ctx* c;
+  int k;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Timer(sixdgs_ctx* c_, int k_, hipStream_t st_) : c(c_), k(k_), st(st_) {
+    if (c->timing_mask & (1 << k)) {
+      a = get_event(c);
+      (void)hipEventRecord(a, st);
+    }
+  }
+  ~Timer() {
+    if (a) {
+      hipEvent_t b = get_event(c);
+      (void)hipEventRecord(b, st);
+      c->pending.push_back({k, a, b});
+    }
+  }
+};
+
+void collect_timing(sixdgs_ctx* c) {
+  for (auto& t : c->pending) {
+    (void)hipEventSynchronize(t.b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t.a, t.b);
+    c->ms[t.kernel] += ms;
+    c->launches[t.kernel] += 1;
+    c->free_events.push_back(t.a);
+    c->free_events.push_back(t.b);
+  }
+  c->pending.clear();
+}
+
+sixdgs_status check_launch(sixdgs_ctx* c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, SIXDGS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+  return SIXDGS_OK;
+}
+
+// Integer stage after the records and tile counts of E entries exist.
+sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
+  const bool fixed = c->s.pair_capacity > 0;
+  if (fixed) {
+    if (!ensure_pairs(c, c->s.pair_capacity, 1.0)) return fail(c, SIXDGS_ERR_OOM, "pair buffers");
+  } else if (c->pkey0.cap == 0 && !ensure_pairs(c, 1 << 16, 1.0)) {
+    return fail(c, SIXDGS_ERR_OOM, "pair buffers");
+  }
+  if (!ensure_scratch(c, E, std::max<int64_t>(c->pkey0.cap, fixed ? c->s.pair_capacity : 0)))
+    return fail(c, SIXDGS_ERR_OOM, "sort scratch");
+  if (!c->ranges.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile ranges");
+  fill_sort_buffers(c, E);
+  Timer t(c, SIXDGS_K_SORT, st);
+  launch_bin_count(c->sb, st);
+  int64_t hint = c->sb.pcap;
+  if (!fixed) {
+    // read the pair count back, then size the pair buffers exactly (with slack for the next call)
+    if (hipMemcpyAsync(c->host_counters, c->counters.p, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(c, SIXDGS_ERR_HIP, "pair count read-back failed");
+    const int64_t P = c->host_counters[1];
+    if (P > c->sb.pcap) {
+      if (!ensure_pairs(c, P, 1.25)) return fail(c, SIXDGS_ERR_OOM, "pair buffers");
+      if (!ensure_scratch(c, E, c->pkey0.cap)) return fail(c, SIXDGS_ERR_OOM, "sort scratch");
+      fill_sort_buffers(c, E);  // keeps dsorted: the depth-sorted entries are untouched
+    }
+    hint = P;
+  }
+  launch_bin_emit(c->sb, c->vt, hint, st);
+  return check_launch(c, "binning");
+}
+
+}  // namespace
+
+extern "C" {
+
+void sixdgs_default_settings(sixdgs_settings* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->lambda_opa = 0.35f;
+  s->z_near = 0.2f;
+  s->tile_w = 16;
+  s->tile_h = 16;
+  s->batch = 256;
+  s->pair_capacity = 0;
+  s->flags = 0;
+}
+
+sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s) {
+  if (!out) return SIXDGS_ERR_INVALID_ARG;
+  *out = nullptr;
+  sixdgs_settings def;
+  sixdgs_default_settings(&def);
+  if (!s) s = &def;
+  std::string why;
+  if (!valid_settings(s, why)) return SIXDGS_ERR_INVALID_ARG;
+  sixdgs_ctx* c = new (std::nothrow) sixdgs_ctx();
+  if (!c) return SIXDGS_ERR_OOM;
+  c->s = *s;
+  if (hipHostMalloc((void**)&c->host_counters, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return SIXDGS_ERR_HIP;
+  }
+  *out = c;
+  return SIXDGS_OK;
+}
+
+void sixdgs_destroy(sixdgs_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  collect_timing(c);
+  for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
+  c->rec.release();
+  c->tiles.release();
+  c->dkey0.release();
+  c->dkey1.release();
+  c->dval0.release();
+  c->dval1.release();
+  c->poff.release();
+  c->pkey0.release();
+  c->pkey1.release();
+  c->pval0.release();
+  c->pval1.release();
+  c->ranges.release();
+  c->T_final.release();
+  c->last.release();
+  c->counts.release();
+  c->g2d.release();
+  c->l1_partial.release();
+  c->scan_blocks.release();
+  c->hist.release();
+  c->counters.release();
+  if (c->host_counters) (void)hipHostFree(c->host_counters);
+  delete c;
+}
+
+sixdgs_status sixdgs_set_settings(sixdgs_ctx* c, const sixdgs_settings* s) {
+  if (!c || !s) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  std::string why;
+  if (!valid_settings(s, why)) return fail(c, SIXDGS_ERR_INVALID_ARG, why);
+  c->s = *s;
+  return SIXDGS_OK;
+}
+
+const char* sixdgs_last_error(const sixdgs_ctx* c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, const sixdgs_camera* cams, int32_t ncam,
+                             float* const* images, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (n < 0) return fail(c, SIXDGS_ERR_INVALID_ARG, "n must be >= 0");
+  if (n > 0 && !params) return fail(c, SIXDGS_ERR_INVALID_ARG, "params is NULL");
+  if (!images) return fail(c, SIXDGS_ERR_INVALID_ARG, "images is NULL");
+  ViewTable vt;
+  int64_t total_px = 0;
+  std::string why = build_views(c->s, n, cams, ncam, vt, total_px);
+  if (!why.empty()) return fail(c, SIXDGS_ERR_INVALID_ARG, why);
+  for (int k = 0; k < ncam; k++) {
+    if (!images[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "an image pointer is NULL");
+    vt.v[k].img = images[k];
+  }
+  const int64_t E = n * ncam;
+  c->have_fwd = false;
+  if (!ensure_entries(c, E)) return fail(c, SIXDGS_ERR_OOM, "entry buffers");
+  if (!c->T_final.ensure(total_px) || !c->last.ensure(total_px)) return fail(c, SIXDGS_ERR_OOM, "pixel state");
+  const bool want_counts = (c->s.flags & SIXDGS_FLAG_COUNTS) != 0;
+  if (want_counts && !c->counts.ensure(total_px)) return fail(c, SIXDGS_ERR_OOM, "pixel counts");
+  c->vt = vt;
+  const DevSettings ds = dev_settings(c->s);
+  {
+    Timer t(c, SIXDGS_K_PREPROCESS, st);
+    launch_preprocess(params, n, vt, ds, c->rec.p, c->tiles.p, st);
+  }
+  sixdgs_status rc = check_launch(c, "preprocess");
+  if (rc != SIXDGS_OK) return rc;
+  rc = run_binning(c, E, st);
+  if (rc != SIXDGS_OK) return rc;
+  BlendState bs{c->T_final.p, c->last.p, want_counts ? c->counts.p : nullptr};
+  {
+    Timer t(c, SIXDGS_K_BLEND_FWD, st);
+    launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->s.batch, st);
+  }
+  rc = check_launch(c, "blend forward");
+  if (rc != SIXDGS_OK) return rc;
+  c->have_fwd = true;
+  c->counts_valid = want_counts;
+  c->fwd_params = params;
+  c->fwd_n = n;
+  c->fwd_E = E;
+  c->fwd_px = total_px;
+  c->stream = st;
+  return SIXDGS_OK;
+}
+
+sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, const float* const* dl_dimages,
+                              float* grad, float* densify, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
+  if (params != c->fwd_params || n != c->fwd_n)
+    return fail(c, SIXDGS_ERR_STATE, "params / n differ from the last forward");
+  if (!dl_dimages) return fail(c, SIXDGS_ERR_INVALID_ARG, "dl_dimages is NULL");
+  if (n > 0 && !grad) return fail(c, SIXDGS_ERR_INVALID_ARG, "grad is NULL");
+  ViewTable vt = c->vt;
+  for (int k = 0; k < vt.nview; k++) {
+    if (!dl_dimages[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "a dL/dI pointer is NULL");
+    vt.v[k].dimg = dl_dimages[k];
+  }
+  if (n == 0) return SIXDGS_OK;
+  if (!c->g2d.ensure(c->fwd_E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
+  const DevSettings ds = dev_settings(c->s);
+  launch_zero_g2d(c->sb, c->g2d.p, st);
+  BlendState bs{c->T_final.p, c->last.p, nullptr};
+  {
+    Timer t(c, SIXDGS_K_BLEND_BWD, st);
+    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch, st);
+  }
+  sixdgs_status rc = check_launch(c, "blend backward");
+  if (rc != SIXDGS_OK) return rc;
+  {
+    Timer t(c, SIXDGS_K_PREPROCESS_BWD, st);
+    launch_preprocess_bwd(params, n, vt, ds, c->tiles.p, c->g2d.p, grad, densify, st);
+  }
+  return check_launch(c, "preprocess backward");
+}
+
+sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images, const float* const* targets,
+                             const int64_t* numel, float* const* dl_dimages, float* loss, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (nimg < 1 || nimg > kMaxViews) return fail(c, SIXDGS_ERR_INVALID_ARG, "nimg out of range");
+  if (!images || !targets || !numel || !dl_dimages || !loss) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < nimg; k++) {
+    if (!images[k] || !targets[k] || !dl_dimages[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL image pointer");
+    if (numel[k] <= 0) return fail(c, SIXDGS_ERR_INVALID_ARG, "numel must be positive");
+  }
+  const int64_t parts = l1_partial_count(nimg, numel);
+  if (!c->l1_partial.ensure(parts)) return fail(c, SIXDGS_ERR_OOM, "loss partials");
+  launch_l1(nimg, images, targets, numel, dl_dimages, c->l1_partial.p, c->l1_partial.cap, loss, (hipStream_t)stream);
+  return check_launch(c, "l1 loss");
+}
+
+sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
+                          float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || !lr || step < 1) return SIXDGS_ERR_INVALID_ARG;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return SIXDGS_ERR_INVALID_ARG;
+  launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, int32_t ncam, const float* u,
+                         const float* v, const float* ex, const float* ey, const float* depth, const int32_t* alive,
+                         void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (n < 0) return fail(c, SIXDGS_ERR_INVALID_ARG, "n must be >= 0");
+  if (n > 0 && (!u || !v || !ex || !ey || !depth || !alive)) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL array");
+  ViewTable vt;
+  int64_t total_px = 0;
+  std::string why = build_views(c->s, n, cams, ncam, vt, total_px);
+  if (!why.empty()) return fail(c, SIXDGS_ERR_INVALID_ARG, why);
+  const int64_t E = n * ncam;
+  c->have_fwd = false;
+  if (!ensure_entries(c, E)) return fail(c, SIXDGS_ERR_OOM, "entry buffers");
+  c->vt = vt;
+  launch_import_records(u, v, ex, ey, depth, alive, vt, c->rec.p, c->tiles.p, st);
+  sixdgs_status rc = run_binning(c, E, st);
+  c->fwd_E = E;
+  c->fwd_px = 0;
+  c->fwd_n = n;
+  c->stream = st;
+  return rc;
+}
+
+sixdgs_status sixdgs_export(sixdgs_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64_t* written) {
+  if (!c || !dst || !written) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  *written = 0;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, SIXDGS_ERR_HIP, "stream synchronisation failed");
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  if (c->counters.p && hipMemcpy(cnt, c->counters.p, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, SIXDGS_ERR_HIP, "counter read-back failed");
+  const int64_t E = c->fwd_E;
+  const int64_t P = std::min<int64_t>(cnt[1], c->sb.pcap);
+  const int64_t T = c->vt.total_tiles;
+  auto copy = [&](const void* src, int64_t bytes) -> sixdgs_status {
+    if (bytes > cap_bytes) return fail(c, SIXDGS_ERR_INVALID_ARG, "destination too small");
+    if (bytes > 0 && hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, SIXDGS_ERR_HIP, "read-back failed");
+    *written = bytes;
+    return SIXDGS_OK;
+  };
+  switch (what) {
+    case SIXDGS_EXPORT_RECORDS: return copy(c->rec.p, E * (int64_t)sizeof(Rec));
+    case SIXDGS_EXPORT_TILES: return copy(c->tiles.p, E * 4);
+    case SIXDGS_EXPORT_VALUES: return copy(c->sb.pval[c->sb.psorted], P * 4);
+    case SIXDGS_EXPORT_RANGES: return copy(c->ranges.p, T * 8);
+    case SIXDGS_EXPORT_T_FINAL: return copy(c->T_final.p, c->fwd_px * 4);
+    case SIXDGS_EXPORT_LAST: return copy(c->last.p, c->fwd_px * 4);
+    case SIXDGS_EXPORT_COUNTS:
+      if (!c->counts_valid) return fail(c, SIXDGS_ERR_STATE, "counts need SIXDGS_FLAG_COUNTS at the forward");
+      return copy(c->counts.p, c->fwd_px * 4);
+    case SIXDGS_EXPORT_KEYS: {
+      if (P * 8 > cap_bytes) return fail(c, SIXDGS_ERR_INVALID_ARG, "destination too small");
+      std::vector<uint32_t> tk(P), tv(P);
+      std::vector<Rec> rec(E);
+      if ((P && (hipMemcpy(tk.data(), c->sb.pkey[c->sb.psorted], P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                 hipMemcpy(tv.data(), c->sb.pval[c->sb.psorted], P * 4, hipMemcpyDeviceToHost) != hipSuccess)) ||
+          (E && hipMemcpy(rec.data(), c->rec.p, E * sizeof(Rec), hipMemcpyDeviceToHost) != hipSuccess))
+        return fail(c, SIXDGS_ERR_HIP, "read-back failed");
+      uint64_t* o = (uint64_t*)dst;
+      for (int64_t i = 0; i < P; i++) {
+        uint32_t bits;
+        std::memcpy(&bits, &rec[tv[i]].c.w, 4);
+        o[i] = ((uint64_t)tk[i] << 32) | bits;
+      }
+      *written = P * 8;
+      return SIXDGS_OK;
+    }
+    case SIXDGS_EXPORT_SIZES: {
+      if (cap_bytes < 40) return fail(c, SIXDGS_ERR_INVALID_ARG, "destination too small");
+      int64_t* o = (int64_t*)dst;
+      o[0] = E;
+      o[1] = cnt[1];
+      o[2] = T;
+      o[3] = cnt[0];
+      o[4] = c->fwd_px;
+      *written = 40;
+      return SIXDGS_OK;
+    }
+    default: return fail(c, SIXDGS_ERR_INVALID_ARG, "unknown export item");
+  }
+}
+
+sixdgs_status sixdgs_check(sixdgs_ctx* c) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, SIXDGS_ERR_HIP, "stream synchronisation failed");
+  if (!c->counters.p) return SIXDGS_OK;
+  uint32_t cnt[4];
+  if (hipMemcpy(cnt, c->counters.p, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, SIXDGS_ERR_HIP, "counter read-back failed");
+  if (cnt[2]) {
+    const uint32_t zero = 0;
+    (void)hipMemcpy(c->counters.p + 2, &zero, 4, hipMemcpyHostToDevice);
+    return fail(c, SIXDGS_ERR_CAPACITY,
+                "pair capacity exceeded: " + std::to_string(cnt[1]) + " pairs > " + std::to_string(c->sb.pcap));
+  }
+  return SIXDGS_OK;
+}
+
+sixdgs_status sixdgs_set_timing(sixdgs_ctx* c, int32_t mask) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  collect_timing(c);
+  c->timing_mask = mask;
+  for (int k = 0; k < SIXDGS_K_COUNT; k++) {
+    c->ms[k] = 0;
+    c->launches[k] = 0;
+  }
+  return SIXDGS_OK;
+}
+
+sixdgs_status sixdgs_kernel_time(sixdgs_ctx* c, int32_t kernel, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches || kernel < 0 || kernel >= SIXDGS_K_COUNT)
+    return fail(c, SIXDGS_ERR_INVALID_ARG, "bad argument");
+  collect_timing(c);
+  *ms = c->ms[kernel];
+  *launches = c->launches[kernel];
+  return SIXDGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations of the gfx950 renderer: device-side camera table,
+// projected record, the settings the kernels see, and the host launchers each
+// translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sixdgs.h"
+
+namespace sixdgs {
+
+constexpr int kRows = 76;
+constexpr int kRowMuP = 0;
+constexpr int kRowMuD = 3;
+constexpr int kRowL = 6;
+constexpr int kRowSH = 27;
+constexpr int kRowOpa = 75;
+constexpr int kMaxViews = SIXDGS_MAX_VIEWS;
+constexpr int kBlock = 256;  // threads per workgroup for every kernel here
+
+// One camera as the kernels see it (passed by value in kernel arguments).
+struct ViewDesc {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float C[3];        // camera centre -R^T t
+  float limx, limy;  // Jacobian guard: 1.3 * tan(half field of view)
+  int32_t W, H;
+  int32_t ntx, nty;   // tiles per row / column
+  int32_t tile_base;  // first global tile id of this view
+  int32_t pad0;
+  int64_t pix_base;   // offset of this view in the per-pixel state arrays
+  float* img;         // [3][H][W] output (forward)
+  const float* dimg;  // [3][H][W] upstream gradient (backward)
+};
+
+struct ViewTable {
+  int32_t nview;
+  int32_t tile_w, tile_h;
+  int32_t tile_shift_x, tile_shift_y;  // log2 of tile_w, tile_h
+  int32_t total_tiles;
+  int64_t n;  // Gaussians (entry e = view * n + gaussian)
+  ViewDesc v[kMaxViews];
+};
+
+// Rasteriser constants (the 3D Gaussian splatting ones) and the method's lambda.
+struct DevSettings {
+  float lambda_opa;
+  float z_near;
+  float bg[3];
+};
+constexpr float kDilation = 0.3f;
+constexpr float kGuard = 1.3f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+
+// Projected record of one (view, Gaussian) entry, 48 bytes, gathered per pair.
+//   a = (u, v, Qxx, Qxy)   b = (Qyy, alpha_cond, ex, ey)   c = (r, g, b, depth)
+struct __align__(16) Rec {
+  float4 a, b, c;
+};
+
+// Screen-space gradient accumulator of one entry:
+//   du, dv, dQxx, dQxy, dQyy, dalpha_cond, dr, dg, db  (dQ as full-matrix gradient)
+constexpr int kG2D = 9;
+
+// Tile rectangle [x0, x1) x [y0, y1) of an extent box, the one definition used
+// by both the projection (to count tiles) and the pair emission (to list them).
+__device__ __forceinline__ void tile_rect(float u, float v, float ex, float ey, int shift_x, int shift_y, int ntx,
+                                          int nty, int& x0, int& y0, int& x1, int& y1) {
+  const float ix = 1.0f / (float)(1 << shift_x);
+  const float iy = 1.0f / (float)(1 << shift_y);
+  // a subtraction then a multiplication by an exact power of two: no contraction possible
+  x0 = (int)floorf(__fmul_rn(__fsub_rn(u, ex), ix));
+  x1 = (int)floorf(__fmul_rn(__fadd_rn(u, ex), ix)) + 1;
+  y0 = (int)floorf(__fmul_rn(__fsub_rn(v, ey), iy));
+  y1 = (int)floorf(__fmul_rn(__fadd_rn(v, ey), iy)) + 1;
+  x0 = min(max(x0, 0), ntx);
+  x1 = min(max(x1, 0), ntx);
+  y0 = min(max(y0, 0), nty);
+  y1 = min(max(y1, 0), nty);
+}
+
+// ----------------------------------------------------------- host launchers
+// preprocess.hip
+void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
+                       uint32_t* tiles, hipStream_t st);
+void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
+                           const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st);
+
+// sort.hip -- the integer stage
+struct SortBuffers {
+  // entries
+  int64_t E;
+  uint32_t* tiles;      // [E] tiles touched (input)
+  const Rec* rec;       // [E]
+  uint32_t* dkey[2];    // [E] depth keys (ping-pong)
+  uint32_t* dval[2];    // [E] entry ids
+  uint32_t* poff;       // [E] exclusive pair offsets of the depth-sorted entries
+  // pairs
+  int64_t pcap;
+  uint32_t* pkey[2];    // [pcap] global tile ids
+  uint32_t* pval[2];    // [pcap] entry ids
+  uint2* ranges;        // [total_tiles]
+  // scratch
+  uint32_t* scan_blocks;  // block sums
+  int64_t scan_blocks_cap;
+  uint32_t* hist;         // radix histograms
+  int64_t hist_cap;
+  uint32_t* counters;     // [0] binned entries, [1] pairs, [2] overflow flag, [3] spare
+  // where the sorted results ended up (index into the ping-pong pairs)
+  int dsorted, psorted;
+};
+// Stage 1: compaction of binned entries and their depth sort, then the pair
+// offsets; leaves counters[0] = binned entries, counters[1] = pairs.
+void launch_bin_count(SortBuffers& b, hipStream_t st);
+// Stage 2: emission of (tile, entry) pairs, their stable tile sort and the
+// per-tile ranges; `pairs_hint` bounds the launch sizes (the capacity in
+// fixed mode, the exact count otherwise).
+void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hipStream_t st);
+// Zero the screen-space gradient accumulators of the binned entries.
+void launch_zero_g2d(const SortBuffers& b, float* g2d, hipStream_t st);
+// sixdgs_bin's record import: (u, v, ex, ey, depth, alive) -> Rec + tiles.
+void launch_import_records(const float* u, const float* v, const float* ex, const float* ey, const float* depth,
+                           const int32_t* alive, const ViewTable& vt, Rec* rec, uint32_t* tiles, hipStream_t st);
+
+// blend.hip
+struct BlendState {
+  float* T_final;     // [pixels]
+  uint32_t* last;     // [pixels]
+  uint32_t* counts;   // [pixels] or nullptr
+};
+void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
+                      const uint32_t* pval, BlendState bs, int batch, hipStream_t st);
+void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
+                      const uint32_t* pval, BlendState bs, float* g2d, int batch, hipStream_t st);
+
+// train.hip
+void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,
+               float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
+int64_t l1_partial_count(int nimg, const int64_t* numel);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
+                 float eps, int step, hipStream_t st);
+
+}  // namespace sixdgs

@@ -1,0 +1,486 @@
+// Per-Gaussian stages of the renderer on gfx950: the slice of every 6D Gaussian
+// into its view-conditioned 3D Gaussian, SH colour and EWA projection (forward),
+// and the chain rule from screen-space gradients back to the 76 raw parameters
+// (backward).  One thread per Gaussian, all cameras of the call in registers, so
+// the 304 bytes of parameters are read from HBM once per call in coalesced rows.
+#include "internal.h"
+
+namespace sixdgs {
+namespace {
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// Index of Cholesky entry (i, j), j <= i, in the packed lower triangle.
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Direction-independent part of the slice (Sec. 3.2 eq:sigma, Algorithm 1 steps 1-3):
+// activated factor, Sigma blocks, A = Sigma_d^-1, K = Sigma_pd A, Sigma_cond.
+struct Static {
+  float L[21];
+  float Spd[3][3];
+  float A[3][3];
+  float K[3][3];
+  float Sc[3][3];
+  float mu_p[3], mu_d[3];
+  float alpha;
+};
+
+__device__ __forceinline__ float Lget(const float* L, int i, int j) { return j <= i ? L[tri(i, j)] : 0.0f; }
+
+__device__ __forceinline__ void load_static(const float* __restrict__ params, int64_t n, int64_t g, Static& s) {
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    s.mu_p[k] = params[(kRowMuP + k) * n + g];
+    s.mu_d[k] = params[(kRowMuD + k) * n + g];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; i++)
+#pragma unroll
+    for (int j = 0; j <= i; j++) {
+      float raw = params[(kRowL + tri(i, j)) * n + g];
+      s.L[tri(i, j)] = (i == j) ? expf(raw) : 2.0f * sigmoidf(raw) - 1.0f;
+    }
+  s.alpha = sigmoidf(params[kRowOpa * n + g]);
+  float Sp[3][3], Sd[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      float sp = 0.f, spd = 0.f, sd = 0.f;
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        sp += Lget(s.L, a, k) * Lget(s.L, b, k);
+        spd += Lget(s.L, a, k) * Lget(s.L, 3 + b, k);
+        sd += Lget(s.L, 3 + a, k) * Lget(s.L, 3 + b, k);
+      }
+      Sp[a][b] = sp;
+      s.Spd[a][b] = spd;
+      Sd[a][b] = sd;
+    }
+  // symmetric 3x3 inverse by the adjugate
+  float c00 = Sd[1][1] * Sd[2][2] - Sd[1][2] * Sd[2][1];
+  float c01 = Sd[1][2] * Sd[2][0] - Sd[1][0] * Sd[2][2];
+  float c02 = Sd[1][0] * Sd[2][1] - Sd[1][1] * Sd[2][0];
+  float det = Sd[0][0] * c00 + Sd[0][1] * c01 + Sd[0][2] * c02;
+  float id = 1.0f / det;
+  s.A[0][0] = c00 * id;
+  s.A[0][1] = s.A[1][0] = c01 * id;
+  s.A[0][2] = s.A[2][0] = c02 * id;
+  s.A[1][1] = (Sd[0][0] * Sd[2][2] - Sd[0][2] * Sd[2][0]) * id;
+  s.A[1][2] = s.A[2][1] = (Sd[0][2] * Sd[1][0] - Sd[0][0] * Sd[1][2]) * id;
+  s.A[2][2] = (Sd[0][0] * Sd[1][1] - Sd[0][1] * Sd[1][0]) * id;
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) s.K[a][b] = s.Spd[a][0] * s.A[0][b] + s.Spd[a][1] * s.A[1][b] + s.Spd[a][2] * s.A[2][b];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+      s.Sc[a][b] = Sp[a][b] - (s.K[a][0] * s.Spd[b][0] + s.K[a][1] * s.Spd[b][1] + s.K[a][2] * s.Spd[b][2]);
+  // exact symmetry
+  s.Sc[1][0] = s.Sc[0][1];
+  s.Sc[2][0] = s.Sc[0][2];
+  s.Sc[2][1] = s.Sc[1][2];
+}
+
+// Real SH basis of degree 3 at unit (x, y, z), textbook normalisation, no
+// Condon-Shortley phase (Sec. 4.2 colour).
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float Y[16]) {
+  const float k0 = 0.282094791773878f, k1 = 0.488602511902920f, k2a = 1.092548430592079f,
+              k2b = 0.315391565252520f, k2c = 0.546274215296040f, k3a = 0.590043589926644f,
+              k3b = 2.890611442640554f, k3c = 0.457045799464466f, k3d = 0.373176332590115f,
+              k3e = 1.445305721320277f;
+  float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = k0;
+  Y[1] = k1 * y;
+  Y[2] = k1 * z;
+  Y[3] = k1 * x;
+  Y[4] = k2a * x * y;
+  Y[5] = k2a * y * z;
+  Y[6] = k2b * (3.f * zz - 1.f);
+  Y[7] = k2a * x * z;
+  Y[8] = k2c * (xx - yy);
+  Y[9] = k3a * y * (3.f * xx - yy);
+  Y[10] = k3b * x * y * z;
+  Y[11] = k3c * y * (5.f * zz - 1.f);
+  Y[12] = k3d * z * (5.f * zz - 3.f);
+  Y[13] = k3c * x * (5.f * zz - 1.f);
+  Y[14] = k3e * z * (xx - yy);
+  Y[15] = k3a * x * (xx - 3.f * yy);
+}
+
+// Gradient of sum_k w_k Y_k w.r.t. (x, y, z), the basis taken as the
+// polynomials written in sh_basis.
+__device__ __forceinline__ void sh_basis_vjp(float x, float y, float z, const float w[16], float g[3]) {
+  const float k1 = 0.488602511902920f, k2a = 1.092548430592079f, k2b = 0.315391565252520f,
+              k2c = 0.546274215296040f, k3a = 0.590043589926644f, k3b = 2.890611442640554f,
+              k3c = 0.457045799464466f, k3d = 0.373176332590115f, k3e = 1.445305721320277f;
+  float xx = x * x, yy = y * y, zz = z * z;
+  float gx = k1 * w[3] + k2a * (y * w[4] + z * w[7]) + 2.f * k2c * x * w[8] + 6.f * k3a * x * y * w[9] +
+             k3b * y * z * w[10] + k3c * (5.f * zz - 1.f) * w[13] + 2.f * k3e * x * z * w[14] +
+             3.f * k3a * (xx - yy) * w[15];
+  float gy = k1 * w[1] + k2a * (x * w[4] + z * w[5]) - 2.f * k2c * y * w[8] + 3.f * k3a * (xx - yy) * w[9] +
+             k3b * x * z * w[10] + k3c * (5.f * zz - 1.f) * w[11] - 2.f * k3e * y * z * w[14] -
+             6.f * k3a * x * y * w[15];
+  float gz = k1 * w[2] + k2a * (y * w[5] + x * w[7]) + 6.f * k2b * z * w[6] + k3b * x * y * w[10] +
+             10.f * k3c * y * z * w[11] + k3d * (15.f * zz - 3.f) * w[12] + 10.f * k3c * x * z * w[13] +
+             k3e * (xx - yy) * w[14];
+  g[0] = gx;
+  g[1] = gy;
+  g[2] = gz;
+}
+
+// Everything about one Gaussian in one view that both directions need.
+struct ViewState {
+  float d[3], nd;     // slice direction and |mu_p - C|
+  float x[3], Ax[3];  // d - mu_d, A x
+  float mu_c[3];
+  float D, f, ac;
+  float sdir[3], ns;  // SH direction and |mu_c - C|
+  float p[3];
+  bool clx, cly;
+  float xt, yt;
+  float T[2][3];
+  float cov[3];  // xx, xy, yy
+  float Q[3];
+};
+
+// Slice for the view (Sec. 3.2 eq:mu, Sec. 4.2 eq:pdfv2), camera transform and
+// EWA projection with the 3DGS guard and dilation.  Returns false when culled.
+__device__ __forceinline__ bool view_state(const Static& s, const ViewDesc& vd, float lambda, float z_near,
+                                           ViewState& w) {
+  float nd2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    w.d[k] = s.mu_p[k] - vd.C[k];
+    nd2 += w.d[k] * w.d[k];
+  }
+  w.nd = sqrtf(nd2);
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    w.d[k] = w.d[k] / w.nd;
+    w.x[k] = w.d[k] - s.mu_d[k];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    w.Ax[r] = s.A[r][0] * w.x[0] + s.A[r][1] * w.x[1] + s.A[r][2] * w.x[2];
+    w.mu_c[r] = s.mu_p[r] + (s.K[r][0] * w.x[0] + s.K[r][1] * w.x[1] + s.K[r][2] * w.x[2]);
+  }
+  w.D = w.x[0] * w.Ax[0] + w.x[1] * w.Ax[1] + w.x[2] * w.Ax[2];
+  w.f = expf(-lambda * w.D);
+  w.ac = s.alpha * w.f;
+  float ns2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    w.sdir[k] = w.mu_c[k] - vd.C[k];
+    ns2 += w.sdir[k] * w.sdir[k];
+  }
+  w.ns = sqrtf(ns2);
+#pragma unroll
+  for (int k = 0; k < 3; k++) w.sdir[k] = w.sdir[k] / w.ns;
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+    w.p[r] = vd.R[3 * r] * w.mu_c[0] + vd.R[3 * r + 1] * w.mu_c[1] + vd.R[3 * r + 2] * w.mu_c[2] + vd.t[r];
+  if (!(w.p[2] > z_near)) return false;
+  const float z = w.p[2];
+  const float rx = w.p[0] / z, ry = w.p[1] / z;
+  w.clx = (rx < -vd.limx) || (rx > vd.limx);
+  w.cly = (ry < -vd.limy) || (ry > vd.limy);
+  w.xt = fminf(vd.limx, fmaxf(-vd.limx, rx));
+  w.yt = fminf(vd.limy, fmaxf(-vd.limy, ry));
+  const float j00 = vd.fx / z, j02 = -vd.fx * w.xt / z, j11 = vd.fy / z, j12 = -vd.fy * w.yt / z;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    w.T[0][c] = j00 * vd.R[c] + j02 * vd.R[6 + c];
+    w.T[1][c] = j11 * vd.R[3 + c] + j12 * vd.R[6 + c];
+  }
+  float TS[2][3];
+#pragma unroll
+  for (int r = 0; r < 2; r++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) TS[r][c] = w.T[r][0] * s.Sc[0][c] + w.T[r][1] * s.Sc[1][c] + w.T[r][2] * s.Sc[2][c];
+  w.cov[0] = TS[0][0] * w.T[0][0] + TS[0][1] * w.T[0][1] + TS[0][2] * w.T[0][2] + kDilation;
+  w.cov[1] = TS[0][0] * w.T[1][0] + TS[0][1] * w.T[1][1] + TS[0][2] * w.T[1][2];
+  w.cov[2] = TS[1][0] * w.T[1][0] + TS[1][1] * w.T[1][1] + TS[1][2] * w.T[1][2] + kDilation;
+  const float det = w.cov[0] * w.cov[2] - w.cov[1] * w.cov[1];
+  if (!(det > 0.f)) return false;
+  const float idet = 1.0f / det;
+  w.Q[0] = w.cov[2] * idet;
+  w.Q[1] = -w.cov[1] * idet;
+  w.Q[2] = w.cov[0] * idet;
+  return true;
+}
+
+__global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__ params, int64_t n, ViewTable vt,
+                                                       DevSettings ds, Rec* __restrict__ rec,
+                                                       uint32_t* __restrict__ tiles) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= n) return;
+  Static s;
+  load_static(params, n, g, s);
+  for (int vi = 0; vi < vt.nview; vi++) {
+    const ViewDesc& vd = vt.v[vi];
+    const int64_t e = (int64_t)vi * n + g;
+    ViewState w;
+    uint32_t count = 0;
+    if (view_state(s, vd, ds.lambda_opa, ds.z_near, w) && w.ac * 255.0f >= 1.0f) {
+      const float qmax = 2.0f * logf(255.0f * w.ac);
+      const float ex = sqrtf(qmax * w.cov[0]);
+      const float ey = sqrtf(qmax * w.cov[2]);
+      const float u = vd.fx * w.p[0] / w.p[2] + vd.cx;
+      const float v = vd.fy * w.p[1] / w.p[2] + vd.cy;
+      int x0, y0, x1, y1;
+      tile_rect(u, v, ex, ey, vt.tile_shift_x, vt.tile_shift_y, vd.ntx, vd.nty, x0, y0, x1, y1);
+      count = (uint32_t)((x1 - x0) * (y1 - y0));
+      if (count > 0) {
+        float Y[16];
+        sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
+        float col[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < 16; k++) acc += params[(kRowSH + 3 * k + c) * n + g] * Y[k];
+          col[c] = sigmoidf(acc);
+        }
+        Rec r;
+        r.a = make_float4(u, v, w.Q[0], w.Q[1]);
+        r.b = make_float4(w.Q[2], w.ac, ex, ey);
+        r.c = make_float4(col[0], col[1], col[2], w.p[2]);
+        rec[e] = r;
+      }
+    }
+    tiles[e] = count;
+  }
+}
+
+// ------------------------------------------------------------------ backward
+__global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* __restrict__ params, int64_t n, ViewTable vt,
+                                                           DevSettings ds, const uint32_t* __restrict__ tiles,
+                                                           const float* __restrict__ g2d, float* __restrict__ grad,
+                                                           float* __restrict__ densify) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= n) return;
+  bool any = false;
+  for (int vi = 0; vi < vt.nview; vi++) any |= tiles[(int64_t)vi * n + g] > 0;
+  if (!any) {
+    for (int r = 0; r < kRows; r++) grad[r * n + g] = 0.f;
+    return;
+  }
+  Static s;
+  load_static(params, n, g, s);
+  float beta[16][3];
+#pragma unroll
+  for (int k = 0; k < 16; k++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) beta[k][c] = params[(kRowSH + 3 * k + c) * n + g];
+
+  // accumulators summed over views
+  float g_beta[16][3];
+#pragma unroll
+  for (int k = 0; k < 16; k++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) g_beta[k][c] = 0.f;
+  float g_mup[3] = {0, 0, 0}, g_mud[3] = {0, 0, 0}, g_alpha = 0.f;
+  float g_Sc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dSigma_cond (symmetric)
+  float g_Spd_mu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // mu_cond part of dL/dSigma_pd
+  float g_A_mu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};    // mu_cond and D parts of dL/dA
+  float dens_norm = 0.f, dens_cnt = 0.f;
+
+  for (int vi = 0; vi < vt.nview; vi++) {
+    const ViewDesc& vd = vt.v[vi];
+    const int64_t e = (int64_t)vi * n + g;
+    if (tiles[e] == 0) continue;
+    ViewState w;
+    view_state(s, vd, ds.lambda_opa, ds.z_near, w);
+    const float* gp = g2d + e * kG2D;
+    const float gu = gp[0], gv = gp[1], gqxx = gp[2], gqxy = gp[3], gqyy = gp[4], gac = gp[5];
+    const float z = w.p[2], fx = vd.fx, fy = vd.fy;
+    dens_norm += sqrtf((gu * 0.5f * vd.W) * (gu * 0.5f * vd.W) + (gv * 0.5f * vd.H) * (gv * 0.5f * vd.H));
+    dens_cnt += 1.f;
+    // conic -> 2D covariance: G_S = -Q G_Q Q
+    const float Q00 = w.Q[0], Q01 = w.Q[1], Q11 = w.Q[2];
+    const float QG00 = Q00 * gqxx + Q01 * gqxy, QG01 = Q00 * gqxy + Q01 * gqyy;
+    const float QG10 = Q01 * gqxx + Q11 * gqxy, QG11 = Q01 * gqxy + Q11 * gqyy;
+    const float GS00 = -(QG00 * Q00 + QG01 * Q01);
+    const float GS01 = -(QG00 * Q01 + QG01 * Q11);
+    const float GS11 = -(QG10 * Q01 + QG11 * Q11);
+    const float GS[2][2] = {{GS00, GS01}, {GS01, GS11}};
+    // Sigma_2D = T Sigma_c T^T + dil I:  dSigma_c = T^T G_S T,  dT = 2 G_S T Sigma_c
+    float GT[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) GT[r][c] = GS[r][0] * w.T[0][c] + GS[r][1] * w.T[1][c];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) g_Sc[a][b] += w.T[0][a] * GT[0][b] + w.T[1][a] * GT[1][b];
+    float dT[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+      for (int c = 0; c < 3; c++)
+        dT[r][c] = 2.f * (GT[r][0] * s.Sc[0][c] + GT[r][1] * s.Sc[1][c] + GT[r][2] * s.Sc[2][c]);
+    // T = J R:  dJ = dT R^T (only the non-zero entries of J matter)
+    const float dJ00 = dT[0][0] * vd.R[0] + dT[0][1] * vd.R[1] + dT[0][2] * vd.R[2];
+    const float dJ02 = dT[0][0] * vd.R[6] + dT[0][1] * vd.R[7] + dT[0][2] * vd.R[8];
+    const float dJ11 = dT[1][0] * vd.R[3] + dT[1][1] * vd.R[4] + dT[1][2] * vd.R[5];
+    const float dJ12 = dT[1][0] * vd.R[6] + dT[1][1] * vd.R[7] + dT[1][2] * vd.R[8];
+    const float iz = 1.0f / z, iz2 = iz * iz;
+    float dp0 = 0.f, dp1 = 0.f, dp2 = -(dJ00 * fx + dJ11 * fy) * iz2;
+    if (!w.clx) {
+      dp0 += -dJ02 * fx * iz2;
+      dp2 += dJ02 * 2.f * fx * w.p[0] * iz2 * iz;
+    } else {
+      dp2 += dJ02 * fx * w.xt * iz2;
+    }
+    if (!w.cly) {
+      dp1 += -dJ12 * fy * iz2;
+      dp2 += dJ12 * 2.f * fy * w.p[1] * iz2 * iz;
+    } else {
+      dp2 += dJ12 * fy * w.yt * iz2;
+    }
+    // u = fx px/pz + cx, v = fy py/pz + cy
+    dp0 += gu * fx * iz;
+    dp1 += gv * fy * iz;
+    dp2 -= (gu * fx * w.p[0] + gv * fy * w.p[1]) * iz2;
+    // p = R mu_c + t
+    float gmu[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) gmu[k] = vd.R[k] * dp0 + vd.R[3 + k] * dp1 + vd.R[6 + k] * dp2;
+    // SH colour (Sec. 4.2): rgb = sigmoid(sum beta Y(s)), s = (mu_c - C)/|mu_c - C|
+    float Y[16];
+    sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
+    float wsum[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) wsum[k] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
+      const float col = sigmoidf(acc);
+      const float dsc = gp[6 + c] * col * (1.f - col);
+#pragma unroll
+      for (int k = 0; k < 16; k++) {
+        g_beta[k][c] += dsc * Y[k];
+        wsum[k] += dsc * beta[k][c];
+      }
+    }
+    float gs[3];
+    sh_basis_vjp(w.sdir[0], w.sdir[1], w.sdir[2], wsum, gs);
+    const float sdot = w.sdir[0] * gs[0] + w.sdir[1] * gs[1] + w.sdir[2] * gs[2];
+#pragma unroll
+    for (int k = 0; k < 3; k++) gmu[k] += (gs[k] - w.sdir[k] * sdot) / w.ns;
+    // slice (Sec. 3.2): mu_c = mu_p + K x, D = x^T A x, alpha_c = alpha exp(-lambda D)
+    const float dD = -ds.lambda_opa * w.ac * gac;
+    float gx[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) gx[k] = s.K[0][k] * gmu[0] + s.K[1][k] * gmu[1] + s.K[2][k] * gmu[2] + 2.f * dD * w.Ax[k];
+    const float ddot = w.d[0] * gx[0] + w.d[1] * gx[1] + w.d[2] * gx[2];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      g_mud[k] -= gx[k];
+      g_mup[k] += gmu[k] + (gx[k] - w.d[k] * ddot) / w.nd;
+    }
+    g_alpha += gac * w.f;
+    float st_g[3];  // Sigma_pd^T gmu
+#pragma unroll
+    for (int a = 0; a < 3; a++) st_g[a] = s.Spd[0][a] * gmu[0] + s.Spd[1][a] * gmu[1] + s.Spd[2][a] * gmu[2];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        g_Spd_mu[a][b] += gmu[a] * w.Ax[b];
+        g_A_mu[a][b] += 0.5f * (st_g[a] * w.x[b] + st_g[b] * w.x[a]) + dD * w.x[a] * w.x[b];
+      }
+  }
+  // direction-independent tail: Sigma_cond = Sigma_p - Sigma_pd A Sigma_pd^T
+  float GSc[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) GSc[a][b] = 0.5f * (g_Sc[a][b] + g_Sc[b][a]);
+  float GcSpd[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) GcSpd[a][b] = GSc[a][0] * s.Spd[0][b] + GSc[a][1] * s.Spd[1][b] + GSc[a][2] * s.Spd[2][b];
+  float GSpd[3][3], GA[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      GSpd[a][b] = g_Spd_mu[a][b] - 2.f * (GcSpd[a][0] * s.A[0][b] + GcSpd[a][1] * s.A[1][b] + GcSpd[a][2] * s.A[2][b]);
+      GA[a][b] = g_A_mu[a][b] - (s.Spd[0][a] * GcSpd[0][b] + s.Spd[1][a] * GcSpd[1][b] + s.Spd[2][a] * GcSpd[2][b]);
+    }
+  // A = Sigma_d^-1:  dSigma_d = -A dA A
+  float AG[3][3], GSd[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) AG[a][b] = s.A[a][0] * GA[0][b] + s.A[a][1] * GA[1][b] + s.A[a][2] * GA[2][b];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) GSd[a][b] = -(AG[a][0] * s.A[0][b] + AG[a][1] * s.A[1][b] + AG[a][2] * s.A[2][b]);
+  // Sigma = L L^T:  dL = lower(2 G6 L), G6 = [[G_p, G_pd/2], [G_pd^T/2, G_d]]
+  float G6[6][6];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      G6[a][b] = GSc[a][b];
+      G6[3 + a][3 + b] = 0.5f * (GSd[a][b] + GSd[b][a]);
+      G6[a][3 + b] = 0.5f * GSpd[a][b];
+      G6[3 + b][a] = 0.5f * GSpd[a][b];
+    }
+#pragma unroll
+  for (int i = 0; i < 6; i++)
+#pragma unroll
+    for (int j = 0; j <= i; j++) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = j; k < 6; k++) acc += G6[i][k] * Lget(s.L, k, j);
+      const float gl = 2.f * acc;
+      const float Lij = s.L[tri(i, j)];
+      // exp on the diagonal; 2 sigmoid(r) - 1 elsewhere, whose derivative is (1 - L)(1 + L)/2
+      const float graw = (i == j) ? gl * Lij : gl * 0.5f * (1.f - Lij) * (1.f + Lij);
+      grad[(kRowL + tri(i, j)) * n + g] = graw;
+    }
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    grad[(kRowMuP + k) * n + g] = g_mup[k];
+    grad[(kRowMuD + k) * n + g] = g_mud[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 16; k++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) grad[(kRowSH + 3 * k + c) * n + g] = g_beta[k][c];
+  grad[kRowOpa * n + g] = g_alpha * s.alpha * (1.f - s.alpha);
+  if (densify) {
+    densify[g] += dens_norm;
+    densify[n + g] += dens_cnt;
+  }
+}
+
+}  // namespace
+
+void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
+                       uint32_t* tiles, hipStream_t st) {
+  if (n <= 0) return;
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, rec, tiles);
+}
+
+void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
+                           const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st) {
+  if (n <= 0) return;
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_preprocess_bwd, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, grad,
+                     densify);
+}
+
+}  // namespace sixdgs

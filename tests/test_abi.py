@@ -1,0 +1,53 @@
+"""The C ABI library loads on the host and exports every entry point its header
+declares; argument checks that need no device run here too."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+from paper_2410_04974_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "sixdgs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sixdgs_\w+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_surface():
+    decl = declared_functions()
+    assert decl == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_default_settings_on_host():
+    s = _lib.default_settings()
+    assert abs(s.lambda_opa - 0.35) < 1e-7 and abs(s.z_near - 0.2) < 1e-7
+    assert (s.tile_w, s.tile_h, s.batch, s.pair_capacity) == (16, 16, 256, 0)
+
+
+def test_adam_rejects_bad_arguments_before_any_launch():
+    L = _lib.lib()
+    lr = (ctypes.c_float * 6)(*([1e-3] * 6))
+    # step 0 and beta out of range are refused without touching a device
+    assert L.sixdgs_adam(None, None, None, None, 0, lr, 0.9, 0.999, 1e-15, 0, None) == _lib.ERR_INVALID_ARG
+    assert L.sixdgs_adam(None, None, None, None, 0, lr, 1.5, 0.999, 1e-15, 1, None) == _lib.ERR_INVALID_ARG
+    assert L.sixdgs_adam(None, None, None, None, 5, lr, 0.9, 0.999, 1e-15, 1, None) == _lib.ERR_INVALID_ARG
+
+
+def test_create_rejects_unsupported_settings():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    for kw in ({"tile_w": 16, "tile_h": 8}, {"batch": 100}, {"lambda_opa": 1.5}, {"z_near": 0.0},
+               {"pair_capacity": -1}):
+        s = _lib.default_settings(**kw)
+        assert L.sixdgs_create(ctypes.byref(h), ctypes.byref(s)) == _lib.ERR_INVALID_ARG
+        assert not h.value

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through its C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars (derived from float32 arithmetic against float64, see the design notes):
+  * integer stage (tile counts, keys, order, ranges) bit-exact given the same
+    float32 records;
+  * pixels within 1e-4 absolute everywhere the oracle does not flag a
+    threshold decision as ambiguous;
+  * gradients within 1e-3 relative (norm per parameter group).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+PIX_TOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2410_04974_amd import lib
+    lib()  # fails loudly when lib6dgs.so is missing
+    yield
+
+
+# ------------------------------------------------------------------ records
+@pytest.mark.parametrize("name,n", [("c0", None), ("c1", 20000), ("c2", 20000)])
+def test_records_match_oracle(name, n):
+    w, p = G.scene(name, n)
+    cam = w.cameras[0]
+    r, _, _ = G.render(p, [cam])
+    rec, tiles = G.records(r)
+    o = oracle.preprocess(p, cam)
+    alive_o = o["alive"]
+    binned = tiles > 0
+    # every GPU-binned entry is alive for the oracle (up to threshold cases)
+    both = binned & alive_o
+    _say(name, "binned", binned.sum(), "oracle alive", alive_o.sum(), "both", both.sum())
+    assert both.sum() >= 0.999 * binned.sum()
+    e = {}
+    e["u"] = np.abs(rec[both, G.REC_U] - o["u"][both]).max()
+    e["v"] = np.abs(rec[both, G.REC_V] - o["v"][both]).max()
+    for k, col in (("Qxx", G.REC_QXX), ("Qxy", G.REC_QXY), ("Qyy", G.REC_QYY)):
+        ref = o["conic"][both, {"Qxx": 0, "Qxy": 1, "Qyy": 2}[k]]
+        scale = np.maximum(np.abs(o["conic"][both, 0]), np.abs(o["conic"][both, 2]))
+        e[k] = (np.abs(rec[both, col] - ref) / scale).max()
+    e["alpha_c"] = G.rel_err(rec[both, G.REC_AC], o["alpha_cond"][both], 1e-6).max()
+    e["rgb"] = np.abs(rec[both][:, [G.REC_R, G.REC_G, G.REC_B]] - o["rgb"][both]).max()
+    e["depth"] = G.rel_err(rec[both, G.REC_DEPTH], o["depth"][both], 1e-6).max()
+    # the extents are sqrt(q_max * Sigma2D_xx) with q_max = 2 ln(255 alpha_cond): compare the
+    # q_max they imply (its absolute error, unlike the extent's relative one, stays bounded as
+    # alpha_cond approaches 1/255)
+    e["qmax_x"] = (np.abs(rec[both, G.REC_EX].astype(np.float64) ** 2 - o["ex"][both] ** 2) / o["cov2d"][both, 0]).max()
+    e["qmax_y"] = (np.abs(rec[both, G.REC_EY].astype(np.float64) ** 2 - o["ey"][both] ** 2) / o["cov2d"][both, 2]).max()
+    _say(name, {k: f"{v:.2e}" for k, v in e.items()})
+    assert e["u"] < 2e-3 and e["v"] < 2e-3
+    assert max(e["Qxx"], e["Qxy"], e["Qyy"]) < 2e-4
+    assert e["alpha_c"] < 2e-5
+    assert e["rgb"] < 2e-6
+    assert e["depth"] < 1e-6
+    assert max(e["qmax_x"], e["qmax_y"]) < 1e-4
+
+
+# ------------------------------------------------------------ integer stage
+def _random_records(n, cams, seed):
+    rng = np.random.default_rng(seed)
+    E = n * len(cams)
+    W = max(c.width for c in cams)
+    H = max(c.height for c in cams)
+    u = rng.uniform(-0.2 * W, 1.2 * W, E).astype(np.float32)
+    v = rng.uniform(-0.2 * H, 1.2 * H, E).astype(np.float32)
+    ex = rng.exponential(10, E).astype(np.float32)
+    ey = rng.exponential(10, E).astype(np.float32)
+    big = rng.random(E) < 0.002
+    ex[big] *= 30
+    ey[big] *= 30
+    depth = rng.uniform(0.5, 8.0, E).astype(np.float32)
+    ties = rng.random(E) < 0.3
+    depth[ties] = np.float32(2.0)  # many exactly equal depths: order falls back to entry id
+    alive = (rng.random(E) < 0.9).astype(np.int32)
+    # some extents exactly on tile boundaries
+    k = rng.random(E) < 0.05
+    u[k] = np.float32(32.0) + ex[k]
+    return u, v, ex, ey, depth, alive
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32)])
+@pytest.mark.parametrize("case", ["one_view", "three_views", "empty"])
+def test_binning_bit_exact(tile, case):
+    if case == "one_view":
+        cams = [synth.default_camera(203, 157)]
+        n = 5000
+    elif case == "three_views":
+        cams = [synth.default_camera(64, 64), synth.default_camera(400, 130), synth.default_camera(33, 517)]
+        n = 3000
+    else:
+        cams = [synth.default_camera(100, 100)]
+        n = 700
+    u, v, ex, ey, depth, alive = _random_records(n, cams, seed=11)
+    if case == "empty":
+        alive[:] = 0
+    r = G.renderer(tile=tile)
+    dev = [torch.from_numpy(a).to(G.DEV) for a in (u, v, ex, ey, depth, alive)]
+    r.ctx.bin(n, cams, *dev)
+    from paper_2410_04974_amd import _lib
+    keys = r.ctx.export(_lib.EXPORT_KEYS)
+    vals = r.ctx.export(_lib.EXPORT_VALUES)
+    ranges = r.ctx.export(_lib.EXPORT_RANGES)
+    tiles = r.ctx.export(_lib.EXPORT_TILES)
+    ref = oracle.bin_records(u, v, ex, ey, depth, alive.astype(bool), n, cams, tile[0], tile[1])
+    _say(case, tile, "pairs", len(ref["keys"]))
+    assert np.array_equal(tiles, ref["tiles_touched"].astype(np.int32))
+    assert np.array_equal(keys, ref["keys"])
+    assert np.array_equal(vals, ref["values"].astype(np.int32))
+    assert np.array_equal(ranges, ref["ranges"].astype(np.int32))
+
+
+# ------------------------------------------------------------------ forward
+def _compare_pixels(img, T, ref_img, ref_T, amb, tag):
+    ok = ~amb
+    err = np.abs(img - ref_img).max(axis=0)
+    terr = np.abs(T - ref_T)
+    _say(tag, "max err (non-ambiguous)", f"{err[ok].max():.2e}", "T err", f"{terr[ok].max():.2e}",
+         "ambiguous frac", f"{amb.mean():.4f}", "max err on ambiguous", f"{err[amb].max() if amb.any() else 0:.2e}")
+    assert err[ok].max() < PIX_TOL
+    assert terr[ok].max() < PIX_TOL
+    return err
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_forward_full_frame_c0(tile):
+    w, p = G.scene("c0")
+    cam = w.cameras[0]
+    r, _, imgs = G.render(p, [cam], tile=tile, flags=1)
+    from paper_2410_04974_amd import _lib
+    T = r.ctx.export(_lib.EXPORT_T_FINAL).reshape(cam.height, cam.width)
+    cnt = r.ctx.export(_lib.EXPORT_COUNTS).reshape(cam.height, cam.width)
+    ref, refT, refn, amb = oracle.render(p, cam)
+    _compare_pixels(imgs[0], T, ref, refT, amb, f"c0 {tile}")
+    assert np.array_equal(cnt[~amb], refn[~amb])
+
+
+def test_forward_ragged_multi_tile_scene_with_background():
+    """Image sizes that are not tile multiples, a non-zero background and a
+    scene dense enough to fill many tiles."""
+    w, p = G.scene("c1", 30000)
+    cam = synth.default_camera(203, 150)
+    st = oracle.Settings(bg=(0.25, 0.5, 1.0))
+    r, _, imgs = G.render(p, [cam], bg=st.bg)
+    from paper_2410_04974_amd import _lib
+    T = r.ctx.export(_lib.EXPORT_T_FINAL).reshape(cam.height, cam.width)
+    ref, refT, _, amb = oracle.render(p, cam, st)
+    _compare_pixels(imgs[0], T, ref, refT, amb, "ragged")
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_forward_sampled_pixels_full_size(name):
+    """Full-size workload, 4096 seeded pixels against the oracle."""
+    w, p = G.scene(name)
+    cam = w.cameras[0]
+    r, _, imgs = G.render(p, [cam])
+    from paper_2410_04974_amd import _lib
+    T = r.ctx.export(_lib.EXPORT_T_FINAL)
+    pix = synth.pixel_subset(cam.width, cam.height, 4096)
+    ref, refT, _, amb = oracle.render(p, cam, pixels=pix)
+    img = imgs[0].reshape(3, -1)[:, pix]
+    _compare_pixels(img, T[pix], ref.T, refT, amb, name)
+    assert amb.mean() < 0.15
+
+
+def test_forward_tile_shapes_bitwise_equal():
+    """The image does not depend on the tile shape or batch depth."""
+    w, p = G.scene("c1", 30000)
+    cam = synth.default_camera(256, 192)
+    outs = []
+    for tile, batch in (((16, 16), 256), ((32, 8), 64), ((8, 32), 128)):
+        _, _, imgs = G.render(p, [cam], tile=tile, batch=batch)
+        outs.append(imgs[0])
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+# ----------------------------------------------------------------- backward
+def _group_errors(g, ref):
+    out = {}
+    for nm, (a, b) in {"mu_p": (0, 3), "mu_d": (3, 6), "L": (6, 27), "sh": (27, 75), "opacity": (75, 76)}.items():
+        den = np.linalg.norm(ref[a:b])
+        out[nm] = np.linalg.norm(g[a:b] - ref[a:b]) / max(den, 1e-30)
+    return out
+
+
+@pytest.mark.parametrize("name,n,size", [("c1", 20000, (256, 256)), ("c2", 20000, (200, 160))])
+def test_backward_matches_oracle_gradient(name, n, size):
+    w, p = G.scene(name, n)
+    cam = synth.default_camera(*size)
+    ref_img, _, _, amb = oracle.render(p, cam)
+    dl = synth.upstream_gradient([cam])[0].astype(np.float64)
+    dl[:, amb] = 0.0  # no gradient through pixels whose threshold decisions may legitimately differ
+    r, pt, _ = G.render(p, [cam])
+    g = r.backward(pt, [torch.from_numpy(dl.astype(np.float32)).to(G.DEV)]).cpu().numpy().astype(np.float64)
+    ref, _ = oracle.backward(p, cam, dl)
+    errs = _group_errors(g, ref)
+    _say(name, "grad rel err per group", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert all(v < 1e-3 for v in errs.values())
