@@ -98,8 +98,8 @@ bool valid_settings(const sixdgs_settings* s, std::string& why) {
     why = "tile shape must be 8x32, 16x16 or 32x8";
     return false;
   }
-  if (!(s->batch == 32 || s->batch == 64 || s->batch == 128 || s->batch == 256)) {
-    why = "batch must be 32, 64, 128 or 256";
+  if (!(s->batch == 64 || s->batch == 128 || s->batch == 256)) {
+    why = "batch must be 64, 128 or 256";
     return false;
   }
   if (s->pair_capacity < 0 || s->pair_capacity > 0xFFFFFFF0ll) { why = "pair_capacity out of range"; return false; }

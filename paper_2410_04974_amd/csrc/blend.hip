@@ -6,9 +6,11 @@
 // One workgroup of 256 threads per screen tile, one pixel per thread; each
 // 64-lane wavefront owns an 8x8 block of the tile.  The tile's depth-ordered
 // list is staged through LDS in batches; while staging, each Gaussian's
-// extent box is tested against the four blocks and every wavefront gets its
-// own order-preserving list of the Gaussians that can reach its pixels, so
-// the per-pixel loop never visits a Gaussian its block cannot see.
+// alpha >= 1/255 ellipse is tested exactly against the four blocks and every
+// wavefront gets its own order-preserving list of the Gaussians that can reach
+// its pixels, so the per-pixel loop -- the kernels' critical path, since a
+// screen this size has fewer wavefronts than the chip can hold -- never
+// visits a Gaussian its block cannot see.
 #include "internal.h"
 
 namespace sixdgs {
@@ -52,6 +54,36 @@ __device__ __forceinline__ bool box_hits(const Rec& r, float x0, float y0) {
          (r.a.y - r.b.w <= y0 + 8.0f);
 }
 
+// Can any pixel centre of the 8x8 block reach alpha >= 1/255, i.e. does the
+// ellipse q(x) = (x - m)^T Q (x - m) <= q_max = 2 ln(255 alpha_cond) meet the
+// block's rectangle of centres?  The minimum of the convex q over the
+// rectangle is 0 when the centre m lies inside; otherwise it lies on an edge
+// whose line separates m from the rectangle, and along an edge q is a 1D
+// quadratic minimised by clamping.  A relative margin keeps the test
+// conservative under float32 rounding, so it only skips Gaussians that no
+// pixel of the block would take.
+__device__ __forceinline__ bool ellipse_hits(const Rec& r, float x0, float y0) {
+  if (!box_hits(r, x0, y0)) return false;
+  const float qa = r.a.z, qb = r.a.w, qc = r.b.x;
+  const float lim = 2.0f * logf(255.0f * r.b.y) * 1.001f + 1e-3f;
+  const float xl = x0 - r.a.x, xh = xl + 7.0f;
+  const float yl = y0 - r.a.y, yh = yl + 7.0f;
+  const bool inx = xl <= 0.f && xh >= 0.f, iny = yl <= 0.f && yh >= 0.f;
+  if (inx && iny) return true;
+  float best = 3.0e38f;
+  if (!inx) {
+    const float dx = xl > 0.f ? xl : xh;
+    const float dy = fminf(fmaxf(-qb * dx / qc, yl), yh);
+    best = fminf(best, qa * dx * dx + 2.0f * qb * dx * dy + qc * dy * dy);
+  }
+  if (!iny) {
+    const float dy = yl > 0.f ? yl : yh;
+    const float dx = fminf(fmaxf(-qb * dy / qa, xl), xh);
+    best = fminf(best, qa * dx * dx + 2.0f * qb * dx * dy + qc * dy * dy);
+  }
+  return best <= lim;
+}
+
 __device__ __forceinline__ int find_view(const ViewTable& vt, int tile) {
   int v = 0;
   for (int k = 1; k < vt.nview; k++)
@@ -88,7 +120,7 @@ __device__ __forceinline__ uint32_t stage_batch(BatchLDS& L, const Rec* __restri
     L.rec[t] = stage(r, e);
 #pragma unroll
     for (int w = 0; w < kWaves; w++)
-      if (box_hits(r, ox + TileMap<TW>::bx(w), oy + TileMap<TW>::by(w))) mask |= 1u << w;
+      if (ellipse_hits(r, ox + TileMap<TW>::bx(w), oy + TileMap<TW>::by(w))) mask |= 1u << w;
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t rank[kWaves];

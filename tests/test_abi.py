@@ -46,8 +46,8 @@ def test_adam_rejects_bad_arguments_before_any_launch():
 def test_create_rejects_unsupported_settings():
     L = _lib.lib()
     h = ctypes.c_void_p()
-    for kw in ({"tile_w": 16, "tile_h": 8}, {"batch": 100}, {"lambda_opa": 1.5}, {"z_near": 0.0},
-               {"pair_capacity": -1}):
+    for kw in ({"tile_w": 16, "tile_h": 8}, {"batch": 100}, {"batch": 32}, {"lambda_opa": 1.5}, {"z_near": 0.0},
+               {"pair_capacity": -1}, {"tile_w": 32, "tile_h": 16}):
         s = _lib.default_settings(**kw)
         assert L.sixdgs_create(ctypes.byref(h), ctypes.byref(s)) == _lib.ERR_INVALID_ARG
         assert not h.value
