@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
   const int py = ty * TileMap<TW>::TH + TileMap<TW>::by(wv) + (l >> 3);
   const bool inside = px < vd.W && py < vd.H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint32_t* list4 = reinterpret_cast<const uint32_t*>(L.list[wv]);
 
   const uint2 rg = ranges[tile];
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -172,27 +173,40 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
     const uint32_t nb = min((uint32_t)batch, rg.y - b0);
     const uint32_t wn = stage_batch<TW>(L, rec, pval, b0, nb, ox, oy);
     const uint32_t pos0 = b0 - rg.x + 1;
-    for (uint32_t k = 0; k < wn; k++) {
+    // four list slots per LDS word; their records are read together so one LDS
+    // round trip serves four Gaussians (slots past wn hold stale but in-range bytes)
+    for (uint32_t g4 = 0; 4 * g4 < wn; g4++) {
       if (__ballot(!done) == 0) break;
-      const uint32_t j = L.list[wv][k];
-      const float4 A = L.rec[j].a;
-      const float4 B = L.rec[j].b;
-      const float p = log2_alpha(A, B, fx - A.x, fy - A.y);
-      if (done || p < kLog2AlphaMin) continue;
-      const float a = fminf(kAlphaMax, exp2_fast(p));
-      const float Tn = T * (1.0f - a);
-      if (Tn < kTMin) {
-        done = true;
-        continue;
+      const uint32_t w4 = list4[g4];
+      uint32_t js[4];
+      float4 A[4], B[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        js[u] = (w4 >> (8 * u)) & 255u;
+        A[u] = L.rec[js[u]].a;
+        B[u] = L.rec[js[u]].b;
       }
-      const float4 Cc = L.rec[j].c;
-      const float wgt = a * T;
-      C0 += Cc.x * wgt;
-      C1 += Cc.y * wgt;
-      C2 += Cc.z * wgt;
-      T = Tn;
-      last = pos0 + j;
-      cnt++;
+      const uint32_t nu = min(4u, wn - 4 * g4);
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if ((uint32_t)u >= nu) break;
+        const float p = log2_alpha(A[u], B[u], fx - A[u].x, fy - A[u].y);
+        if (done || p < kLog2AlphaMin) continue;
+        const float a = fminf(kAlphaMax, exp2_fast(p));
+        const float Tn = T * (1.0f - a);
+        if (Tn < kTMin) {
+          done = true;
+          continue;
+        }
+        const float4 Cc = L.rec[js[u]].c;
+        const float wgt = a * T;
+        C0 += Cc.x * wgt;
+        C1 += Cc.y * wgt;
+        C2 += Cc.z * wgt;
+        T = Tn;
+        last = pos0 + js[u];
+        cnt++;
+      }
     }
   }
   if (inside) {
@@ -207,21 +221,56 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
   }
 }
 
-// Sum over the 64 lanes of a wavefront, left in lane 63 (DPP row and
-// row-broadcast steps, no LDS traffic).
+// ------------------------------------------------------------- reductions
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_move(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
 }
 
-__device__ __forceinline__ float wave_sum_to_last(float v) {
+// Sum over the 16 lanes of each row; every lane of the row gets the row total.
+__device__ __forceinline__ float row_sum(float v) {
   v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x124, 0xF>(v);  // row_ror:4
-  v += dpp_move<0x128, 0xF>(v);  // row_ror:8   -> every lane holds its row's sum
-  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the total
+  v += dpp_move<0x128, 0xF>(v);  // row_ror:8
   return v;
+}
+
+// a + b after swapping the upper half of a with the lower half of b: lanes
+// 0-31 get a[i] + a[i+32], lanes 32-63 get b[i-32] + b[i].
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(a), __float_as_int(b), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
+// a + b after swapping the odd rows of a with the even rows of b: rows 0, 1,
+// 2, 3 get a0 + a1, b0 + b1, a2 + a3, b2 + b3 (rows of 16 lanes).
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(a), __float_as_int(b), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
+// Sums nine per-lane values over the wavefront by halving exchanges -- each
+// exchange step halves two values at once -- then adds the totals into LDS
+// column j of s_g ([9][kBlock]): after the two swap stages and the row sums,
+// lanes 0/16/32/48 hold (g0, g2, g1, g3) in k0 and (g4, g6, g5, g7) in k1, and
+// lane 0 holds g8 in k2.
+__device__ __forceinline__ void wave_sum9_to_lds(const float (&g)[kG2D], float (*s_g)[kBlock], int j, int lane) {
+  const float h0 = swap32_add(g[0], g[1]);
+  const float h1 = swap32_add(g[2], g[3]);
+  const float h2 = swap32_add(g[4], g[5]);
+  const float h3 = swap32_add(g[6], g[7]);
+  const float h4 = swap32_add(g[8], g[8]);
+  const float k0 = row_sum(swap16_add(h0, h1));
+  const float k1 = row_sum(swap16_add(h2, h3));
+  const float k2 = row_sum(swap16_add(h4, h4));
+  if ((lane & 15) == 0) {
+    const int row = lane >> 4;
+    const int f0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+    atomicAdd(&s_g[f0][j], k0);
+    atomicAdd(&s_g[f0 + 4][j], k1);
+    if (row == 0) atomicAdd(&s_g[8][j], k2);
+  }
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
@@ -249,6 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
   const int py = ty * TileMap<TW>::TH + TileMap<TW>::by(wv) + (l >> 3);
   const bool inside = px < vd.W && py < vd.H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const uint32_t* list4 = reinterpret_cast<const uint32_t*>(L.list[wv]);
 
   float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
   uint32_t last = 0;
@@ -279,68 +329,64 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
     const uint32_t nb = bend - b0;
     const uint32_t wn = stage_batch<TW>(L, rec, pval, b0, nb, ox, oy);
     const uint32_t pos0 = b0 - rg.x;
-    for (int k = (int)wn - 1; k >= 0; k--) {
-      const uint32_t j = L.list[wv][k];
-      if (pos0 + j >= wlast) continue;  // no pixel of this wavefront reached it
-      const float4 A = L.rec[j].a;
-      const float4 B = L.rec[j].b;
-      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f, g8 = 0.f;
-      bool contrib = false;
-      if (pos0 + j < last) {
-        const float dx = fx - A.x, dy = fy - A.y;
-        const float p = log2_alpha(A, B, dx, dy);
-        if (p >= kLog2AlphaMin) {
-          contrib = true;
-          const float araw = exp2_fast(p);
-          const float a = fminf(kAlphaMax, araw);
-          const float4 Cc = L.rec[j].c;
-          const float ro = rcp_fast(1.0f - a);
-          const float Tb = T * ro;  // transmittance in front of this Gaussian
-          const float wgt = a * Tb;
-          g6 = dC0 * wgt;
-          g7 = dC1 * wgt;
-          g8 = dC2 * wgt;
-          const float dl_da = dC0 * (Cc.x * Tb - S0 * ro) + dC1 * (Cc.y * Tb - S1 * ro) + dC2 * (Cc.z * Tb - S2 * ro);
-          S0 += Cc.x * wgt;
-          S1 += Cc.y * wgt;
-          S2 += Cc.z * wgt;
-          T = Tb;
-          if (araw <= kAlphaMax) {
-            const float dl_dp = dl_da * araw;
-            g5 = dl_dp * B.z;  // d alpha / d alpha_cond = exp(-q/2) = araw / alpha_cond
-            const float dl_dp2 = dl_dp * kLn2;
-            g0 = -dl_dp2 * (2.f * A.z * dx + A.w * dy);
-            g1 = -dl_dp2 * (A.w * dx + 2.f * B.x * dy);
-            g2 = dl_dp2 * dx * dx;
-            g3 = dl_dp2 * dx * dy;
-            g4 = dl_dp2 * dy * dy;
+    for (int g4 = (int)((wn + 3) / 4) - 1; g4 >= 0; g4--) {
+      const uint32_t w4 = list4[g4];
+      uint32_t js[4];
+      float4 A[4], B[4], Cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        js[u] = (w4 >> (8 * u)) & 255u;
+        A[u] = L.rec[js[u]].a;
+        B[u] = L.rec[js[u]].b;
+        Cc[u] = L.rec[js[u]].c;
+      }
+#pragma unroll
+      for (int u = 3; u >= 0; u--) {
+        if ((uint32_t)(4 * g4 + u) >= wn) continue;
+        const uint32_t j = js[u];
+        const uint32_t pos = pos0 + j;
+        if (pos >= wlast) continue;  // no pixel of this wavefront reached it
+        float g[kG2D];
+#pragma unroll
+        for (int i = 0; i < kG2D; i++) g[i] = 0.f;
+        bool contrib = false;
+        if (pos < last) {
+          const float dx = fx - A[u].x, dy = fy - A[u].y;
+          const float p = log2_alpha(A[u], B[u], dx, dy);
+          if (p >= kLog2AlphaMin) {
+            contrib = true;
+            const float araw = exp2_fast(p);
+            const float a = fminf(kAlphaMax, araw);
+            const float ro = rcp_fast(1.0f - a);
+            const float Tb = T * ro;  // transmittance in front of this Gaussian
+            const float wgt = a * Tb;
+            g[6] = dC0 * wgt;
+            g[7] = dC1 * wgt;
+            g[8] = dC2 * wgt;
+            const float dl_da = dC0 * (Cc[u].x * Tb - S0 * ro) + dC1 * (Cc[u].y * Tb - S1 * ro) +
+                                dC2 * (Cc[u].z * Tb - S2 * ro);
+            S0 += Cc[u].x * wgt;
+            S1 += Cc[u].y * wgt;
+            S2 += Cc[u].z * wgt;
+            T = Tb;
+            if (araw <= kAlphaMax) {
+              const float dl_dp = dl_da * araw;
+              g[5] = dl_dp * B[u].z;  // d alpha / d alpha_cond = exp(-q/2) = araw / alpha_cond
+              const float dl_dp2 = dl_dp * kLn2;
+              g[0] = -dl_dp2 * (2.f * A[u].z * dx + A[u].w * dy);
+              g[1] = -dl_dp2 * (A[u].w * dx + 2.f * B[u].x * dy);
+              g[2] = dl_dp2 * dx * dx;
+              g[3] = dl_dp2 * dx * dy;
+              g[4] = dl_dp2 * dy * dy;
+            }
           }
         }
-      }
-      if (__ballot(contrib) == 0) continue;
-      g0 = wave_sum_to_last(g0);
-      g1 = wave_sum_to_last(g1);
-      g2 = wave_sum_to_last(g2);
-      g3 = wave_sum_to_last(g3);
-      g4 = wave_sum_to_last(g4);
-      g5 = wave_sum_to_last(g5);
-      g6 = wave_sum_to_last(g6);
-      g7 = wave_sum_to_last(g7);
-      g8 = wave_sum_to_last(g8);
-      if (l == 63) {
-        atomicAdd(&s_g[0][j], g0);
-        atomicAdd(&s_g[1][j], g1);
-        atomicAdd(&s_g[2][j], g2);
-        atomicAdd(&s_g[3][j], g3);
-        atomicAdd(&s_g[4][j], g4);
-        atomicAdd(&s_g[5][j], g5);
-        atomicAdd(&s_g[6][j], g6);
-        atomicAdd(&s_g[7][j], g7);
-        atomicAdd(&s_g[8][j], g8);
+        if (__ballot(contrib) == 0) continue;
+        wave_sum9_to_lds(g, s_g, (int)j, l);
       }
     }
     __syncthreads();
-    // one set of global atomics per (tile, Gaussian), conic gradient converted
+    // one set of global atomics per (tile, Gaussian); the conic gradient goes
     // from the pre-scaled coefficients back to the conic's full-matrix gradient
     if ((uint32_t)threadIdx.x < nb) {
       const int t = threadIdx.x;
