@@ -127,6 +127,17 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* ctx, const float* params, int64_t n, co
 sixdgs_status sixdgs_backward(sixdgs_ctx* ctx, const float* params, int64_t n, const float* const* dl_dimages,
                               float* grad, float* densify, void* stream);
 
+/* Backward of the last forward fused with one Adam step (the training-step
+ * form of sixdgs_backward followed by sixdgs_adam): the per-Gaussian gradient
+ * is applied to params, m and v (device [76][n] each, updated in place) as it
+ * is produced and never written to memory.  params must be the pointer the
+ * forward rendered (it is modified here, so the forward's saved state is spent:
+ * a further backward needs a new forward).  lr, beta1, beta2, eps and step as
+ * in sixdgs_adam; densify as in sixdgs_backward. */
+sixdgs_status sixdgs_backward_adam(sixdgs_ctx* ctx, float* params, int64_t n, const float* const* dl_dimages,
+                                   float* m, float* v, const float* lr, float beta1, float beta2, float eps,
+                                   int32_t step, float* densify, void* stream);
+
 /* L1 photometric loss over nimg (1..SIXDGS_MAX_VIEWS) image pairs:
  * loss = mean |I - I*| over every element of every image (written to the
  * device float `loss`), and dL/dI = sign(I - I*) / total_count written to

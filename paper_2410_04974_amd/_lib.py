@@ -64,6 +64,7 @@ def lib():
         L.sixdgs_last_error.restype = ctypes.c_char_p
         L.sixdgs_forward.argtypes = [P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
         L.sixdgs_backward.argtypes = [P, P, I64, PP, P, P, P]
+        L.sixdgs_backward_adam.argtypes = [P, P, I64, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
         L.sixdgs_bin.argtypes = [P, I64, ctypes.POINTER(Camera), I32, P, P, P, P, P, P, P]
@@ -71,7 +72,8 @@ def lib():
         L.sixdgs_check.argtypes = [P]
         L.sixdgs_set_timing.argtypes = [P, I32]
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
-        for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward", "sixdgs_l1_loss",
+        for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
+                     "sixdgs_backward_adam", "sixdgs_l1_loss",
                      "sixdgs_adam", "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing",
                      "sixdgs_kernel_time"):
             getattr(L, name).restype = I32
@@ -80,7 +82,8 @@ def lib():
 
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
-            "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_l1_loss", "sixdgs_adam",
+            "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
+            "sixdgs_adam",
             "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
 
 
@@ -190,6 +193,25 @@ class Context:
         dens = ctypes.c_void_p(densify.data_ptr()) if densify is not None else None
         self._rc(lib().sixdgs_backward(self._h, ctypes.c_void_p(params.data_ptr()), n, _ptrs(dl_dimages),
                                        ctypes.c_void_p(grad.data_ptr()), dens, ctypes.c_void_p(_stream(stream))))
+
+    def backward_adam(self, params, dl_dimages, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, densify=None,
+                      stream=None):
+        n = params.shape[1]
+        for t in dl_dimages:
+            _check_f32_cuda(t, "dl_dimage")
+        for t, nm in ((m, "m"), (v, "v")):
+            _check_f32_cuda(t, nm)
+            if t.shape != params.shape:
+                raise ValueError(f"{nm} must have the shape of params")
+        if densify is not None:
+            _check_f32_cuda(densify, "densify")
+            if densify.numel() != 2 * n:
+                raise ValueError("densify must hold [2, N] floats")
+        lrs = (ctypes.c_float * 6)(*[float(x) for x in lr])
+        dens = ctypes.c_void_p(densify.data_ptr()) if densify is not None else None
+        self._rc(lib().sixdgs_backward_adam(self._h, ctypes.c_void_p(params.data_ptr()), n, _ptrs(dl_dimages),
+                                            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), lrs,
+                                            beta1, beta2, eps, int(step), dens, ctypes.c_void_p(_stream(stream))))
 
     def l1_loss(self, images, targets, dl_dimages, loss, stream=None):
         for a, b, g in zip(images, targets, dl_dimages):

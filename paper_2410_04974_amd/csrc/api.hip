@@ -456,6 +456,43 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, con
   return check_launch(c, "preprocess backward");
 }
 
+sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, const float* const* dl_dimages,
+                                   float* m, float* v, const float* lr, float beta1, float beta2, float eps,
+                                   int32_t step, float* densify, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
+  if (params != c->fwd_params || n != c->fwd_n)
+    return fail(c, SIXDGS_ERR_STATE, "params / n differ from the last forward");
+  if (!dl_dimages || !lr) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  if (n > 0 && (!m || !v)) return fail(c, SIXDGS_ERR_INVALID_ARG, "m or v is NULL");
+  if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+    return fail(c, SIXDGS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  ViewTable vt = c->vt;
+  for (int k = 0; k < vt.nview; k++) {
+    if (!dl_dimages[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "a dL/dI pointer is NULL");
+    vt.v[k].dimg = dl_dimages[k];
+  }
+  if (n == 0) return SIXDGS_OK;
+  if (!c->g2d.ensure(c->fwd_E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
+  const DevSettings ds = dev_settings(c->s);
+  launch_zero_g2d(c->sb, c->g2d.p, st);
+  BlendState bs{c->T_final.p, c->last.p, nullptr};
+  {
+    Timer t(c, SIXDGS_K_BLEND_BWD, st);
+    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch, st);
+  }
+  sixdgs_status rc = check_launch(c, "blend backward");
+  if (rc != SIXDGS_OK) return rc;
+  const AdamArgs a = make_adam_args(lr, beta1, beta2, eps, step);
+  {
+    Timer t(c, SIXDGS_K_PREPROCESS_BWD, st);
+    launch_preprocess_bwd_adam(params, n, vt, ds, c->tiles.p, c->g2d.p, m, v, a, densify, st);
+  }
+  c->have_fwd = false;  // the parameters moved
+  return check_launch(c, "preprocess backward + Adam");
+}
+
 sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images, const float* const* targets,
                              const int64_t* numel, float* const* dl_dimages, float* loss, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;

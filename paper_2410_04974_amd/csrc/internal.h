@@ -83,12 +83,36 @@ __device__ __forceinline__ void tile_rect(float u, float v, float ex, float ey, 
   y1 = min(max(y1, 0), nty);
 }
 
+// One Adam step's constants (bias corrections folded in by the host).
+struct AdamArgs {
+  float lr[6];  // row groups: mu_p, mu_d, Cholesky, SH degree 0, SH degrees 1-3, opacity
+  float b1, b2, eps, bc1, bc2;
+};
+AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int step);
+
+__device__ __forceinline__ int adam_row_group(int r) {
+  return r < 3 ? 0 : r < 6 ? 1 : r < 27 ? 2 : r < 30 ? 3 : r < 75 ? 4 : 5;
+}
+
+// Bias-corrected Adam update of one parameter.
+__device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float lr, const AdamArgs& a) {
+  m = a.b1 * m + (1.f - a.b1) * g;
+  v = a.b2 * v + (1.f - a.b2) * g * g;
+  const float mh = m / a.bc1;
+  const float vh = v / a.bc2;
+  p -= lr * mh / (sqrtf(vh) + a.eps);
+}
+
 // ----------------------------------------------------------- host launchers
 // preprocess.hip
 void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
                        uint32_t* tiles, hipStream_t st);
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st);
+// The same chain rule with an Adam step applied to params/m/v in place of writing the gradient.
+void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
+                                const uint32_t* tiles, const float* g2d, float* m, float* v, const AdamArgs& a,
+                                float* densify, hipStream_t st);
 
 // sort.hip -- the integer stage
 struct SortBuffers {

@@ -256,16 +256,40 @@ __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__
 }
 
 // ------------------------------------------------------------------ backward
-__global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* __restrict__ params, int64_t n, ViewTable vt,
+// Where the per-parameter gradient goes: to a gradient buffer, or straight into
+// an Adam step on the parameters (the gradient then never reaches memory).
+struct GradToBuffer {
+  float* grad;
+  __device__ void put(int row, int64_t n, int64_t g, float v) const { grad[row * n + g] = v; }
+};
+struct GradToAdam {
+  float* p;
+  float* m;
+  float* v;
+  AdamArgs a;
+  __device__ void put(int row, int64_t n, int64_t g, float gv) const {
+    const int64_t k = row * n + g;
+    float pp = p[k], mm = m[k], vv = v[k];
+    adam_update(pp, gv, mm, vv, a.lr[adam_row_group(row)], a);
+    p[k] = pp;
+    m[k] = mm;
+    v[k] = vv;
+  }
+};
+
+// params is read before the sink writes (the Adam sink writes the same rows),
+// so it is not declared __restrict__.
+template <class Sink>
+__global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, int64_t n, ViewTable vt,
                                                            DevSettings ds, const uint32_t* __restrict__ tiles,
-                                                           const float* __restrict__ g2d, float* __restrict__ grad,
+                                                           const float* __restrict__ g2d, Sink sink,
                                                            float* __restrict__ densify) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= n) return;
   bool any = false;
   for (int vi = 0; vi < vt.nview; vi++) any |= tiles[(int64_t)vi * n + g] > 0;
   if (!any) {
-    for (int r = 0; r < kRows; r++) grad[r * n + g] = 0.f;
+    for (int r = 0; r < kRows; r++) sink.put(r, n, g, 0.f);
     return;
   }
   Static s;
@@ -448,18 +472,18 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* __restri
       const float Lij = s.L[tri(i, j)];
       // exp on the diagonal; 2 sigmoid(r) - 1 elsewhere, whose derivative is (1 - L)(1 + L)/2
       const float graw = (i == j) ? gl * Lij : gl * 0.5f * (1.f - Lij) * (1.f + Lij);
-      grad[(kRowL + tri(i, j)) * n + g] = graw;
+      sink.put(kRowL + tri(i, j), n, g, graw);
     }
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    grad[(kRowMuP + k) * n + g] = g_mup[k];
-    grad[(kRowMuD + k) * n + g] = g_mud[k];
+    sink.put(kRowMuP + k, n, g, g_mup[k]);
+    sink.put(kRowMuD + k, n, g, g_mud[k]);
   }
 #pragma unroll
   for (int k = 0; k < 16; k++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) grad[(kRowSH + 3 * k + c) * n + g] = g_beta[k][c];
-  grad[kRowOpa * n + g] = g_alpha * s.alpha * (1.f - s.alpha);
+    for (int c = 0; c < 3; c++) sink.put(kRowSH + 3 * k + c, n, g, g_beta[k][c]);
+  sink.put(kRowOpa, n, g, g_alpha * s.alpha * (1.f - s.alpha));
   if (densify) {
     densify[g] += dens_norm;
     densify[n + g] += dens_cnt;
@@ -479,8 +503,17 @@ void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, 
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess_bwd, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, grad,
-                     densify);
+  hipLaunchKernelGGL(k_preprocess_bwd<GradToBuffer>, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d,
+                     GradToBuffer{grad}, densify);
+}
+
+void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
+                                const uint32_t* tiles, const float* g2d, float* m, float* v, const AdamArgs& a,
+                                float* densify, hipStream_t st) {
+  if (n <= 0) return;
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_preprocess_bwd<GradToAdam>, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d,
+                     GradToAdam{params, m, v, a}, densify);
 }
 
 }  // namespace sixdgs

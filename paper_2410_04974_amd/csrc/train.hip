@@ -50,37 +50,21 @@ int l1_blocks(int64_t numel) {
   return (int)(b < kL1MaxBlocks ? b : kL1MaxBlocks);
 }
 
-struct AdamArgs {
-  float lr[6];
-  float b1, b2, eps, bc1, bc2;
-};
-
-__device__ __forceinline__ int row_group(int r) {
-  return r < 3 ? 0 : r < 6 ? 1 : r < 27 ? 2 : r < 30 ? 3 : r < 75 ? 4 : 5;
-}
-
-__device__ __forceinline__ void adam1(float& p, float g, float& m, float& v, float lr, const AdamArgs& a) {
-  m = a.b1 * m + (1.f - a.b1) * g;
-  v = a.b2 * v + (1.f - a.b2) * g * g;
-  const float mh = m / a.bc1;
-  const float vh = v / a.bc2;
-  p -= lr * mh / (sqrtf(vh) + a.eps);
-}
 
 // grid.y = parameter row, grid.x covers the row (float4 when n % 4 == 0)
 __global__ void __launch_bounds__(kBlock) k_adam4(float4* __restrict__ p, const float4* __restrict__ g,
                                                   float4* __restrict__ m, float4* __restrict__ v, int64_t n4,
                                                   AdamArgs a) {
   const int r = blockIdx.y;
-  const float lr = a.lr[row_group(r)];
+  const float lr = a.lr[adam_row_group(r)];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n4) return;
   const int64_t k = (int64_t)r * n4 + i;
   float4 pp = p[k], gg = g[k], mm = m[k], vv = v[k];
-  adam1(pp.x, gg.x, mm.x, vv.x, lr, a);
-  adam1(pp.y, gg.y, mm.y, vv.y, lr, a);
-  adam1(pp.z, gg.z, mm.z, vv.z, lr, a);
-  adam1(pp.w, gg.w, mm.w, vv.w, lr, a);
+  adam_update(pp.x, gg.x, mm.x, vv.x, lr, a);
+  adam_update(pp.y, gg.y, mm.y, vv.y, lr, a);
+  adam_update(pp.z, gg.z, mm.z, vv.z, lr, a);
+  adam_update(pp.w, gg.w, mm.w, vv.w, lr, a);
   p[k] = pp;
   m[k] = mm;
   v[k] = vv;
@@ -89,12 +73,12 @@ __global__ void __launch_bounds__(kBlock) k_adam4(float4* __restrict__ p, const 
 __global__ void __launch_bounds__(kBlock) k_adam1(float* __restrict__ p, const float* __restrict__ g,
                                                   float* __restrict__ m, float* __restrict__ v, int64_t n, AdamArgs a) {
   const int r = blockIdx.y;
-  const float lr = a.lr[row_group(r)];
+  const float lr = a.lr[adam_row_group(r)];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int64_t k = (int64_t)r * n + i;
   float pp = p[k], mm = m[k], vv = v[k];
-  adam1(pp, g[k], mm, vv, lr, a);
+  adam_update(pp, g[k], mm, vv, lr, a);
   p[k] = pp;
   m[k] = mm;
   v[k] = vv;
@@ -123,9 +107,7 @@ void launch_l1(int nimg, const float* const* img, const float* const* tgt, const
   hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, off, inv, loss);
 }
 
-void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
-                 float eps, int step, hipStream_t st) {
-  if (n <= 0) return;
+AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int step) {
   AdamArgs a;
   for (int k = 0; k < 6; k++) a.lr[k] = lr[k];
   a.b1 = b1;
@@ -133,6 +115,13 @@ void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const 
   a.eps = eps;
   a.bc1 = (float)(1.0 - __builtin_pow((double)b1, (double)step));
   a.bc2 = (float)(1.0 - __builtin_pow((double)b2, (double)step));
+  return a;
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
+                 float eps, int step, hipStream_t st) {
+  if (n <= 0) return;
+  const AdamArgs a = make_adam_args(lr, b1, b2, eps, step);
   const bool vec = (n % 4 == 0) && ((uintptr_t)p % 16 == 0) && ((uintptr_t)g % 16 == 0) &&
                    ((uintptr_t)m % 16 == 0) && ((uintptr_t)v % 16 == 0);
   if (vec) {

@@ -89,14 +89,23 @@ class Trainer:
         self._imgs = None
         self._dl = None
 
-    def step(self, cams, targets, densify=None):
+    def step(self, cams, targets, densify=None, fused=False):
+        """Render, L1 loss, backward, Adam.  fused=True applies Adam inside the
+        preprocess backward (the gradient never reaches memory, but the in-place
+        per-row updates serialise on load latency: slower on MI355X today);
+        fused=False writes the gradient to self.grad and runs the streaming Adam
+        kernel."""
         if self._imgs is None or [tuple(i.shape) for i in self._imgs] != [(3, c.height, c.width) for c in cams]:
             self._imgs = [torch.empty((3, c.height, c.width), device=self.params.device) for c in cams]
             self._dl = [torch.empty_like(i) for i in self._imgs]
         self.renderer.forward(self.params, cams, out=self._imgs)
         self.renderer.ctx.l1_loss(self._imgs, targets, self._dl, self.loss)
-        self.renderer.backward(self.params, self._dl, grad=self.grad, densify=densify)
         self.step_count += 1
-        _lib.adam(self.params, self.grad, self.m, self.v, self.lr, self.step_count, self.betas[0], self.betas[1],
-                  self.eps)
+        if fused:
+            self.renderer.ctx.backward_adam(self.params, self._dl, self.m, self.v, self.lr, self.step_count,
+                                            self.betas[0], self.betas[1], self.eps, densify=densify)
+        else:
+            self.renderer.backward(self.params, self._dl, grad=self.grad, densify=densify)
+            _lib.adam(self.params, self.grad, self.m, self.v, self.lr, self.step_count, self.betas[0],
+                      self.betas[1], self.eps)
         return self.loss
