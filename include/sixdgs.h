@@ -153,6 +153,14 @@ sixdgs_status sixdgs_l1_loss(sixdgs_ctx* ctx, int32_t nimg, const float* const* 
 sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
                           float beta1, float beta2, float eps, int32_t step, void* stream);
 
+/* sixdgs_adam with the step count kept on the device: step_counter (device
+ * int32, 0 before the first step) holds the number of steps taken; this call
+ * takes step *step_counter + 1 and then increments the counter, all on the
+ * stream.  Nothing about the step is baked into the launch, so a captured
+ * graph of a training step advances Adam on every replay. */
+sixdgs_status sixdgs_adam_devstep(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
+                                  float beta1, float beta2, float eps, int32_t* step_counter, void* stream);
+
 /* The integer stage alone, on caller-given projected records: bins entries
  * e = view*n + i (arrays of length n*ncam, device) with extents (u +- ex,
  * v +- ey) into the cameras' tile grids, keyed by (tile, float32 depth bits,

@@ -67,6 +67,7 @@ def lib():
         L.sixdgs_backward_adam.argtypes = [P, P, I64, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
+        L.sixdgs_adam_devstep.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, P, P]
         L.sixdgs_bin.argtypes = [P, I64, ctypes.POINTER(Camera), I32, P, P, P, P, P, P, P]
         L.sixdgs_export.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
         L.sixdgs_check.argtypes = [P]
@@ -74,7 +75,8 @@ def lib():
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
                      "sixdgs_backward_adam", "sixdgs_l1_loss",
-                     "sixdgs_adam", "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing",
+                     "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check",
+                     "sixdgs_set_timing",
                      "sixdgs_kernel_time"):
             getattr(L, name).restype = I32
         _lib = L
@@ -83,8 +85,7 @@ def lib():
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
             "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
-            "sixdgs_adam",
-            "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
+            "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
 
 
 def default_settings(**kw) -> Settings:
@@ -272,6 +273,24 @@ class Context:
         n = ctypes.c_int64()
         self._rc(lib().sixdgs_kernel_time(self._h, kernel, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def adam_devstep(params, grad, m, v, lr, step_counter, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """Adam with the step count in a device int32 tensor (capturable in a graph)."""
+    import torch
+    for t, nm in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _check_f32_cuda(t, nm)
+        if t.shape != params.shape:
+            raise ValueError("params, grad, m and v must share one shape")
+    if not (step_counter.is_cuda and step_counter.dtype == torch.int32 and step_counter.numel() == 1):
+        raise ValueError("step_counter must be a one-element int32 CUDA tensor")
+    lrs = (ctypes.c_float * 6)(*[float(x) for x in lr])
+    rc = lib().sixdgs_adam_devstep(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                   ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), params.shape[1],
+                                   lrs, beta1, beta2, eps, ctypes.c_void_p(step_counter.data_ptr()),
+                                   ctypes.c_void_p(_stream(stream)))
+    if rc != OK:
+        raise SixDGSError(rc, "adam failed (bad arguments)")
 
 
 def adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

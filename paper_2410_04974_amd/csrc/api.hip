@@ -512,7 +512,15 @@ sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, 
                           float beta1, float beta2, float eps, int32_t step, void* stream) {
   if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || !lr || step < 1) return SIXDGS_ERR_INVALID_ARG;
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return SIXDGS_ERR_INVALID_ARG;
-  launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, nullptr, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_adam_devstep(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
+                                  float beta1, float beta2, float eps, int32_t* step_counter, void* stream) {
+  if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || !lr || !step_counter) return SIXDGS_ERR_INVALID_ARG;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return SIXDGS_ERR_INVALID_ARG;
+  launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, 1, step_counter, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
 }
 

@@ -166,6 +166,6 @@ void launch_l1(int nimg, const float* const* img, const float* const* tgt, const
                float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
 int64_t l1_partial_count(int nimg, const int64_t* numel);
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
-                 float eps, int step, hipStream_t st);
+                 float eps, int step, int32_t* step_dev, hipStream_t st);
 
 }  // namespace sixdgs

@@ -51,10 +51,24 @@ int l1_blocks(int64_t numel) {
 }
 
 
+// With a device step counter the bias corrections are formed on the device
+// from the step about to be taken (*step + 1), so a captured graph advances
+// the step on every replay; k_step_inc then moves the counter on.
+__device__ __forceinline__ void device_bias(AdamArgs& a, const int32_t* step_dev) {
+  if (step_dev) {
+    const float t = (float)(*step_dev + 1);
+    a.bc1 = 1.0f - powf(a.b1, t);
+    a.bc2 = 1.0f - powf(a.b2, t);
+  }
+}
+
+__global__ void k_step_inc(int32_t* step_dev) { *step_dev += 1; }
+
 // grid.y = parameter row, grid.x covers the row (float4 when n % 4 == 0)
 __global__ void __launch_bounds__(kBlock) k_adam4(float4* __restrict__ p, const float4* __restrict__ g,
                                                   float4* __restrict__ m, float4* __restrict__ v, int64_t n4,
-                                                  AdamArgs a) {
+                                                  AdamArgs a, const int32_t* step_dev) {
+  device_bias(a, step_dev);
   const int r = blockIdx.y;
   const float lr = a.lr[adam_row_group(r)];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -71,7 +85,9 @@ __global__ void __launch_bounds__(kBlock) k_adam4(float4* __restrict__ p, const 
 }
 
 __global__ void __launch_bounds__(kBlock) k_adam1(float* __restrict__ p, const float* __restrict__ g,
-                                                  float* __restrict__ m, float* __restrict__ v, int64_t n, AdamArgs a) {
+                                                  float* __restrict__ m, float* __restrict__ v, int64_t n, AdamArgs a,
+                                                  const int32_t* step_dev) {
+  device_bias(a, step_dev);
   const int r = blockIdx.y;
   const float lr = a.lr[adam_row_group(r)];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -119,19 +135,21 @@ AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int st
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
-                 float eps, int step, hipStream_t st) {
+                 float eps, int step, int32_t* step_dev, hipStream_t st) {
   if (n <= 0) return;
-  const AdamArgs a = make_adam_args(lr, b1, b2, eps, step);
+  const AdamArgs a = make_adam_args(lr, b1, b2, eps, step_dev ? 1 : step);
   const bool vec = (n % 4 == 0) && ((uintptr_t)p % 16 == 0) && ((uintptr_t)g % 16 == 0) &&
                    ((uintptr_t)m % 16 == 0) && ((uintptr_t)v % 16 == 0);
   if (vec) {
     const int64_t n4 = n / 4;
     const dim3 grid((unsigned)((n4 + kBlock - 1) / kBlock), kRows);
-    hipLaunchKernelGGL(k_adam4, grid, dim3(kBlock), 0, st, (float4*)p, (const float4*)g, (float4*)m, (float4*)v, n4, a);
+    hipLaunchKernelGGL(k_adam4, grid, dim3(kBlock), 0, st, (float4*)p, (const float4*)g, (float4*)m, (float4*)v, n4, a,
+                       (const int32_t*)step_dev);
   } else {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock), kRows);
-    hipLaunchKernelGGL(k_adam1, grid, dim3(kBlock), 0, st, p, g, m, v, n, a);
+    hipLaunchKernelGGL(k_adam1, grid, dim3(kBlock), 0, st, p, g, m, v, n, a, (const int32_t*)step_dev);
   }
+  if (step_dev) hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step_dev);
 }
 
 }  // namespace sixdgs

@@ -85,9 +85,12 @@ class Trainer:
         self.betas = betas
         self.eps = eps
         self.step_count = 0
+        # Adam's step count lives on the device so a captured step advances it on every replay
+        self.step_counter = torch.zeros(1, device=params.device, dtype=torch.int32)
         self.loss = torch.zeros(1, device=params.device, dtype=torch.float32)
         self._imgs = None
         self._dl = None
+        self.graph = None
 
     def step(self, cams, targets, densify=None, fused=False):
         """Render, L1 loss, backward, Adam.  fused=True applies Adam inside the
@@ -104,8 +107,64 @@ class Trainer:
         if fused:
             self.renderer.ctx.backward_adam(self.params, self._dl, self.m, self.v, self.lr, self.step_count,
                                             self.betas[0], self.betas[1], self.eps, densify=densify)
+            self.step_counter += 1
         else:
             self.renderer.backward(self.params, self._dl, grad=self.grad, densify=densify)
-            _lib.adam(self.params, self.grad, self.m, self.v, self.lr, self.step_count, self.betas[0],
-                      self.betas[1], self.eps)
+            _lib.adam_devstep(self.params, self.grad, self.m, self.v, self.lr, self.step_counter, self.betas[0],
+                              self.betas[1], self.eps)
         return self.loss
+
+    def capture(self, cams, targets, densify=None, warmup=2):
+        """Capture one training step (render, L1, backward, Adam) as a graph;
+        ``replay()`` then runs a step with one launch.  Needs a fixed pair
+        capacity on the renderer (no host waits inside a step)."""
+        if self.renderer.ctx.settings.pair_capacity <= 0:
+            raise RuntimeError("graph capture needs Renderer(pair_capacity=...) > 0")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.step(cams, targets, densify=densify)
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.step(cams, targets, densify=densify)
+        self.step_count -= 1  # capturing did not run a step
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+        self.step_count += 1
+        return self.loss
+
+    # -- checkpoint / resume ----------------------------------------------------
+    def save(self, path, extra=None):
+        """Writes params, Adam moments, the step count and any extra tensors
+        (e.g. densification statistics) to an .npz file."""
+        import numpy as np
+        torch.cuda.synchronize()
+        arrays = {"params": self.params.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
+                  "step_count": np.array(self.step_count, np.int64),
+                  "step_counter": self.step_counter.cpu().numpy()}
+        for k, t in (extra or {}).items():
+            arrays["extra_" + k] = t.cpu().numpy()
+        np.savez(path, **arrays)
+
+    def load(self, path):
+        """Restores a checkpoint written by save(); returns its extra tensors on the device."""
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            dev = self.params.device
+            if tuple(z["params"].shape) != tuple(self.params.shape):
+                self.params = torch.empty(tuple(z["params"].shape), device=dev, dtype=torch.float32)
+                self.m = torch.empty_like(self.params)
+                self.v = torch.empty_like(self.params)
+                self.grad = torch.empty_like(self.params)
+            self.params.copy_(torch.from_numpy(z["params"]))
+            self.m.copy_(torch.from_numpy(z["m"]))
+            self.v.copy_(torch.from_numpy(z["v"]))
+            self.step_count = int(z["step_count"])
+            self.step_counter.copy_(torch.from_numpy(z["step_counter"]))
+            extra = {k[len("extra_"):]: torch.from_numpy(z[k]).to(dev) for k in z.files if k.startswith("extra_")}
+        self.graph = None
+        return extra
