@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=8192)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2: the training-step benchmark (default); c3: 16 uneven views batched in one "
+                         "captured forward+backward vs 16 per-view launches; c4: 8-view training steps "
+                         "from a 64-camera 1920x1080 pool, one captured graph per camera group")
     return ap.parse_args()
 
 
@@ -61,6 +65,11 @@ def main():
         print("bench.py measures one GPU only: this renderer has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
 
     import numpy as np
     import torch
@@ -175,6 +184,140 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
     achieved = bytes_ / (avg_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic(name), "avg_ms": round(avg_ms, 4)}
+
+
+def _timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_c3(args):
+    """16 uneven cameras: one captured forward+backward over all views (tile
+    shape and LDS batch depth autotuned) against 16 per-view eager calls."""
+    import torch
+
+    import synth
+    from paper_2410_04974_amd import Renderer
+    from paper_2410_04974_amd.autotune import autotune
+
+    w = synth.workload("c3")
+    cams = w.cameras
+    params = torch.from_numpy(synth.make_scene(w.scene)).to("cuda:0")
+    px = sum(c.width * c.height for c in cams)
+    tune = autotune(params, cams, use_cache=False)
+    gen = torch.Generator(device="cuda:0").manual_seed(2)
+    dls = [torch.randn((3, c.height, c.width), device="cuda:0", generator=gen) for c in cams]
+
+    rb = Renderer(tile=tune["tile"], batch=tune["batch"])
+    imgs = rb.forward(params, cams)
+    torch.cuda.synchronize()
+    pairs = rb.ctx.sizes()["pairs"]
+    rb.configure(pair_capacity=int(pairs * 1.3) + 4096)
+    grad = torch.empty_like(params)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            rb.forward(params, cams, out=imgs)
+            rb.backward(params, dls, grad=grad)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rb.forward(params, cams, out=imgs)
+        rb.backward(params, dls, grad=grad)
+    for _ in range(args.warmup):
+        g.replay()
+    ms_batched = _timed(g.replay, args.steps)
+    rb.ctx.check()
+
+    per = [Renderer(tile=tune["tile"], batch=tune["batch"]) for _ in cams]
+    gsum = torch.empty_like(params)
+
+    def per_view():
+        for r1, c, d in zip(per, cams, dls):
+            r1.forward(params, [c])
+            r1.backward(params, [d], grad=gsum)
+
+    per_view()
+    equal = all(torch.equal(per[k].forward(params, [c])[0], imgs[k]) for k, c in enumerate(cams))
+    for _ in range(max(1, args.warmup // 2)):
+        per_view()
+    ms_per_view = _timed(per_view, max(1, args.steps // 4))
+    out = {"metric": "fwd+bwd Mpixels/sec, 16 uneven views batched in one captured graph", "workload": "c3",
+           "value": round(px / (ms_batched * 1e-3) / 1e6, 3), "unit": "Mpixels/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batched, 4), "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "c3: 500k 6D Gaussians on a noisy sphere, 16 Fibonacci cameras cycling "
+                                  "400x400, 800x800, 1280x720, 1600x900", "pixels": px, "pairs": pairs,
+                      "tile": list(tune["tile"]), "batch": tune["batch"]},
+           "per_view_launches": {"ms_per_step": round(ms_per_view, 4),
+                                 "value": round(px / (ms_per_view * 1e-3) / 1e6, 3)},
+           "speedup_vs_per_view": round(ms_per_view / ms_batched, 3),
+           "images_bitwise_equal": bool(equal), "autotune_ms": {k: round(v, 3) for k, v in tune["timings"].items()}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_c4(args):
+    """8-view training steps over a 64-camera 1920x1080 pool with Adam and
+    densification statistics; one captured graph per camera group."""
+    import torch
+
+    import synth
+    from paper_2410_04974_amd import Renderer, Trainer
+
+    w = synth.workload("c4")
+    pool = w.cameras
+    pn = synth.make_scene(w.scene)
+    tr_r = Renderer()
+    pert = torch.from_numpy(synth.perturbed(pn)).to("cuda:0")
+    targets = []
+    for c in pool:
+        targets.append(tr_r.forward(pert, [c])[0])
+    del tr_r
+    params = torch.from_numpy(pn).to("cuda:0")
+    r = Renderer()
+    tr = Trainer(params, r)
+    dens = torch.zeros((2, pn.shape[1]), device="cuda:0")
+    groups = len(pool) // 8
+    # size the fixed pair capacity from one eager pass over every group
+    pmax = 0
+    for gi in range(groups):
+        vs = synth.c4_step_views(gi)
+        tr.step([pool[i] for i in vs], [targets[i] for i in vs], densify=dens)
+        torch.cuda.synchronize()
+        pmax = max(pmax, r.ctx.sizes()["pairs"])
+    r.configure(pair_capacity=int(pmax * 1.3) + 4096)
+    for gi in range(groups):
+        vs = synth.c4_step_views(gi)
+        tr.capture([pool[i] for i in vs], [targets[i] for i in vs], densify=dens, warmup=1, key=gi)
+    torch.cuda.synchronize()
+    steps = args.steps
+    step = [0]
+
+    def one():
+        tr.replay(step[0] % groups)
+        step[0] += 1
+
+    ms = _timed(one, steps)
+    r.ctx.check()
+    px = sum(pool[i].width * pool[i].height for i in synth.c4_step_views(0))
+    out = {"metric": "train steps/sec, 8 views per step at 1M 6D Gaussians 1920x1080", "workload": "c4",
+           "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": groups,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "mpixels_per_s": round(px / (ms * 1e-3) / 1e6, 3),
+           "config": {"workload": "c4: 1M 6D Gaussians (70% sphere, 30% cube), 64-camera 1920x1080 pool, "
+                                  "8 views per step, L1 + Adam + densification statistics",
+                      "pairs_max": pmax},
+           "final_loss": float(tr.loss), "densify_visible_max": float(dens[1].max())}
+    print(json.dumps(out), flush=True)
 
 
 def Renderer_with_counts(r):

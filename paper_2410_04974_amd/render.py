@@ -90,7 +90,7 @@ class Trainer:
         self.loss = torch.zeros(1, device=params.device, dtype=torch.float32)
         self._imgs = None
         self._dl = None
-        self.graph = None
+        self.graphs = {}
 
     def step(self, cams, targets, densify=None, fused=False):
         """Render, L1 loss, backward, Adam.  fused=True applies Adam inside the
@@ -114,10 +114,12 @@ class Trainer:
                               self.betas[1], self.eps)
         return self.loss
 
-    def capture(self, cams, targets, densify=None, warmup=2):
-        """Capture one training step (render, L1, backward, Adam) as a graph;
-        ``replay()`` then runs a step with one launch.  Needs a fixed pair
-        capacity on the renderer (no host waits inside a step)."""
+    def capture(self, cams, targets, densify=None, warmup=2, key=0):
+        """Capture one training step (render, L1, backward, Adam) for these
+        cameras as a graph; ``replay(key)`` then runs a step with one launch.
+        Several camera sets can be captured under different keys (the camera
+        table is part of each capture).  Needs a fixed pair capacity on the
+        renderer (no host waits inside a step); warm-up steps are real steps."""
         if self.renderer.ctx.settings.pair_capacity <= 0:
             raise RuntimeError("graph capture needs Renderer(pair_capacity=...) > 0")
         s = torch.cuda.Stream()
@@ -126,14 +128,15 @@ class Trainer:
             for _ in range(warmup):
                 self.step(cams, targets, densify=densify)
         torch.cuda.current_stream().wait_stream(s)
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
             self.step(cams, targets, densify=densify)
         self.step_count -= 1  # capturing did not run a step
-        return self.graph
+        self.graphs[key] = g
+        return g
 
-    def replay(self):
-        self.graph.replay()
+    def replay(self, key=0):
+        self.graphs[key].replay()
         self.step_count += 1
         return self.loss
 
@@ -166,5 +169,5 @@ class Trainer:
             self.step_count = int(z["step_count"])
             self.step_counter.copy_(torch.from_numpy(z["step_counter"]))
             extra = {k[len("extra_"):]: torch.from_numpy(z[k]).to(dev) for k in z.files if k.startswith("extra_")}
-        self.graph = None
+        self.graphs = {}
         return extra
