@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=8192)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB once (a kernel of known traffic that "
+                         "scales the HBM byte counters of a profiler run)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
                     help="c2: the training-step benchmark (default); c3: 16 uneven views batched in one "
                          "captured forward+backward vs 16 per-view launches; c4: 8-view training steps "
@@ -156,6 +159,13 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params_np, cam, args.cpu_pixels)
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib << 18, device=dev, dtype=torch.float32).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = a.numel() * 4
     print(json.dumps(out), flush=True)
 
 
