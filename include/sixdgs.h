@@ -80,7 +80,8 @@ typedef struct {
                             (sixdgs_forward then waits once on the stream to
                             read the pair count); > 0: fixed capacity, no host
                             waits (capturable), overflow reported as
-                            SIXDGS_ERR_CAPACITY by sixdgs_check(). */
+                            SIXDGS_ERR_CAPACITY by sixdgs_check().  At most
+                            2^30 - 1 pairs either way (CAPACITY beyond). */
   int32_t flags;       /* SIXDGS_FLAG_* */
 } sixdgs_settings;
 
@@ -110,7 +111,7 @@ const char* sixdgs_last_error(const sixdgs_ctx* ctx);
  *           backward has run.
  *   cams    host array of ncam cameras.
  *   images  host array of ncam device pointers, each [3][H][W], overwritten.
- * Keeps, inside ctx, the per-view projected records, the sorted (tile,
+ * n * ncam must stay below 2^30 (INVALID_ARG otherwise).  Keeps, inside ctx, the per-view projected records, the sorted (tile,
  * Gaussian) lists and the per-pixel final transmittance and last-contributor
  * index that the backward consumes; they stay valid until the next forward or
  * sixdgs_bin on this context. */
@@ -198,7 +199,9 @@ sixdgs_status sixdgs_bin(sixdgs_ctx* ctx, int64_t n, const sixdgs_camera* cams, 
 sixdgs_status sixdgs_export(sixdgs_ctx* ctx, int32_t what, void* dst, int64_t cap_bytes, int64_t* written);
 
 /* Waits for the context's last stream and reports a capacity overflow of the
- * fixed-capacity mode (SIXDGS_ERR_CAPACITY, then the flag is cleared). */
+ * fixed-capacity mode (SIXDGS_ERR_CAPACITY), or a sort pass whose bounded
+ * wait on an earlier workgroup ran out (SIXDGS_ERR_HIP); the flag is then
+ * cleared. */
 sixdgs_status sixdgs_check(sixdgs_ctx* ctx);
 
 /* Kernel timing with HIP events recorded on the launch stream around the

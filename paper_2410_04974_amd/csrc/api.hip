@@ -61,7 +61,7 @@ struct sixdgs_ctx {
   // backward and loss
   DevBuf<float> g2d, l1_partial;
   // scratch
-  DevBuf<uint32_t> scan_blocks, hist, counters;
+  DevBuf<uint32_t> rstate, blk_start, counters;
   uint32_t* host_counters = nullptr;  // pinned
   // state of the last forward
   bool have_fwd = false;
@@ -88,6 +88,9 @@ sixdgs_status fail(sixdgs_ctx* c, sixdgs_status st, const std::string& msg) {
   return st;
 }
 
+// Bound on entries and pairs: the radix sort's look-back words hold 30-bit counts.
+constexpr int64_t kMaxItems = (1ll << 30) - 1;
+
 bool valid_settings(const sixdgs_settings* s, std::string& why) {
   if (!(s->lambda_opa >= 0.f && s->lambda_opa <= 1.f)) { why = "lambda_opa must lie in [0, 1]"; return false; }
   if (!(s->z_near > 0.f) || !std::isfinite(s->z_near)) { why = "z_near must be positive"; return false; }
@@ -102,7 +105,7 @@ bool valid_settings(const sixdgs_settings* s, std::string& why) {
     why = "batch must be 64, 128 or 256";
     return false;
   }
-  if (s->pair_capacity < 0 || s->pair_capacity > 0xFFFFFFF0ll) { why = "pair_capacity out of range"; return false; }
+  if (s->pair_capacity < 0 || s->pair_capacity > kMaxItems) { why = "pair_capacity out of range"; return false; }
   return true;
 }
 
@@ -171,20 +174,17 @@ DevSettings dev_settings(const sixdgs_settings& s) {
   return d;
 }
 
-constexpr int64_t kSortChunk = 2048;  // items per workgroup in the integer stage
-
 bool ensure_entries(sixdgs_ctx* c, int64_t E) {
   const int64_t e1 = E > 0 ? E : 1;
   return c->rec.ensure(e1) && c->tiles.ensure(e1) && c->dkey0.ensure(e1) && c->dkey1.ensure(e1) &&
-         c->dval0.ensure(e1) && c->dval1.ensure(e1) && c->poff.ensure(e1) && c->counters.ensure(4);
+         c->dval0.ensure(e1) && c->dval1.ensure(e1) && c->poff.ensure(e1);
 }
 
 bool ensure_scratch(sixdgs_ctx* c, int64_t E, int64_t pcap) {
-  const int64_t bound = std::max<int64_t>(std::max<int64_t>(E, pcap), 1);
-  const int64_t nb = (bound + kSortChunk - 1) / kSortChunk;
-  const int64_t hist = 256 * nb;
-  const int64_t sblocks = std::max((hist + kSortChunk - 1) / kSortChunk, nb) + 1;
-  return c->hist.ensure(hist) && c->scan_blocks.ensure(sblocks);
+  const int64_t e1 = std::max<int64_t>(E, 1);
+  const int64_t p1 = std::max<int64_t>(pcap, 1);
+  return c->rstate.ensure(sort_state_words(e1, false) + sort_state_words(p1, true)) &&
+         c->blk_start.ensure(sort_block_starts(p1));
 }
 
 bool ensure_pairs(sixdgs_ctx* c, int64_t P, double slack) {
@@ -209,10 +209,9 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.pval[0] = c->pval0.p;
   b.pval[1] = c->pval1.p;
   b.ranges = c->ranges.p;
-  b.scan_blocks = c->scan_blocks.p;
-  b.scan_blocks_cap = c->scan_blocks.cap;
-  b.hist = c->hist.p;
-  b.hist_cap = c->hist.cap;
+  b.rstate_depth = c->rstate.p;
+  b.rstate_pairs = c->rstate.p + sort_state_words(std::max<int64_t>(E, 1), false);
+  b.blk_start = c->blk_start.p;
   b.counters = c->counters.p;
 }
 
@@ -288,6 +287,7 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
         hipStreamSynchronize(st) != hipSuccess)
       return fail(c, SIXDGS_ERR_HIP, "pair count read-back failed");
     const int64_t P = c->host_counters[1];
+    if (P > kMaxItems) return fail(c, SIXDGS_ERR_CAPACITY, "more than 2^30 - 1 pairs");
     if (P > c->sb.pcap) {
       if (!ensure_pairs(c, P, 1.25)) return fail(c, SIXDGS_ERR_OOM, "pair buffers");
       if (!ensure_scratch(c, E, c->pkey0.cap)) return fail(c, SIXDGS_ERR_OOM, "sort scratch");
@@ -330,6 +330,11 @@ sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s) {
     delete c;
     return SIXDGS_ERR_HIP;
   }
+  // the error flags in counters[2..3] are only ever set by kernels and cleared by sixdgs_check
+  if (!c->counters.ensure(4) || hipMemset(c->counters.p, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+    sixdgs_destroy(c);
+    return SIXDGS_ERR_OOM;
+  }
   *out = c;
   return SIXDGS_OK;
 }
@@ -356,8 +361,8 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   c->counts.release();
   c->g2d.release();
   c->l1_partial.release();
-  c->scan_blocks.release();
-  c->hist.release();
+  c->rstate.release();
+  c->blk_start.release();
   c->counters.release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   delete c;
@@ -392,6 +397,7 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
     vt.v[k].img = images[k];
   }
   const int64_t E = n * ncam;
+  if (E > kMaxItems) return fail(c, SIXDGS_ERR_INVALID_ARG, "n * cameras must stay below 2^30");
   c->have_fwd = false;
   if (!ensure_entries(c, E)) return fail(c, SIXDGS_ERR_OOM, "entry buffers");
   if (!c->T_final.ensure(total_px) || !c->last.ensure(total_px)) return fail(c, SIXDGS_ERR_OOM, "pixel state");
@@ -536,6 +542,7 @@ sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, in
   std::string why = build_views(c->s, n, cams, ncam, vt, total_px);
   if (!why.empty()) return fail(c, SIXDGS_ERR_INVALID_ARG, why);
   const int64_t E = n * ncam;
+  if (E > kMaxItems) return fail(c, SIXDGS_ERR_INVALID_ARG, "n * cameras must stay below 2^30");
   c->have_fwd = false;
   if (!ensure_entries(c, E)) return fail(c, SIXDGS_ERR_OOM, "entry buffers");
   c->vt = vt;
@@ -614,6 +621,11 @@ sixdgs_status sixdgs_check(sixdgs_ctx* c) {
   uint32_t cnt[4];
   if (hipMemcpy(cnt, c->counters.p, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(c, SIXDGS_ERR_HIP, "counter read-back failed");
+  if (cnt[3]) {
+    const uint32_t zero = 0;
+    (void)hipMemcpy(c->counters.p + 3, &zero, 4, hipMemcpyHostToDevice);
+    return fail(c, SIXDGS_ERR_HIP, "radix sort look-back wait timed out (output invalid)");
+  }
   if (cnt[2]) {
     const uint32_t zero = 0;
     (void)hipMemcpy(c->counters.p + 2, &zero, 4, hipMemcpyHostToDevice);

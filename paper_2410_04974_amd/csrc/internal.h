@@ -115,6 +115,8 @@ void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, c
                                 float* densify, hipStream_t st);
 
 // sort.hip -- the integer stage
+constexpr int kMaxPasses = 4;  // radix passes of at most 8 bits over a 32-bit key
+
 struct SortBuffers {
   // entries
   int64_t E;
@@ -129,14 +131,16 @@ struct SortBuffers {
   uint32_t* pval[2];    // [pcap] entry ids
   uint2* ranges;        // [total_tiles]
   // scratch
-  uint32_t* scan_blocks;  // block sums
-  int64_t scan_blocks_cap;
-  uint32_t* hist;         // radix histograms
-  int64_t hist_cap;
-  uint32_t* counters;     // [0] binned entries, [1] pairs, [2] overflow flag, [3] spare
+  uint32_t* rstate_depth;  // [sort_state_words(E, false)] state of the scans and the depth sort
+  uint32_t* rstate_pairs;  // [sort_state_words(pcap, true)] radix state of the tile sort
+  uint32_t* blk_start;     // [sort_block_starts(pcap)] first sorted entry of each emission block
+  uint32_t* counters;      // [0] binned entries, [1] pairs, [2] overflow flag, [3] sort look-back timeout
   // where the sorted results ended up (index into the ping-pong pairs)
   int dsorted, psorted;
 };
+// Scratch sizes (32-bit words) of the integer stage for a bound on the items.
+int64_t sort_state_words(int64_t bound, bool pairs);
+int64_t sort_block_starts(int64_t pcap);
 // Stage 1: compaction of binned entries and their depth sort, then the pair
 // offsets; leaves counters[0] = binned entries, counters[1] = pairs.
 void launch_bin_count(SortBuffers& b, hipStream_t st);

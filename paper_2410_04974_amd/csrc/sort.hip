@@ -54,175 +54,338 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t& total)
   return before + inc - x;
 }
 
-// ---------------------------------------------------------- generic scan
-// Phase 1: per-workgroup sums of f(i) over i < count.
-template <class F>
-__global__ void __launch_bounds__(kBlock) k_scan_reduce(F f, const uint32_t* count_ptr, uint32_t fixed, uint32_t cap,
-                                                        uint32_t* __restrict__ block_sums) {
-  const uint32_t count = load_count(count_ptr, fixed, cap);
-  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kItems; k++)
-    if (base + k < count) s += f(base + k);
-  uint32_t total;
-  block_scan_excl(s, total);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+// ------------------------------------------------------------ radix sort
+// One kernel per pass: each workgroup takes the next 4096 items in ticket
+// order, ranks them stably by digit in LDS, and finds where its items of each
+// digit go by looking back over the per-digit counts that earlier workgroups
+// publish (a status word per digit: aggregate of that workgroup alone, or
+// inclusive prefix through it).  The global digit offsets come from a
+// histogram of every pass taken before the first pass, so each pass reads and
+// writes the data once.  Tickets make a workgroup wait only on workgroups that
+// are already running; the wait is bounded and reports a timeout in the error
+// word instead of spinning forever.
+constexpr int kRItems = 16;
+constexpr int kRChunk = kBlock * kRItems;  // items per workgroup and pass over the pairs
+constexpr int kRItemsSmall = 4;           // the depth sort: 1024 items per workgroup, 4x the workgroups
+constexpr uint32_t kStAgg = 1u << 30;
+constexpr uint32_t kStIncl = 2u << 30;
+constexpr uint32_t kStVal = kStAgg - 1u;
+constexpr int kMaxSpin = 1 << 20;
+
+// Radix state of one sort: global digit histograms, tickets and look-back
+// status words, laid out in one buffer.
+struct RadixState {
+  uint32_t* ghist;        // [kMaxPasses][256]
+  uint32_t* tickets;      // [kMaxPasses] passes, then [2] scans (padded to 256 words)
+  uint32_t* status;       // [kMaxPasses][nblk][256]
+  uint64_t* scan_status;  // [2][nscan] look-back words of the two scans over entries
+  int64_t nblk, nscan;
+  int items;              // items per thread of the passes
+  __host__ __device__ int64_t words() const { return (int64_t)kMaxPasses * 256 * (nblk + 2) + 4 * nscan; }
+};
+
+inline int64_t radix_blocks(int64_t bound, int items) {
+  const int64_t chunk = (int64_t)kBlock * items;
+  return (bound + chunk - 1) / chunk;
 }
 
-// Phase 2: one workgroup scans the block sums in place (exclusive) and writes the total.
-__global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t* __restrict__ block_sums, uint32_t nblocks,
-                                                     uint32_t* __restrict__ total_out) {
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < nblocks; base += kChunk) {
-    uint32_t v[kItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; k++) {
-      const uint32_t i = base + threadIdx.x * kItems + k;
-      v[k] = i < nblocks ? block_sums[i] : 0u;
-      s += v[k];
+RadixState radix_state(uint32_t* base, int64_t bound, int items, bool with_scans) {
+  RadixState r;
+  r.items = items;
+  r.nblk = radix_blocks(bound, items);
+  r.nscan = with_scans ? (bound + kChunk - 1) / kChunk : 0;
+  r.ghist = base;
+  r.tickets = base + kMaxPasses * 256;
+  r.status = base + 2 * kMaxPasses * 256;
+  r.scan_status = reinterpret_cast<uint64_t*>(r.status + (int64_t)kMaxPasses * r.nblk * 256);
+  return r;
+}
+
+// Pass layout of a key with `bits` significant bits: ceil(bits / 8) passes of
+// equal digit width (fewer buckets per pass when the key is short).
+struct RadixPlan {
+  int npass, dbits;
+};
+RadixPlan radix_plan(int bits) {
+  RadixPlan p;
+  p.npass = (bits + 7) / 8;
+  if (p.npass < 1) p.npass = 1;
+  p.dbits = (bits + p.npass - 1) / p.npass;
+  if (p.dbits < 1) p.dbits = 1;
+  return p;
+}
+
+__device__ __forceinline__ uint32_t st_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix over earlier workgroups from their 64-bit look-back words
+// (flag in the high half, a 32-bit sum in the low half); bounded wait.
+constexpr uint64_t kSc64Agg = 1ull << 32;
+constexpr uint64_t kSc64Incl = 2ull << 32;
+
+__device__ __forceinline__ uint64_t st_load64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ uint32_t look_back64(const uint64_t* status, int64_t blk, uint32_t* err) {
+  uint32_t excl = 0;
+  for (int64_t j = blk - 1; j >= 0; j--) {
+    uint64_t s = 0;
+    for (int spin = 0; spin < kMaxSpin; spin++) {
+      s = st_load64(status + j);
+      if (s) break;
+      __builtin_amdgcn_s_sleep(1);
     }
-    uint32_t total;
-    uint32_t pre = block_scan_excl(s, total) + carry;
-#pragma unroll
-    for (int k = 0; k < kItems; k++) {
-      const uint32_t i = base + threadIdx.x * kItems + k;
-      if (i < nblocks) block_sums[i] = pre;
-      pre += v[k];
+    if (!s) {
+      atomicOr(err, 1u);
+      break;
     }
-    carry += total;
+    excl += (uint32_t)s;
+    if (s & kSc64Incl) break;
   }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
+  return excl;
 }
 
-// Phase 3: exclusive prefix of f(i) handed to g(i, prefix, value).
-template <class F, class G>
-__global__ void __launch_bounds__(kBlock) k_scan_apply(F f, G g, const uint32_t* count_ptr, uint32_t fixed,
-                                                       uint32_t cap, const uint32_t* __restrict__ block_sums) {
+// Single-pass exclusive scan of f(i) over i < count, handing (i, prefix,
+// value) to g.  Workgroups take 2048 items each in ticket order and chain
+// their prefixes through look-back words; the workgroup holding the last item
+// writes the total.  With HIST, g.key(i) of every item with a non-zero value
+// also enters the digit histograms of a 4-pass, 8-bit radix sort.
+template <class F, class G, bool HIST>
+__global__ void __launch_bounds__(kBlock) k_scan1(F f, G g, const uint32_t* count_ptr, uint32_t fixed, uint32_t cap,
+                                                  uint32_t* ticket, uint64_t* status, uint32_t* total_out,
+                                                  uint32_t* ghist, uint32_t* err) {
+  __shared__ uint32_t s_blk, s_pre;
+  __shared__ uint32_t s_h[HIST ? kMaxPasses : 1][256];
+  const int t = threadIdx.x;
+  if (t == 0) s_blk = atomicAdd(ticket, 1u);
+  if (HIST) {
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; p++) s_h[p][t] = 0;
+  }
+  __syncthreads();
+  const int64_t blk = s_blk;
   const uint32_t count = load_count(count_ptr, fixed, cap);
-  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+  const int64_t start = blk * kChunk;
+  if (start >= count) {  // uniform
+    if (blk == 0 && t == 0 && total_out) *total_out = 0u;
+    return;
+  }
+  const int64_t base = start + (int64_t)t * kItems;
   uint32_t v[kItems];
-  uint32_t s = 0;
+  uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kItems; k++) {
     v[k] = (base + k < count) ? f(base + k) : 0u;
-    s += v[k];
+    sum += v[k];
   }
   uint32_t total;
-  uint32_t pre = block_scan_excl(s, total) + block_sums[blockIdx.x];
+  uint32_t pre = block_scan_excl(sum, total);
+  if (t == 0) {
+    uint64_t* my = status + blk;
+    uint32_t excl = 0;
+    if (blk == 0) {
+      st_store64(my, kSc64Incl | total);
+    } else {
+      st_store64(my, kSc64Agg | total);
+      excl = look_back64(status, blk, err);
+      st_store64(my, kSc64Incl | (uint32_t)(excl + total));
+    }
+    s_pre = excl;
+    if (start + kChunk >= count && total_out) *total_out = excl + total;
+  }
+  __syncthreads();
+  pre += s_pre;
 #pragma unroll
   for (int k = 0; k < kItems; k++) {
-    if (base + k < count) g(base + k, pre, v[k]);
+    if (base + k < count) {
+      g(base + k, pre, v[k]);
+      if constexpr (HIST) {
+        if (v[k]) {
+          const uint32_t key = g.key(base + k);
+#pragma unroll
+          for (int p = 0; p < kMaxPasses; p++) atomicAdd(&s_h[p][(key >> (8 * p)) & 255u], 1u);
+        }
+      }
+    }
     pre += v[k];
   }
-}
-
-template <class F, class G>
-void scan(F f, G g, const uint32_t* count_ptr, uint32_t fixed, uint32_t cap, int64_t bound, uint32_t* block_sums,
-          uint32_t* total_out, hipStream_t st) {
-  const uint32_t nb = (uint32_t)((bound + kChunk - 1) / kChunk);
-  if (nb == 0) return;
-  hipLaunchKernelGGL((k_scan_reduce<F>), dim3(nb), dim3(kBlock), 0, st, f, count_ptr, fixed, cap, block_sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, block_sums, nb, total_out);
-  hipLaunchKernelGGL((k_scan_apply<F, G>), dim3(nb), dim3(kBlock), 0, st, f, g, count_ptr, fixed, cap, block_sums);
-}
-
-// ------------------------------------------------------------ radix sort
-__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* count_ptr,
-                                                       uint32_t cap, int shift, uint32_t* __restrict__ hist,
-                                                       uint32_t nblocks) {
-  __shared__ uint32_t s_h[256];
-  s_h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t count = load_count(count_ptr, cap, cap);
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  if (HIST) {
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kItems; r++) {
-    const int64_t i = base + r * kBlock + threadIdx.x;
-    if (i < count) atomicAdd(&s_h[(keys[i] >> shift) & 255u], 1u);
+    for (int p = 0; p < kMaxPasses; p++)
+      if (s_h[p][t]) atomicAdd(&ghist[p * 256 + t], s_h[p][t]);
   }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// Stable scatter: items are ranked in index order within the workgroup (256
-// consecutive items per round; within a wavefront equal digits are matched
-// with 8 ballots), then placed after all smaller digits and all earlier
-// workgroups' items of the same digit.
-__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ kin,
-                                                          const uint32_t* __restrict__ vin,
-                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          const uint32_t* count_ptr, uint32_t cap, int shift,
-                                                          const uint32_t* __restrict__ hist, uint32_t nblocks) {
-  __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_cnt[kWaves][256];
+template <bool HIST, class F, class G>
+void scan1(F f, G g, const uint32_t* count_ptr, uint32_t fixed, uint32_t cap, int64_t bound, uint32_t* ticket,
+           uint64_t* status, uint32_t* total_out, uint32_t* ghist, uint32_t* err, hipStream_t st) {
+  int64_t nb = (bound + kChunk - 1) / kChunk;
+  if (nb < 1) nb = 1;  // one workgroup writes a zero total
+  hipLaunchKernelGGL((k_scan1<F, G, HIST>), dim3((unsigned)nb), dim3(kBlock), 0, st, f, g, count_ptr, fixed, cap,
+                     ticket, status, total_out, ghist, err);
+}
+
+// Zeroes a radix state (and optionally the tile ranges), and when given the
+// depth-sorted entries, records for every 4096-pair block the sorted entry
+// whose pairs contain the block's first pair.
+__global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, uint2* __restrict__ ranges, int64_t nranges,
+                                                       const uint32_t* __restrict__ counters,
+                                                       const uint32_t* __restrict__ tiles,
+                                                       const uint32_t* __restrict__ dval,
+                                                       const uint32_t* __restrict__ poff, uint32_t pcap,
+                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t w4 = rs.words() / 4;
+  if (i < w4) reinterpret_cast<uint4*>(rs.ghist)[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (ranges && i < nranges) ranges[i] = make_uint2(0u, 0u);
+  if (blk_start && i < (int64_t)counters[0] && counters[1] <= pcap) {
+    const uint32_t o = poff[i];
+    const uint32_t end = o + tiles[dval[i]];
+    for (uint32_t b = (o + kRChunk - 1) / kRChunk; (int64_t)b * kRChunk < end && b < nblk_start; b++)
+      blk_start[b] = (uint32_t)i;
+  }
+}
+
+// One stable pass over the digit at `shift` (width dbits) of keys[0, count).
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                     uint32_t* __restrict__ vout, const uint32_t* count_ptr,
+                                                     uint32_t cap, int shift, int dbits,
+                                                     const uint32_t* __restrict__ ghist, uint32_t* ticket,
+                                                     uint32_t* status, uint32_t* err) {
+  constexpr int kChunkI = kBlock * ITEMS;
+  constexpr int kWaveItems = kChunkI / kWaves;
+  __shared__ uint32_t s_key[kChunkI];
+  __shared__ uint32_t s_val[kChunkI];
+  __shared__ uint32_t s_wc[kWaves][256];  // per-wave digit counts, then exclusive prefixes over waves
+  __shared__ uint32_t s_lex[256];         // exclusive digit offsets inside the workgroup
+  __shared__ uint32_t s_gb[256];          // output position of LDS slot 0 of each digit
+  __shared__ uint32_t s_blk;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const uint32_t count = load_count(count_ptr, cap, cap);
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  if (base >= count) return;  // uniform over the workgroup
-  s_off[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+  if (t == 0) s_blk = atomicAdd(ticket, 1u);
 #pragma unroll
-  for (int w = 0; w < kWaves; w++) s_cnt[w][t] = 0;
+  for (int w = 0; w < kWaves; w++) s_wc[w][t] = 0;
   __syncthreads();
+  const int64_t blk = s_blk;
+  const uint32_t count = load_count(count_ptr, cap, cap);
+  const int64_t base = blk * kChunkI;
+  if (base >= count) return;  // uniform; no later workgroup has items, so none waits on this one
+  const uint32_t mask = (1u << dbits) - 1u;
+  const bool own = (uint32_t)t <= mask;
+  const uint32_t gh = own ? ghist[t] : 0u;  // issued early: used after the look-back
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kItems; r++) {
-    const int64_t i = base + r * kBlock + t;
-    if (base + r * kBlock >= count) break;  // uniform
-    const bool valid = i < count;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t dig = (key >> shift) & 255u;
-    uint64_t m = __ballot(valid);
+  const int64_t wbase = base + (int64_t)wv * kWaveItems;  // each wavefront ranks consecutive items
+  uint32_t key[ITEMS], val[ITEMS], loc[ITEMS];
 #pragma unroll
-    for (int b = 0; b < 8; b++) {
-      const bool bit = (dig >> b) & 1u;
+  for (int r = 0; r < ITEMS; r++) {
+    const int64_t i = wbase + r * 64 + lane;
+    key[r] = i < count ? kin[i] : 0u;
+    val[r] = i < count ? vin[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const bool valid = wbase + r * 64 + lane < count;
+    const uint32_t d = (key[r] >> shift) & mask;
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < dbits; b++) {
+      const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
       m &= bit ? bb : ~bb;
     }
     const uint32_t rank = __popcll(m & lt);
-    if (valid && rank == 0) s_cnt[wv][dig] = __popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t off = s_off[dig] + rank;
-      for (int w = 0; w < wv; w++) off += s_cnt[w][dig];
-      kout[off] = key;
-      vout[off] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    // every lane of a digit group reads the running count before its first lane moves it on
+    const uint32_t pre = s_wc[wv][d];
+    if (valid && rank == 0) s_wc[wv][d] = pre + (uint32_t)__popcll(m);
+    loc[r] = valid ? ((pre + rank) << 8 | d) : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  uint32_t tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; w++) {
-      add += s_cnt[w][t];
-      s_cnt[w][t] = 0;
+  for (int w = 0; w < kWaves; w++) {
+    const uint32_t c = s_wc[w][t];
+    s_wc[w][t] = tot;
+    tot += c;
+  }
+  uint32_t* my = status + blk * 256 + t;
+  if (own) st_store(my, (blk == 0 ? kStIncl : kStAgg) | tot);
+  uint32_t total;
+  const uint32_t lex = block_scan_excl(tot, total);
+  s_lex[t] = lex;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    if (loc[r] != 0xFFFFFFFFu) {
+      const uint32_t d = loc[r] & 255u;
+      const uint32_t pos = s_lex[d] + s_wc[wv][d] + (loc[r] >> 8);
+      if (pos < (uint32_t)kChunkI) {  // always true; guards LDS against inconsistent counts
+        s_key[pos] = key[r];
+        s_val[pos] = val[r];
+      }
     }
-    s_off[t] += add;
-    __syncthreads();
+  }
+  // exclusive prefix of this digit over the earlier workgroups
+  uint32_t excl = 0;
+  if (own && blk > 0) {
+    int64_t j = blk - 1;
+    for (;;) {
+      uint32_t s = 0;
+      for (int spin = 0; spin < kMaxSpin; spin++) {
+        s = st_load(status + j * 256 + t);
+        if (s) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (!s) {
+        atomicOr(err, 1u);
+        break;
+      }
+      excl += s & kStVal;
+      if ((s & kStIncl) || j == 0) break;
+      j--;
+    }
+    st_store(my, kStIncl | (excl + tot));
+  }
+  const uint32_t gex = block_scan_excl(gh, total);
+  s_gb[t] = gex + excl - lex;  // modular: adding an LDS slot of this digit lands in range
+  __syncthreads();
+  const int64_t left = (int64_t)count - base;
+  const int nvalid = left < kChunkI ? (int)left : kChunkI;
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const int k = r * kBlock + t;
+    if (k < nvalid) {
+      const uint32_t kk = s_key[k];
+      const uint32_t o = s_gb[(kk >> shift) & mask] + (uint32_t)k;
+      if (o < count) {  // always true for a consistent histogram; guards the buffers
+        kout[o] = kk;
+        vout[o] = s_val[k];
+      }
+    }
   }
 }
 
-struct HistVal {
-  const uint32_t* h;
-  __device__ uint32_t operator()(int64_t i) const { return h[i]; }
-};
-struct HistStore {
-  uint32_t* h;
-  __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { h[i] = pre; }
-};
-
-// Sorts (keys, vals) of length *count_ptr (<= bound) by the low `bits` bits;
-// returns which buffer of the ping-pong pair holds the result.
-int radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* count_ptr, int64_t bound, int bits,
-               uint32_t* hist, uint32_t* scan_blocks, hipStream_t st) {
-  const uint32_t nb = (uint32_t)((bound + kChunk - 1) / kChunk);
+// Sorts (keys, vals) of length *count_ptr (<= bound) over plan.npass digits
+// whose histograms are already in rs.ghist; returns which buffer of the
+// ping-pong pair holds the result.
+int radix_sort(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* count_ptr, int64_t bound, RadixPlan plan,
+               const RadixState& rs, uint32_t* err, hipStream_t st) {
+  const int64_t nb = rs.nblk;
   int cur = 0;
   if (nb == 0) return cur;
-  const uint32_t cap = (uint32_t)bound;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBlock), 0, st, keys[cur], count_ptr, cap, shift, hist, nb);
-    scan(HistVal{hist}, HistStore{hist}, nullptr, 256u * nb, 256u * nb, (int64_t)256 * nb, scan_blocks, nullptr, st);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBlock), 0, st, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], count_ptr, cap, shift, hist, nb);
+  for (int p = 0; p < plan.npass; p++) {
+    auto k = rs.items == kRItems ? k_onesweep<kRItems> : k_onesweep<kRItemsSmall>;
+    hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(kBlock), 0, st, keys[cur], vals[cur], keys[cur ^ 1],
+                       vals[cur ^ 1], count_ptr, (uint32_t)bound, p * plan.dbits, plan.dbits, rs.ghist + p * 256,
+                       rs.tickets + p, rs.status + (int64_t)p * rs.nblk * 256, err);
     cur ^= 1;
   }
   return cur;
@@ -237,10 +400,11 @@ struct CompactDepth {
   const Rec* rec;
   uint32_t* dkey;
   uint32_t* dval;
+  // depths of binned entries exceed z_near > 0, so their bit patterns order as the values
+  __device__ uint32_t key(int64_t i) const { return __float_as_uint(rec[i].c.w); }
   __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const {
     if (v) {
-      // depths of binned entries exceed z_near > 0, so their bit patterns order as the values
-      dkey[pre] = __float_as_uint(rec[i].c.w);
+      dkey[pre] = key(i);
       dval[pre] = (uint32_t)i;
     }
   }
@@ -255,40 +419,80 @@ struct StoreOffset {
   __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { poff[i] = pre; }
 };
 
+// Load-balanced pair emission: workgroup b writes pairs [4096 b, 4096 (b + 1))
+// in depth order.  It walks the depth-sorted entries from the one holding its
+// first pair, 256 entries per step; each thread finds the entry of a pair by
+// binary search over the entries' pair offsets in LDS and the pair's tile from
+// its index in the entry's tile rectangle (row-major, the order the count
+// came from), so consecutive threads write consecutive pairs whatever the
+// entries' sizes.  The digit histograms of every pass of the tile sort are
+// accumulated on the way.
 __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __restrict__ rec,
-                                                 const uint32_t* __restrict__ tiles,
                                                  const uint32_t* __restrict__ dval, const uint32_t* __restrict__ poff,
-                                                 uint32_t* __restrict__ counters, uint32_t pcap,
-                                                 uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+                                                 const uint32_t* __restrict__ blk_start,
+                                                 uint32_t* __restrict__ counters, uint32_t pcap, int npass, int dbits,
+                                                 uint32_t* __restrict__ ghist, uint32_t* __restrict__ pkey,
+                                                 uint32_t* __restrict__ pval) {
+  __shared__ uint32_t s_o[kBlock + 1];  // pair offset of each entry of the step; [kBlock]: the next step's
+  __shared__ uint32_t s_e[kBlock];      // entry id
+  __shared__ uint32_t s_base[kBlock];   // global id of the rectangle's first tile
+  __shared__ uint32_t s_w[kBlock];      // rectangle width in tiles
+  __shared__ uint32_t s_ntx[kBlock];    // tiles per row of the entry's view
+  __shared__ uint32_t s_h[kMaxPasses][256];
+  const int t = threadIdx.x;
   const uint32_t nb = counters[0];
   const uint32_t P = counters[1];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (P > pcap) {
-    if (i == 0) counters[2] = 1u;
+    if (blockIdx.x == 0 && t == 0) counters[2] = 1u;
     return;
   }
-  if (i >= nb) return;
-  const uint32_t e = dval[i];
-  const int view = (int)(e / (uint64_t)vt.n);
-  const ViewDesc& vd = vt.v[view];
-  const Rec r = rec[e];
-  int x0, y0, x1, y1;
-  tile_rect(r.a.x, r.a.y, r.b.z, r.b.w, vt.tile_shift_x, vt.tile_shift_y, vd.ntx, vd.nty, x0, y0, x1, y1);
-  uint32_t o = poff[i];
-  // the rectangle is the one the tile count came from; the bound only guards the buffers
-  const uint32_t stop = min(o + tiles[e], P);
-  for (int ty = y0; ty < y1; ty++)
-    for (int tx = x0; tx < x1; tx++) {
-      if (o >= stop) return;
-      pkey[o] = (uint32_t)(vd.tile_base + ty * vd.ntx + tx);
-      pval[o] = e;
-      o++;
+  const int64_t p0 = (int64_t)blockIdx.x * kRChunk;
+  if (p0 >= P) return;  // uniform
+  const uint32_t p1 = (uint32_t)min<int64_t>(p0 + kRChunk, (int64_t)P);
+  const uint32_t mask = (1u << dbits) - 1u;
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; p++) s_h[p][t] = 0;
+  uint32_t ib = blk_start[blockIdx.x];
+  for (;;) {
+    const uint32_t i = ib + t;
+    if (i < nb) {
+      const uint32_t e = dval[i];
+      const ViewDesc& vd = vt.v[e / (uint64_t)vt.n];
+      const float4 ra = rec[e].a, rb = rec[e].b;
+      int x0, y0, x1, y1;
+      tile_rect(ra.x, ra.y, rb.z, rb.w, vt.tile_shift_x, vt.tile_shift_y, vd.ntx, vd.nty, x0, y0, x1, y1);
+      s_o[t] = poff[i];
+      s_e[t] = e;
+      s_base[t] = (uint32_t)(vd.tile_base + y0 * vd.ntx + x0);
+      s_w[t] = (uint32_t)(x1 - x0);
+      s_ntx[t] = (uint32_t)vd.ntx;
+    } else {
+      s_o[t] = P;  // past the last entry: never chosen by the search below
     }
-}
-
-__global__ void __launch_bounds__(kBlock) k_fill_u2(uint2* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = make_uint2(0u, 0u);
+    if (t == 0) s_o[kBlock] = (uint64_t)ib + kBlock < nb ? poff[ib + kBlock] : P;
+    __syncthreads();
+    const uint32_t lo = max((uint32_t)p0, s_o[0]);
+    const uint32_t hi = min(p1, s_o[kBlock]);
+    for (uint32_t q = lo + t; q < hi; q += kBlock) {
+      int j = 0;  // last entry of the step whose pairs start at or before q
+#pragma unroll
+      for (int step = kBlock / 2; step > 0; step >>= 1)
+        if (s_o[j + step] <= q) j += step;
+      const uint32_t local = q - s_o[j];
+      const uint32_t w = s_w[j];
+      const uint32_t ty = local / w;
+      const uint32_t key = s_base[j] + ty * s_ntx[j] + (local - ty * w);
+      pkey[q] = key;
+      pval[q] = s_e[j];
+      for (int p = 0; p < npass; p++) atomicAdd(&s_h[p][(key >> (p * dbits)) & mask], 1u);
+    }
+    const bool done = s_o[kBlock] >= p1;
+    __syncthreads();
+    if (done) break;
+    ib += kBlock;
+  }
+  for (int p = 0; p < npass; p++)
+    if (s_h[p][t]) atomicAdd(&ghist[p * 256 + t], s_h[p][t]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_ranges(const uint32_t* __restrict__ pkey, const uint32_t* counters,
@@ -338,32 +542,51 @@ __global__ void __launch_bounds__(kBlock) k_import(const float* __restrict__ u, 
 
 void launch_bin_count(SortBuffers& b, hipStream_t st) {
   const uint32_t E = (uint32_t)b.E;
-  // compaction of the binned entries with their depth keys
-  scan(BinnedFlag{b.tiles}, CompactDepth{b.rec, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E, b.scan_blocks,
-       &b.counters[0], st);
+  const RadixState rs = radix_state(b.rstate_depth, b.E, kRItemsSmall, true);
+  const RadixPlan plan{4, 8};
+  const unsigned gprep = (unsigned)((rs.words() / 4 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_stage_prep, dim3(gprep), dim3(kBlock), 0, st, rs, (uint2*)nullptr, (int64_t)0,
+                     (const uint32_t*)b.counters, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
+                     (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0);
+  // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
+  scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.rec, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
+              rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
   // depth order (stable: equal depths keep entry order)
-  b.dsorted = radix_sort(b.dkey, b.dval, &b.counters[0], b.E, 32, b.hist, b.scan_blocks, st);
+  b.dsorted = radix_sort(b.dkey, b.dval, &b.counters[0], b.E, plan, rs, &b.counters[3], st);
   // pair offsets in depth order
-  scan(SortedTiles{b.tiles, b.dval[b.dsorted]}, StoreOffset{b.poff}, &b.counters[0], 0u, E, b.E, b.scan_blocks,
-       &b.counters[1], st);
+  scan1<false>(SortedTiles{b.tiles, b.dval[b.dsorted]}, StoreOffset{b.poff}, &b.counters[0], 0u, E, b.E,
+               rs.tickets + kMaxPasses + 1, rs.scan_status + rs.nscan, &b.counters[1], (uint32_t*)nullptr,
+               &b.counters[3], st);
 }
 
 void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hipStream_t st) {
-  const unsigned ge = (unsigned)((b.E + kBlock - 1) / kBlock);
-  if (ge)
-    hipLaunchKernelGGL(k_emit, dim3(ge), dim3(kBlock), 0, st, vt, b.rec, b.tiles, b.dval[b.dsorted], b.poff, b.counters,
-                       (uint32_t)b.pcap, b.pkey[0], b.pval[0]);
   int bits = 1;
   while ((1ll << bits) < (int64_t)vt.total_tiles) bits++;
+  const RadixPlan plan = radix_plan(bits);
   const int64_t bound = pairs_hint < b.pcap ? pairs_hint : b.pcap;
-  b.psorted = radix_sort(b.pkey, b.pval, &b.counters[1], bound, bits, b.hist, b.scan_blocks, st);
-  const unsigned gt = (unsigned)((vt.total_tiles + kBlock - 1) / kBlock);
-  if (gt) hipLaunchKernelGGL(k_fill_u2, dim3(gt), dim3(kBlock), 0, st, b.ranges, (int64_t)vt.total_tiles);
+  const RadixState rs = radix_state(b.rstate_pairs, bound, kRItems, false);
+  int64_t prep = rs.words() / 4;
+  if (prep < vt.total_tiles) prep = vt.total_tiles;
+  if (prep < b.E) prep = b.E;
+  hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs, b.ranges,
+                     (int64_t)vt.total_tiles, (const uint32_t*)b.counters, (const uint32_t*)b.tiles,
+                     (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.poff, (uint32_t)b.pcap, b.blk_start,
+                     rs.nblk);
+  if (rs.nblk)
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)rs.nblk), dim3(kBlock), 0, st, vt, b.rec, b.dval[b.dsorted], b.poff,
+                       b.blk_start, b.counters, (uint32_t)b.pcap, plan.npass, plan.dbits, rs.ghist, b.pkey[0],
+                       b.pval[0]);
+  b.psorted = radix_sort(b.pkey, b.pval, &b.counters[1], bound, plan, rs, &b.counters[3], st);
   const unsigned gp = (unsigned)((bound + kBlock - 1) / kBlock);
   if (gp)
     hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
                        (uint32_t)vt.total_tiles, b.ranges);
 }
+
+int64_t sort_state_words(int64_t bound, bool pairs) {
+  return radix_state(nullptr, bound, pairs ? kRItems : kRItemsSmall, !pairs).words();
+}
+int64_t sort_block_starts(int64_t pcap) { return radix_blocks(pcap, kRItems) + 1; }
 
 void launch_zero_g2d(const SortBuffers& b, float* g2d, hipStream_t st) {
   const unsigned g = (unsigned)((b.E + kBlock - 1) / kBlock);

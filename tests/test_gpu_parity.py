@@ -74,15 +74,15 @@ def test_records_match_oracle(name, n):
 
 
 # ------------------------------------------------------------ integer stage
-def _random_records(n, cams, seed):
+def _random_records(n, cams, seed, ext=10.0):
     rng = np.random.default_rng(seed)
     E = n * len(cams)
     W = max(c.width for c in cams)
     H = max(c.height for c in cams)
     u = rng.uniform(-0.2 * W, 1.2 * W, E).astype(np.float32)
     v = rng.uniform(-0.2 * H, 1.2 * H, E).astype(np.float32)
-    ex = rng.exponential(10, E).astype(np.float32)
-    ey = rng.exponential(10, E).astype(np.float32)
+    ex = rng.exponential(ext, E).astype(np.float32)
+    ey = rng.exponential(ext, E).astype(np.float32)
     big = rng.random(E) < 0.002
     ex[big] *= 30
     ey[big] *= 30
@@ -125,6 +125,32 @@ def test_binning_bit_exact(tile, case):
     assert np.array_equal(keys, ref["keys"])
     assert np.array_equal(vals, ref["values"].astype(np.int32))
     assert np.array_equal(ranges, ref["ranges"].astype(np.int32))
+
+
+@pytest.mark.parametrize("case", ["c2_size", "sixteen_1080p_views"])
+def test_binning_bit_exact_at_full_size(case):
+    """The integer stage at the sizes the benchmarks run: ~300k entries giving
+    several million pairs on one 800x800 view (a 12-bit tile id: two 6-bit
+    passes), and 16 views of 1920x1080 (130k tiles: three passes), in both the
+    growing and the fixed-capacity mode."""
+    if case == "c2_size":
+        cams, n, ext = [synth.default_camera(800, 800)], 300000, 30.0
+    else:
+        cams, n, ext = [synth.default_camera(1920, 1080)] * 16, 40000, 20.0
+    u, v, ex, ey, depth, alive = _random_records(n, cams, seed=12, ext=ext)
+    ref = oracle.bin_records(u, v, ex, ey, depth, alive.astype(bool), n, cams, 16, 16)
+    P = len(ref["keys"])
+    from paper_2410_04974_amd import _lib
+    dev = [torch.from_numpy(a).to(G.DEV) for a in (u, v, ex, ey, depth, alive)]
+    for cap in (0, P + 12345):
+        r = G.renderer()
+        r.configure(pair_capacity=cap)
+        r.ctx.bin(n, cams, *dev)
+        r.ctx.check()
+        _say(case, "pairs", P, "capacity", cap)
+        assert np.array_equal(r.ctx.export(_lib.EXPORT_KEYS), ref["keys"])
+        assert np.array_equal(r.ctx.export(_lib.EXPORT_VALUES), ref["values"].astype(np.int32))
+        assert np.array_equal(r.ctx.export(_lib.EXPORT_RANGES), ref["ranges"].astype(np.int32))
 
 
 # ------------------------------------------------------------------ forward
