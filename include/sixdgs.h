@@ -83,12 +83,16 @@ typedef struct {
                             SIXDGS_ERR_CAPACITY by sixdgs_check().  At most
                             2^30 - 1 pairs either way (CAPACITY beyond). */
   int32_t flags;       /* SIXDGS_FLAG_* */
+  int32_t chunk;       /* list positions per backward work item: the backward
+                          walks each tile's list in chunks of this length in
+                          parallel, restarting from state the forward saves at
+                          chunk starts.  A power of two, >= batch, <= 16384. */
 } sixdgs_settings;
 
 #define SIXDGS_FLAG_COUNTS 1 /* forward also stores per-pixel contributor counts (debug export) */
 
 /* Fills `s` with the defaults: lambda 0.35, z_near 0.2, bg 0, 16x16 tiles,
- * batch 256, pair_capacity 0, flags 0. */
+ * batch 256, pair_capacity 0, flags 0, chunk 256. */
 void sixdgs_default_settings(sixdgs_settings* s);
 
 /* Creates a context on the current HIP device.  It owns all scratch memory

@@ -33,7 +33,7 @@ class Camera(ctypes.Structure):
 class Settings(ctypes.Structure):
     _fields_ = [("lambda_opa", ctypes.c_float), ("z_near", ctypes.c_float), ("bg", ctypes.c_float * 3),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
-                ("pair_capacity", ctypes.c_int64), ("flags", ctypes.c_int32)]
+                ("pair_capacity", ctypes.c_int64), ("flags", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
 class SixDGSError(RuntimeError):

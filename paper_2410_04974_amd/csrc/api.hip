@@ -58,6 +58,12 @@ struct sixdgs_ctx {
   // per-pixel state
   DevBuf<float> T_final;
   DevBuf<uint32_t> last, counts;
+  // backward work items: chunk-boundary state, per-tile chunk counts, (tile, chunk) list
+  DevBuf<float4> bound;
+  DevBuf<uint32_t> tile_nch, chunk_state;
+  DevBuf<uint2> items;
+  int64_t bwd_grid = 0;
+  int32_t fwd_chunk = 256;   // chunk length the last forward saved its boundary state for
   // backward and loss
   DevBuf<float> g2d, l1_partial;
   // scratch
@@ -88,6 +94,10 @@ sixdgs_status fail(sixdgs_ctx* c, sixdgs_status st, const std::string& msg) {
   return st;
 }
 
+// counters: [0] binned entries, [1] pairs, [2] pair overflow flag, [3] look-back
+// timeout flag, [4] backward work items
+constexpr int kCounters = 8;
+
 // Bound on entries and pairs: the radix sort's look-back words hold 30-bit counts.
 constexpr int64_t kMaxItems = (1ll << 30) - 1;
 
@@ -106,6 +116,10 @@ bool valid_settings(const sixdgs_settings* s, std::string& why) {
     return false;
   }
   if (s->pair_capacity < 0 || s->pair_capacity > kMaxItems) { why = "pair_capacity out of range"; return false; }
+  if (s->chunk < s->batch || s->chunk > 16384 || (s->chunk & (s->chunk - 1)) != 0) {
+    why = "chunk must be a power of two between batch and 16384";
+    return false;
+  }
   return true;
 }
 
@@ -187,6 +201,21 @@ bool ensure_scratch(sixdgs_ctx* c, int64_t E, int64_t pcap) {
          c->blk_start.ensure(sort_block_starts(p1));
 }
 
+BlendState blend_state(sixdgs_ctx* c) {
+  BlendState bs{};
+  bs.chunk = (uint32_t)c->fwd_chunk;
+  bs.T_final = c->T_final.p;
+  bs.last = c->last.p;
+  bs.counts = nullptr;
+  bs.bound = c->bound.p;
+  bs.nbound = c->bound.cap / kBlock;
+  bs.tile_nch = c->tile_nch.p;
+  bs.items = c->items.p;
+  bs.items_cap = c->items.cap;
+  bs.n_items = c->counters.p + 4;
+  return bs;
+}
+
 bool ensure_pairs(sixdgs_ctx* c, int64_t P, double slack) {
   const int64_t p1 = P > 0 ? P : 1;
   return c->pkey0.ensure(p1, slack) && c->pkey1.ensure(p1, slack) && c->pval0.ensure(p1, slack) &&
@@ -212,6 +241,7 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.rstate_depth = c->rstate.p;
   b.rstate_pairs = c->rstate.p + sort_state_words(std::max<int64_t>(E, 1), false);
   b.blk_start = c->blk_start.p;
+  b.chunk_state = c->chunk_state.p;
   b.counters = c->counters.p;
 }
 
@@ -276,6 +306,7 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
   if (!ensure_scratch(c, E, std::max<int64_t>(c->pkey0.cap, fixed ? c->s.pair_capacity : 0)))
     return fail(c, SIXDGS_ERR_OOM, "sort scratch");
   if (!c->ranges.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile ranges");
+  if (!c->chunk_state.ensure(chunk_scan_words(c->vt.total_tiles))) return fail(c, SIXDGS_ERR_OOM, "tile scan");
   fill_sort_buffers(c, E);
   Timer t(c, SIXDGS_K_SORT, st);
   launch_bin_count(c->sb, st);
@@ -313,6 +344,7 @@ void sixdgs_default_settings(sixdgs_settings* s) {
   s->batch = 256;
   s->pair_capacity = 0;
   s->flags = 0;
+  s->chunk = 256;
 }
 
 sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s) {
@@ -331,7 +363,7 @@ sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s) {
     return SIXDGS_ERR_HIP;
   }
   // the error flags in counters[2..3] are only ever set by kernels and cleared by sixdgs_check
-  if (!c->counters.ensure(4) || hipMemset(c->counters.p, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+  if (!c->counters.ensure(kCounters) || hipMemset(c->counters.p, 0, kCounters * sizeof(uint32_t)) != hipSuccess) {
     sixdgs_destroy(c);
     return SIXDGS_ERR_OOM;
   }
@@ -357,6 +389,10 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   c->pval1.release();
   c->ranges.release();
   c->T_final.release();
+  c->bound.release();
+  c->tile_nch.release();
+  c->chunk_state.release();
+  c->items.release();
   c->last.release();
   c->counts.release();
   c->g2d.release();
@@ -413,11 +449,22 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
   if (rc != SIXDGS_OK) return rc;
   rc = run_binning(c, E, st);
   if (rc != SIXDGS_OK) return rc;
-  BlendState bs{c->T_final.p, c->last.p, want_counts ? c->counts.p : nullptr};
+  // the backward's work items: at most one per `chunk` pairs plus one per tile
+  const int64_t nbound = c->sb.pcap / c->s.chunk + 1;
+  const int64_t grid = nbound + vt.total_tiles;
+  if (!c->bound.ensure(nbound * kBlock) ||
+      !c->tile_nch.ensure(std::max<int64_t>(vt.total_tiles, 1)) || !c->items.ensure(grid))
+    return fail(c, SIXDGS_ERR_OOM, "backward work items");
+  c->bwd_grid = grid;
+  c->fwd_chunk = c->s.chunk;
+  BlendState bs = blend_state(c);
+  bs.counts = want_counts ? c->counts.p : nullptr;
   {
     Timer t(c, SIXDGS_K_BLEND_FWD, st);
     launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->s.batch, st);
   }
+  launch_chunk_items(c->tile_nch.p, vt.total_tiles, c->items.p, grid, c->chunk_state.p, c->counters.p + 4,
+                     c->counters.p + 3, st);
   rc = check_launch(c, "blend forward");
   if (rc != SIXDGS_OK) return rc;
   c->have_fwd = true;
@@ -448,10 +495,11 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, con
   if (!c->g2d.ensure(c->fwd_E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
   const DevSettings ds = dev_settings(c->s);
   launch_zero_g2d(c->sb, c->g2d.p, st);
-  BlendState bs{c->T_final.p, c->last.p, nullptr};
+  const BlendState bs = blend_state(c);
   {
     Timer t(c, SIXDGS_K_BLEND_BWD, st);
-    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch, st);
+    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch,
+                     c->bwd_grid, st);
   }
   sixdgs_status rc = check_launch(c, "blend backward");
   if (rc != SIXDGS_OK) return rc;
@@ -483,10 +531,11 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, cons
   if (!c->g2d.ensure(c->fwd_E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
   const DevSettings ds = dev_settings(c->s);
   launch_zero_g2d(c->sb, c->g2d.p, st);
-  BlendState bs{c->T_final.p, c->last.p, nullptr};
+  const BlendState bs = blend_state(c);
   {
     Timer t(c, SIXDGS_K_BLEND_BWD, st);
-    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch, st);
+    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch,
+                     c->bwd_grid, st);
   }
   sixdgs_status rc = check_launch(c, "blend backward");
   if (rc != SIXDGS_OK) return rc;

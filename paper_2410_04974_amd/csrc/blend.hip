@@ -91,6 +91,12 @@ __device__ __forceinline__ int find_view(const ViewTable& vt, int tile) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
 template <int TW>
 struct TileMap {
   static constexpr int TH = 256 / TW;
@@ -143,7 +149,30 @@ __device__ __forceinline__ uint32_t stage_batch(BatchLDS& L, const Rec* __restri
 #pragma unroll
   for (int s = 0; s < kWaves; s++) cnt += L.wcnt[wv][s];
   __syncthreads();
-  return cnt;
+  return __builtin_amdgcn_readfirstlane(cnt);  // uniform over the wavefront
+}
+
+// The staged records of four consecutive list slots of a wavefront, as the
+// per-pixel loops read them.  The wavefront's list (at most 256 one-byte
+// slots) is held one 32-bit word per lane, so a group's slots come from a
+// readlane instead of an LDS round trip.
+struct Group4 {
+  uint32_t j[4];  // staged slots
+  float4 a[4];    // u, v, cA, cB
+  float2 b[4];    // cC, log2(alpha_cond)
+  float3 c[4];    // r, g, b
+};
+
+__device__ __forceinline__ void fetch_group(const BatchLDS& L, uint32_t lw, uint32_t g, Group4& G) {
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)lw, (int)g);
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const uint32_t j = (w >> (8 * u)) & 255u;
+    G.j[u] = j;
+    G.a[u] = L.rec[j].a;
+    G.b[u] = make_float2(L.rec[j].b.x, L.rec[j].b.y);
+    G.c[u] = make_float3(L.rec[j].c.x, L.rec[j].c.y, L.rec[j].c.z);
+  }
 }
 
 template <int TW>
@@ -164,49 +193,62 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint32_t* list4 = reinterpret_cast<const uint32_t*>(L.list[wv]);
 
+  __shared__ uint32_t s_maxlast;
+  if (threadIdx.x == 0) s_maxlast = 0;
   const uint2 rg = ranges[tile];
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  uint32_t last = 0, cnt = 0;
+  float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // colour of the current backward chunk alone
+  uint32_t last = 0, cnt = 0, nbd = 0;
   bool done = !inside;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += batch) {
     if (__syncthreads_count(!done) == 0) break;
+    const uint32_t rel = b0 - rg.x;
+    if (rel != 0 && (rel & (bs.chunk - 1)) == 0) {
+      // a backward work item starts here: keep this pixel's transmittance and
+      // the colour of the chunk that ends here
+      const int64_t slot = b0 / bs.chunk;
+      if (slot < bs.nbound) bs.bound[slot * kBlock + threadIdx.x] = make_float4(T, K0, K1, K2);
+      K0 = K1 = K2 = 0.f;
+      nbd++;
+    }
     const uint32_t nb = min((uint32_t)batch, rg.y - b0);
     const uint32_t wn = stage_batch<TW>(L, rec, pval, b0, nb, ox, oy);
     const uint32_t pos0 = b0 - rg.x + 1;
-    // four list slots per LDS word; their records are read together so one LDS
-    // round trip serves four Gaussians (slots past wn hold stale but in-range bytes)
-    for (uint32_t g4 = 0; 4 * g4 < wn; g4++) {
-      if (__ballot(!done) == 0) break;
-      const uint32_t w4 = list4[g4];
-      uint32_t js[4];
-      float4 A[4], B[4];
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        js[u] = (w4 >> (8 * u)) & 255u;
-        A[u] = L.rec[js[u]].a;
-        B[u] = L.rec[js[u]].b;
-      }
-      const uint32_t nu = min(4u, wn - 4 * g4);
+    // groups of four list slots (slots past wn hold stale but in-range bytes)
+    const uint32_t lw = list4[l];
+    const uint32_t ng = (wn + 3) >> 2;
+    auto blend = [&](const Group4& G, uint32_t g) {
+      const uint32_t nu = min(4u, wn - 4 * g);
+      // predicated rather than branched: the lanes of a wavefront rarely agree
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         if ((uint32_t)u >= nu) break;
-        const float p = log2_alpha(A[u], B[u], fx - A[u].x, fy - A[u].y);
-        if (done || p < kLog2AlphaMin) continue;
+        const float4 A = G.a[u];
+        const float4 B = make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f);
+        const float p = log2_alpha(A, B, fx - A.x, fy - A.y);
         const float a = fminf(kAlphaMax, exp2_fast(p));
         const float Tn = T * (1.0f - a);
-        if (Tn < kTMin) {
-          done = true;
-          continue;
-        }
-        const float4 Cc = L.rec[js[u]].c;
-        const float wgt = a * T;
-        C0 += Cc.x * wgt;
-        C1 += Cc.y * wgt;
-        C2 += Cc.z * wgt;
-        T = Tn;
-        last = pos0 + js[u];
-        cnt++;
+        const bool take = !done && p >= kLog2AlphaMin;
+        const bool stop = take && Tn < kTMin;
+        done = done || stop;
+        const bool use = take && !stop;
+        const float wgt = use ? a * T : 0.f;
+        C0 += G.c[u].x * wgt;
+        C1 += G.c[u].y * wgt;
+        C2 += G.c[u].z * wgt;
+        K0 += G.c[u].x * wgt;
+        K1 += G.c[u].y * wgt;
+        K2 += G.c[u].z * wgt;
+        T = use ? Tn : T;
+        last = use ? pos0 + G.j[u] : last;
+        cnt += use ? 1u : 0u;
       }
+    };
+    for (uint32_t g = 0; g < ng; g++) {
+      if (__ballot(!done) == 0) break;
+      Group4 X;
+      fetch_group(L, lw, g, X);
+      blend(X, g);
     }
   }
   if (inside) {
@@ -219,6 +261,25 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
     bs.last[vd.pix_base + pix] = last;
     if (bs.counts) bs.counts[vd.pix_base + pix] = cnt;
   }
+  // turn the per-chunk colours into the colour behind each boundary: sums of
+  // positive terms from the back, so no cancellation against the total
+  {
+    float S0 = K0, S1 = K1, S2 = K2;
+    for (uint32_t m = nbd; m >= 1; m--) {
+      const int64_t slot = (int64_t)(rg.x + m * bs.chunk) / bs.chunk;
+      if (slot >= bs.nbound) continue;
+      float4* q = bs.bound + slot * kBlock + threadIdx.x;
+      const float4 v = *q;
+      *q = make_float4(v.x, S0, S1, S2);
+      S0 += v.y;
+      S1 += v.z;
+      S2 += v.w;
+    }
+  }
+  const uint32_t wlast = wave_max(last);
+  if ((threadIdx.x & 63) == 0) atomicMax(&s_maxlast, wlast);
+  __syncthreads();
+  if (threadIdx.x == 0) bs.tile_nch[tile] = (s_maxlast + bs.chunk - 1) / bs.chunk;
 }
 
 // ------------------------------------------------------------- reductions
@@ -273,12 +334,9 @@ __device__ __forceinline__ void wave_sum9_to_lds(const float (&g)[kG2D], float (
   }
 }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-  return v;
-}
-
+// One work item = one chunk of `chunk` list positions of one tile, walked
+// back to front from the state the forward saved where the next chunk begins
+// (or from the pixel's final state for the tile's last chunk).
 template <int TW>
 __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings ds, const Rec* __restrict__ rec,
                                                       const uint2* __restrict__ ranges,
@@ -287,7 +345,11 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
   __shared__ BatchLDS L;
   __shared__ float s_g[kG2D][kBlock];  // per staged Gaussian, summed over the four wavefronts
   __shared__ uint32_t s_maxlast;
-  const int tile = blockIdx.x;
+  if (blockIdx.x >= *bs.n_items) return;  // uniform
+  const uint2 item = bs.items[blockIdx.x];
+  const int tile = (int)item.x;
+  const uint32_t chunk = bs.chunk;
+  const uint32_t cstart = item.y * chunk;  // list positions [cstart, cstart + chunk) of the tile
   const int vi = find_view(vt, tile);
   const ViewDesc& vd = vt.v[vi];
   const int local = tile - vd.tile_base;
@@ -300,90 +362,95 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const uint32_t* list4 = reinterpret_cast<const uint32_t*>(L.list[wv]);
 
-  float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+  float Tf = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
   uint32_t last = 0;
   if (inside) {
     const int64_t HW = (int64_t)vd.W * vd.H;
     const int64_t pix = (int64_t)py * vd.W + px;
-    T = bs.T_final[vd.pix_base + pix];
+    Tf = bs.T_final[vd.pix_base + pix];
     last = bs.last[vd.pix_base + pix];
     dC0 = vd.dimg[pix];
     dC1 = vd.dimg[HW + pix];
     dC2 = vd.dimg[2 * HW + pix];
   }
-  // colour behind the current Gaussian, starting with the background seen through T_final
-  float S0 = T * ds.bg[0], S1 = T * ds.bg[1], S2 = T * ds.bg[2];
   if (threadIdx.x == 0) s_maxlast = 0;
 #pragma unroll
   for (int k = 0; k < kG2D; k++) s_g[k][threadIdx.x] = 0.f;
   __syncthreads();
-  const uint32_t wlast = wave_max(last);
+  const uint32_t wlast = __builtin_amdgcn_readfirstlane(wave_max(last));
   if (l == 0) atomicMax(&s_maxlast, wlast);
   __syncthreads();
   const uint2 rg = ranges[tile];
-  const uint32_t end = rg.x + s_maxlast;
+  const uint32_t maxlast = s_maxlast;
+  // state behind the chunk: transmittance T in front of it and the colour S
+  // behind it (background included), carried as D = dL/dC . S
+  float T = Tf;
+  float S0 = Tf * ds.bg[0], S1 = Tf * ds.bg[1], S2 = Tf * ds.bg[2];
+  if (cstart + chunk < maxlast) {
+    const int64_t slot = (int64_t)(rg.x + cstart + chunk) / chunk;
+    const float4 st = slot < bs.nbound ? bs.bound[slot * kBlock + threadIdx.x] : make_float4(1.f, 0.f, 0.f, 0.f);
+    T = st.x;
+    S0 += st.y;
+    S1 += st.z;
+    S2 += st.w;
+  }
+  float D = dC0 * S0 + dC1 * S1 + dC2 * S2;
+  const uint32_t cend = min(cstart + chunk, maxlast);
   const float kq = -0.5f * kLog2e;
 
-  for (uint32_t bend = end; bend > rg.x;) {
-    const uint32_t b0 = (bend - rg.x > (uint32_t)batch) ? bend - batch : rg.x;
+  for (uint32_t bend = rg.x + cend; bend > rg.x + cstart;) {
+    const uint32_t b0 = (bend - (rg.x + cstart) > (uint32_t)batch) ? bend - batch : rg.x + cstart;
     const uint32_t nb = bend - b0;
     const uint32_t wn = stage_batch<TW>(L, rec, pval, b0, nb, ox, oy);
     const uint32_t pos0 = b0 - rg.x;
-    for (int g4 = (int)((wn + 3) / 4) - 1; g4 >= 0; g4--) {
-      const uint32_t w4 = list4[g4];
-      uint32_t js[4];
-      float4 A[4], B[4], Cc[4];
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        js[u] = (w4 >> (8 * u)) & 255u;
-        A[u] = L.rec[js[u]].a;
-        B[u] = L.rec[js[u]].b;
-        Cc[u] = L.rec[js[u]].c;
-      }
+    // groups of four list slots, from the back
+    const uint32_t lw = list4[l];
+    const int ng = (int)((wn + 3) >> 2);
+    auto grad = [&](const Group4& G, int g) {
 #pragma unroll
       for (int u = 3; u >= 0; u--) {
-        if ((uint32_t)(4 * g4 + u) >= wn) continue;
-        const uint32_t j = js[u];
+        if ((uint32_t)(4 * g + u) >= wn) continue;
+        const uint32_t j = G.j[u];
         const uint32_t pos = pos0 + j;
         if (pos >= wlast) continue;  // no pixel of this wavefront reached it
-        float g[kG2D];
-#pragma unroll
-        for (int i = 0; i < kG2D; i++) g[i] = 0.f;
-        bool contrib = false;
-        if (pos < last) {
-          const float dx = fx - A[u].x, dy = fy - A[u].y;
-          const float p = log2_alpha(A[u], B[u], dx, dy);
-          if (p >= kLog2AlphaMin) {
-            contrib = true;
-            const float araw = exp2_fast(p);
-            const float a = fminf(kAlphaMax, araw);
-            const float ro = rcp_fast(1.0f - a);
-            const float Tb = T * ro;  // transmittance in front of this Gaussian
-            const float wgt = a * Tb;
-            g[6] = dC0 * wgt;
-            g[7] = dC1 * wgt;
-            g[8] = dC2 * wgt;
-            const float dl_da = dC0 * (Cc[u].x * Tb - S0 * ro) + dC1 * (Cc[u].y * Tb - S1 * ro) +
-                                dC2 * (Cc[u].z * Tb - S2 * ro);
-            S0 += Cc[u].x * wgt;
-            S1 += Cc[u].y * wgt;
-            S2 += Cc[u].z * wgt;
-            T = Tb;
-            if (araw <= kAlphaMax) {
-              const float dl_dp = dl_da * araw;
-              g[5] = dl_dp * B[u].z;  // d alpha / d alpha_cond = exp(-q/2) = araw / alpha_cond
-              const float dl_dp2 = dl_dp * kLn2;
-              g[0] = -dl_dp2 * (2.f * A[u].z * dx + A[u].w * dy);
-              g[1] = -dl_dp2 * (A[u].w * dx + 2.f * B[u].x * dy);
-              g[2] = dl_dp2 * dx * dx;
-              g[3] = dl_dp2 * dx * dy;
-              g[4] = dl_dp2 * dy * dy;
-            }
-          }
-        }
+        // predicated rather than branched: the lanes of a wavefront rarely agree
+        const float4 A = G.a[u];
+        const float4 B = make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f);
+        const float dx = fx - A.x, dy = fy - A.y;
+        const float p = log2_alpha(A, B, dx, dy);
+        const bool contrib = pos < last && p >= kLog2AlphaMin;
         if (__ballot(contrib) == 0) continue;
-        wave_sum9_to_lds(g, s_g, (int)j, l);
+        const float araw = exp2_fast(p);
+        const float a = fminf(kAlphaMax, araw);
+        const float ro = rcp_fast(1.0f - a);
+        const float Tb = T * ro;  // transmittance in front of this Gaussian
+        const float wgt = contrib ? a * Tb : 0.f;
+        const float dc = dC0 * G.c[u].x + dC1 * G.c[u].y + dC2 * G.c[u].z;
+        const float dl_da = Tb * dc - ro * D;  // dL/dC . (c T_front - S_behind / (1 - alpha))
+        D += dc * wgt;
+        T = contrib ? Tb : T;
+        // d alpha / d(exponent) = alpha while alpha is below its clamp, zero above
+        const float dl_dp = (contrib && araw <= kAlphaMax) ? dl_da * araw : 0.f;
+        const float e0 = dl_dp * dx, e1 = dl_dp * dy;
+        // moments of dL/d(exponent) over the lanes; the mean and opacity gradients
+        // are formed from them once per Gaussian after the reduction
+        float gv[kG2D];
+        gv[0] = e0;
+        gv[1] = e1;
+        gv[2] = e0 * dx;
+        gv[3] = e0 * dy;
+        gv[4] = e1 * dy;
+        gv[5] = dl_dp;
+        gv[6] = dC0 * wgt;
+        gv[7] = dC1 * wgt;
+        gv[8] = dC2 * wgt;
+        wave_sum9_to_lds(gv, s_g, (int)j, l);
       }
+    };
+    for (int g = ng - 1; g >= 0; g--) {
+      Group4 X;
+      fetch_group(L, lw, (uint32_t)g, X);
+      grad(X, g);
     }
     __syncthreads();
     // one set of global atomics per (tile, Gaussian); the conic gradient goes
@@ -399,13 +466,18 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
         any |= v[k] != 0.f;
       }
       if (any) {
-        float* dst = g2d + (int64_t)__float_as_uint(L.rec[t].b.w) * kG2D;
-        unsafeAtomicAdd(dst + 0, v[0]);
-        unsafeAtomicAdd(dst + 1, v[1]);
-        unsafeAtomicAdd(dst + 2, v[2] * kq);
-        unsafeAtomicAdd(dst + 3, v[3] * kq);
-        unsafeAtomicAdd(dst + 4, v[4] * kq);
-        unsafeAtomicAdd(dst + 5, v[5]);
+        // exponent p2 = log2(alpha) = cA dx^2 + cB dx dy + cC dy^2 + log2(alpha_cond), with
+        // dx = x - u: dp2/du = -(2 cA dx + cB dy), dp2/dv = -(cB dx + 2 cC dy); and
+        // dp2/dcA = dx^2 etc., cA = kq Qxx, cB = 2 kq Qxy, cC = kq Qyy
+        const Staged& sr = L.rec[t];
+        const float m0 = v[0] * kLn2, m1 = v[1] * kLn2;  // moments of dL/dp2 = dL/dp ln 2
+        float* dst = g2d + (int64_t)__float_as_uint(sr.b.w) * kG2D;
+        unsafeAtomicAdd(dst + 0, -(2.f * sr.a.z * m0 + sr.a.w * m1));
+        unsafeAtomicAdd(dst + 1, -(sr.a.w * m0 + 2.f * sr.b.x * m1));
+        unsafeAtomicAdd(dst + 2, v[2] * (kLn2 * kq));
+        unsafeAtomicAdd(dst + 3, v[3] * (kLn2 * kq));
+        unsafeAtomicAdd(dst + 4, v[4] * (kLn2 * kq));
+        unsafeAtomicAdd(dst + 5, v[5] * sr.b.z);  // d alpha / d alpha_cond = alpha / alpha_cond
         unsafeAtomicAdd(dst + 6, v[6]);
         unsafeAtomicAdd(dst + 7, v[7]);
         unsafeAtomicAdd(dst + 8, v[8]);
@@ -430,9 +502,9 @@ void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec,
 }
 
 void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
-                      const uint32_t* pval, BlendState bs, float* g2d, int batch, hipStream_t st) {
-  if (vt.total_tiles <= 0) return;
-  const dim3 grid(vt.total_tiles);
+                      const uint32_t* pval, BlendState bs, float* g2d, int batch, int64_t items, hipStream_t st) {
+  if (vt.total_tiles <= 0 || items <= 0) return;
+  const dim3 grid((unsigned)items);
   switch (vt.tile_w) {
     case 8: hipLaunchKernelGGL(k_blend_bwd<8>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs, g2d, batch); break;
     case 32: hipLaunchKernelGGL(k_blend_bwd<32>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs, g2d, batch); break;

@@ -134,6 +134,7 @@ struct SortBuffers {
   uint32_t* rstate_depth;  // [sort_state_words(E, false)] state of the scans and the depth sort
   uint32_t* rstate_pairs;  // [sort_state_words(pcap, true)] radix state of the tile sort
   uint32_t* blk_start;     // [sort_block_starts(pcap)] first sorted entry of each emission block
+  uint32_t* chunk_state;   // [chunk_scan_words(total_tiles)] state of the backward work-item scan
   uint32_t* counters;      // [0] binned entries, [1] pairs, [2] overflow flag, [3] sort look-back timeout
   // where the sorted results ended up (index into the ping-pong pairs)
   int dsorted, psorted;
@@ -155,15 +156,35 @@ void launch_import_records(const float* u, const float* v, const float* ex, cons
                            const int32_t* alive, const ViewTable& vt, Rec* rec, uint32_t* tiles, hipStream_t st);
 
 // blend.hip
+// The backward splits each tile's list into work items of `chunk` list
+// positions (a power of two and a multiple of the LDS batch); the forward
+// saves each tile pixel's transmittance, and the colour behind, where a chunk
+// begins.
 struct BlendState {
-  float* T_final;     // [pixels]
-  uint32_t* last;     // [pixels]
-  uint32_t* counts;   // [pixels] or nullptr
+  uint32_t chunk;
+  float* T_final;      // [pixels]
+  uint32_t* last;      // [pixels] 1-based list position of the last contributor (0: none)
+  uint32_t* counts;    // [pixels] or nullptr
+  float4* bound;       // [nbound][kBlock] per tile pixel at each chunk start after the first: the
+                       // transmittance there and the colour of everything behind it (background
+                       // excluded); slot = absolute pair position / chunk (unique per boundary)
+  int64_t nbound;
+  uint32_t* tile_nch;  // [total_tiles] backward work items per tile
+  uint2* items;        // [items_cap] (tile, chunk) backward work items
+  int64_t items_cap;
+  uint32_t* n_items;   // device count of items
 };
 void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
                       const uint32_t* pval, BlendState bs, int batch, hipStream_t st);
+// `grid` bounds the number of backward work items (pairs / chunk + tiles).
 void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
-                      const uint32_t* pval, BlendState bs, float* g2d, int batch, hipStream_t st);
+                      const uint32_t* pval, BlendState bs, float* g2d, int batch, int64_t grid, hipStream_t st);
+// sort.hip: the backward work items (tile, chunk) of every tile, from the
+// forward's per-tile chunk counts.  `state` holds chunk_scan_words(tiles)
+// words zeroed by the stage's preparation.
+void launch_chunk_items(const uint32_t* tile_nch, int64_t total_tiles, uint2* items, int64_t items_cap,
+                        uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st);
+int64_t chunk_scan_words(int64_t total_tiles);
 
 // train.hip
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,

@@ -242,10 +242,12 @@ __global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, uint2* __r
                                                        const uint32_t* __restrict__ tiles,
                                                        const uint32_t* __restrict__ dval,
                                                        const uint32_t* __restrict__ poff, uint32_t pcap,
-                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start) {
+                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start,
+                                                       uint32_t* __restrict__ extra, int64_t extra_words) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t w4 = rs.words() / 4;
   if (i < w4) reinterpret_cast<uint4*>(rs.ghist)[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (extra && i < extra_words) extra[i] = 0u;
   if (ranges && i < nranges) ranges[i] = make_uint2(0u, 0u);
   if (blk_start && i < (int64_t)counters[0] && counters[1] <= pcap) {
     const uint32_t o = poff[i];
@@ -547,7 +549,7 @@ void launch_bin_count(SortBuffers& b, hipStream_t st) {
   const unsigned gprep = (unsigned)((rs.words() / 4 + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_stage_prep, dim3(gprep), dim3(kBlock), 0, st, rs, (uint2*)nullptr, (int64_t)0,
                      (const uint32_t*)b.counters, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
-                     (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0);
+                     (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0, (uint32_t*)nullptr, (int64_t)0);
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
   scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.rec, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
               rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
@@ -565,13 +567,15 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
   const RadixPlan plan = radix_plan(bits);
   const int64_t bound = pairs_hint < b.pcap ? pairs_hint : b.pcap;
   const RadixState rs = radix_state(b.rstate_pairs, bound, kRItems, false);
+  const int64_t cwords = chunk_scan_words(vt.total_tiles);
   int64_t prep = rs.words() / 4;
   if (prep < vt.total_tiles) prep = vt.total_tiles;
   if (prep < b.E) prep = b.E;
+  if (prep < cwords) prep = cwords;
   hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs, b.ranges,
                      (int64_t)vt.total_tiles, (const uint32_t*)b.counters, (const uint32_t*)b.tiles,
                      (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.poff, (uint32_t)b.pcap, b.blk_start,
-                     rs.nblk);
+                     rs.nblk, b.chunk_state, cwords);
   if (rs.nblk)
     hipLaunchKernelGGL(k_emit, dim3((unsigned)rs.nblk), dim3(kBlock), 0, st, vt, b.rec, b.dval[b.dsorted], b.poff,
                        b.blk_start, b.counters, (uint32_t)b.pcap, plan.npass, plan.dbits, rs.ghist, b.pkey[0],
@@ -581,6 +585,30 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
   if (gp)
     hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
                        (uint32_t)vt.total_tiles, b.ranges);
+}
+
+namespace {
+struct TileChunks {
+  const uint32_t* nch;
+  __device__ uint32_t operator()(int64_t i) const { return nch[i]; }
+};
+struct ExpandItems {
+  uint2* items;
+  uint32_t cap;
+  __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const {
+    for (uint32_t k = 0; k < v; k++)
+      if (pre + k < cap) items[pre + k] = make_uint2((uint32_t)i, k);
+  }
+};
+}  // namespace
+
+int64_t chunk_scan_words(int64_t total_tiles) { return 2 + 2 * ((total_tiles + kChunk - 1) / kChunk + 1); }
+
+void launch_chunk_items(const uint32_t* tile_nch, int64_t total_tiles, uint2* items, int64_t items_cap,
+                        uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st) {
+  const uint32_t T = (uint32_t)total_tiles;
+  scan1<false>(TileChunks{tile_nch}, ExpandItems{items, (uint32_t)items_cap}, nullptr, T, T, total_tiles, state,
+               reinterpret_cast<uint64_t*>(state + 2), n_items, (uint32_t*)nullptr, err, st);
 }
 
 int64_t sort_state_words(int64_t bound, bool pairs) {

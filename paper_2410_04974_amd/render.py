@@ -20,9 +20,9 @@ class Renderer:
     of the last forward)."""
 
     def __init__(self, lambda_opa=0.35, z_near=0.2, bg=(0.0, 0.0, 0.0), tile=(16, 16), batch=256,
-                 pair_capacity=0, flags=0):
+                 pair_capacity=0, flags=0, chunk=256):
         self.ctx = _lib.Context(lambda_opa=lambda_opa, z_near=z_near, bg=bg, tile_w=tile[0], tile_h=tile[1],
-                                batch=batch, pair_capacity=pair_capacity, flags=flags)
+                                batch=batch, pair_capacity=pair_capacity, flags=flags, chunk=chunk)
 
     def configure(self, **kw):
         if "tile" in kw:
