@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib6dgs.so")
+# SIXDGS_LIB selects another build of the same library (e.g. to compare two builds)
+LIB_PATH = os.environ.get("SIXDGS_LIB", os.path.join(_HERE, "lib6dgs.so"))
 
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_STATE = range(6)
 MAX_VIEWS = 16

@@ -134,21 +134,42 @@ __device__ __forceinline__ void st_store64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ uint32_t look_back64(const uint64_t* status, int64_t blk, uint32_t* err) {
+// Exclusive prefix over workgroups [0, blk) from their look-back words at
+// status[j * stride] (an aggregate of workgroup j alone, or an inclusive
+// prefix through it).  A window of predecessors is read per round trip and
+// summed nearest first until an inclusive word; a word not yet published is
+// waited on, boundedly (a timeout sets *err and gives up).
+constexpr int kLookWin = 8;
+
+__device__ __forceinline__ bool lb_incl(uint32_t s) { return (s & kStIncl) != 0; }
+__device__ __forceinline__ uint32_t lb_val(uint32_t s) { return s & kStVal; }
+__device__ __forceinline__ uint32_t lb_load(const uint32_t* p) { return st_load(p); }
+__device__ __forceinline__ bool lb_incl(uint64_t s) { return (s & kSc64Incl) != 0; }
+__device__ __forceinline__ uint32_t lb_val(uint64_t s) { return (uint32_t)s; }
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) { return st_load64(p); }
+
+template <class W>
+__device__ uint32_t look_back(const W* status, int64_t stride, int64_t blk, uint32_t* err) {
   uint32_t excl = 0;
-  for (int64_t j = blk - 1; j >= 0; j--) {
-    uint64_t s = 0;
-    for (int spin = 0; spin < kMaxSpin; spin++) {
-      s = st_load64(status + j);
-      if (s) break;
-      __builtin_amdgcn_s_sleep(1);
+  for (int64_t j = blk - 1; j >= 0; j -= kLookWin) {
+    W s[kLookWin];
+#pragma unroll
+    for (int k = 0; k < kLookWin; k++) s[k] = (j - k >= 0) ? lb_load(status + (j - k) * stride) : W(0);
+#pragma unroll
+    for (int k = 0; k < kLookWin; k++) {
+      if (j - k < 0) return excl;  // not reached: the first workgroup publishes an inclusive word
+      W v = s[k];
+      for (int spin = 0; !v && spin < kMaxSpin; spin++) {
+        __builtin_amdgcn_s_sleep(1);
+        v = lb_load(status + (j - k) * stride);
+      }
+      if (!v) {
+        atomicOr(err, 1u);
+        return excl;
+      }
+      excl += lb_val(v);
+      if (lb_incl(v)) return excl;
     }
-    if (!s) {
-      atomicOr(err, 1u);
-      break;
-    }
-    excl += (uint32_t)s;
-    if (s & kSc64Incl) break;
   }
   return excl;
 }
@@ -195,7 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_scan1(F f, G g, const uint32_t* coun
       st_store64(my, kSc64Incl | total);
     } else {
       st_store64(my, kSc64Agg | total);
-      excl = look_back64(status, blk, err);
+      excl = look_back(status, 1, blk, err);
       st_store64(my, kSc64Incl | (uint32_t)(excl + total));
     }
     s_pre = excl;
@@ -338,22 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
   // exclusive prefix of this digit over the earlier workgroups
   uint32_t excl = 0;
   if (own && blk > 0) {
-    int64_t j = blk - 1;
-    for (;;) {
-      uint32_t s = 0;
-      for (int spin = 0; spin < kMaxSpin; spin++) {
-        s = st_load(status + j * 256 + t);
-        if (s) break;
-        __builtin_amdgcn_s_sleep(1);
-      }
-      if (!s) {
-        atomicOr(err, 1u);
-        break;
-      }
-      excl += s & kStVal;
-      if ((s & kStIncl) || j == 0) break;
-      j--;
-    }
+    excl = look_back(status + t, 256, blk, err);
     st_store(my, kStIncl | (excl + tot));
   }
   const uint32_t gex = block_scan_excl(gh, total);
