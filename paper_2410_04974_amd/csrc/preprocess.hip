@@ -288,7 +288,11 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
   if (g >= n) return;
   bool any = false;
   for (int vi = 0; vi < vt.nview; vi++) any |= tiles[(int64_t)vi * n + g] > 0;
-  if (!any) {
+  // Only a wavefront with no visible Gaussian leaves early: its lanes store
+  // together.  Otherwise invisible lanes run along with zero accumulators
+  // (every view is skipped), so each gradient row is written by one store
+  // of the whole wavefront instead of two partial ones.
+  if (__ballot(any) == 0) {
     for (int r = 0; r < kRows; r++) sink.put(r, n, g, 0.f);
     return;
   }
@@ -300,6 +304,8 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
 #pragma unroll
     for (int c = 0; c < 3; c++) beta[k][c] = params[(kRowSH + 3 * k + c) * n + g];
 
+  // an invisible lane's rows are exact zeros whatever its parameters
+  auto put = [&](int row, float v) { sink.put(row, n, g, any ? v : 0.f); };
   // accumulators summed over views
   float g_beta[16][3];
 #pragma unroll
@@ -472,18 +478,18 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
       const float Lij = s.L[tri(i, j)];
       // exp on the diagonal; 2 sigmoid(r) - 1 elsewhere, whose derivative is (1 - L)(1 + L)/2
       const float graw = (i == j) ? gl * Lij : gl * 0.5f * (1.f - Lij) * (1.f + Lij);
-      sink.put(kRowL + tri(i, j), n, g, graw);
+      put(kRowL + tri(i, j), graw);
     }
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    sink.put(kRowMuP + k, n, g, g_mup[k]);
-    sink.put(kRowMuD + k, n, g, g_mud[k]);
+    put(kRowMuP + k, g_mup[k]);
+    put(kRowMuD + k, g_mud[k]);
   }
 #pragma unroll
   for (int k = 0; k < 16; k++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) sink.put(kRowSH + 3 * k + c, n, g, g_beta[k][c]);
-  sink.put(kRowOpa, n, g, g_alpha * s.alpha * (1.f - s.alpha));
+    for (int c = 0; c < 3; c++) put(kRowSH + 3 * k + c, g_beta[k][c]);
+  put(kRowOpa, g_alpha * s.alpha * (1.f - s.alpha));
   if (densify) {
     densify[g] += dens_norm;
     densify[n + g] += dens_cnt;
