@@ -16,6 +16,9 @@ FLAGS = [
     # no packed-fp32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    # the atomics here either have per-lane addresses or one active lane; the
+    # compiler's wavefront-combining rewrite only adds a readlane loop
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

@@ -334,6 +334,37 @@ __device__ __forceinline__ void wave_sum9_to_lds(const float (&g)[kG2D], float (
   }
 }
 
+// The same for two Gaussians at once (18 values, slots ja and jb): after the
+// swap stages the rows of k0..k4 hold (a0 a2 a1 a3), (a4 a6 a5 a7),
+// (a8 b0 b8 b1), (b2 b4 b3 b5) and (b6 b6 b7 b7).
+__device__ __forceinline__ void wave_sum18_to_lds(const float (&a)[kG2D], const float (&b)[kG2D],
+                                                  float (*s_g)[kBlock], int ja, int jb, int lane) {
+  const float h0 = swap32_add(a[0], a[1]);
+  const float h1 = swap32_add(a[2], a[3]);
+  const float h2 = swap32_add(a[4], a[5]);
+  const float h3 = swap32_add(a[6], a[7]);
+  const float h4 = swap32_add(a[8], b[8]);
+  const float h5 = swap32_add(b[0], b[1]);
+  const float h6 = swap32_add(b[2], b[3]);
+  const float h7 = swap32_add(b[4], b[5]);
+  const float h8 = swap32_add(b[6], b[7]);
+  const float k0 = row_sum(swap16_add(h0, h1));
+  const float k1 = row_sum(swap16_add(h2, h3));
+  const float k2 = row_sum(swap16_add(h4, h5));
+  const float k3 = row_sum(swap16_add(h6, h7));
+  const float k4 = row_sum(swap16_add(h8, h8));
+  if ((lane & 15) == 0) {
+    const int row = lane >> 4;
+    const int f0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+    atomicAdd(&s_g[f0][ja], k0);
+    atomicAdd(&s_g[f0 + 4][ja], k1);
+    const int f2 = (row == 1) ? 0 : (row == 3) ? 1 : 8;
+    atomicAdd(&s_g[f2][row == 0 ? ja : jb], k2);
+    atomicAdd(&s_g[f0 + 2][jb], k3);
+    if ((row & 1) == 0) atomicAdd(&s_g[6 + (row >> 1)][jb], k4);
+  }
+}
+
 // One work item = one chunk of `chunk` list positions of one tile, walked
 // back to front from the state the forward saved where the next chunk begins
 // (or from the pixel's final state for the tile's last chunk).
@@ -406,45 +437,57 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
     // groups of four list slots, from the back
     const uint32_t lw = list4[l];
     const int ng = (int)((wn + 3) >> 2);
+    // one Gaussian of the reverse walk: updates T and D, fills the per-lane
+    // values to sum, and says (uniformly) whether any lane contributed
+    auto eval = [&](const Group4& G, int g, int u, float (&gv)[kG2D]) -> bool {
+      if ((uint32_t)(4 * g + u) >= wn) return false;
+      const uint32_t pos = pos0 + G.j[u];
+      if (pos >= wlast) return false;  // no pixel of this wavefront reached it
+      // predicated rather than branched: the lanes of a wavefront rarely agree
+      const float4 A = G.a[u];
+      const float4 B = make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f);
+      const float dx = fx - A.x, dy = fy - A.y;
+      const float p = log2_alpha(A, B, dx, dy);
+      const bool contrib = pos < last && p >= kLog2AlphaMin;
+      if (__ballot(contrib) == 0) return false;
+      const float araw = exp2_fast(p);
+      const float a = fminf(kAlphaMax, araw);
+      const float ro = rcp_fast(1.0f - a);
+      const float Tb = T * ro;  // transmittance in front of this Gaussian
+      const float wgt = contrib ? a * Tb : 0.f;
+      const float dc = dC0 * G.c[u].x + dC1 * G.c[u].y + dC2 * G.c[u].z;
+      const float dl_da = Tb * dc - ro * D;  // dL/dC . (c T_front - S_behind / (1 - alpha))
+      D += dc * wgt;
+      T = contrib ? Tb : T;
+      // d alpha / d(exponent) = alpha while alpha is below its clamp, zero above
+      const float dl_dp = (contrib && araw <= kAlphaMax) ? dl_da * araw : 0.f;
+      const float e0 = dl_dp * dx, e1 = dl_dp * dy;
+      // moments of dL/d(exponent) over the lanes; the mean and opacity gradients
+      // are formed from them once per Gaussian after the reduction
+      gv[0] = e0;
+      gv[1] = e1;
+      gv[2] = e0 * dx;
+      gv[3] = e0 * dy;
+      gv[4] = e1 * dy;
+      gv[5] = dl_dp;
+      gv[6] = dC0 * wgt;
+      gv[7] = dC1 * wgt;
+      gv[8] = dC2 * wgt;
+      return true;
+    };
+    // back to front in pairs, reduced together when both contributed
     auto grad = [&](const Group4& G, int g) {
 #pragma unroll
-      for (int u = 3; u >= 0; u--) {
-        if ((uint32_t)(4 * g + u) >= wn) continue;
-        const uint32_t j = G.j[u];
-        const uint32_t pos = pos0 + j;
-        if (pos >= wlast) continue;  // no pixel of this wavefront reached it
-        // predicated rather than branched: the lanes of a wavefront rarely agree
-        const float4 A = G.a[u];
-        const float4 B = make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f);
-        const float dx = fx - A.x, dy = fy - A.y;
-        const float p = log2_alpha(A, B, dx, dy);
-        const bool contrib = pos < last && p >= kLog2AlphaMin;
-        if (__ballot(contrib) == 0) continue;
-        const float araw = exp2_fast(p);
-        const float a = fminf(kAlphaMax, araw);
-        const float ro = rcp_fast(1.0f - a);
-        const float Tb = T * ro;  // transmittance in front of this Gaussian
-        const float wgt = contrib ? a * Tb : 0.f;
-        const float dc = dC0 * G.c[u].x + dC1 * G.c[u].y + dC2 * G.c[u].z;
-        const float dl_da = Tb * dc - ro * D;  // dL/dC . (c T_front - S_behind / (1 - alpha))
-        D += dc * wgt;
-        T = contrib ? Tb : T;
-        // d alpha / d(exponent) = alpha while alpha is below its clamp, zero above
-        const float dl_dp = (contrib && araw <= kAlphaMax) ? dl_da * araw : 0.f;
-        const float e0 = dl_dp * dx, e1 = dl_dp * dy;
-        // moments of dL/d(exponent) over the lanes; the mean and opacity gradients
-        // are formed from them once per Gaussian after the reduction
-        float gv[kG2D];
-        gv[0] = e0;
-        gv[1] = e1;
-        gv[2] = e0 * dx;
-        gv[3] = e0 * dy;
-        gv[4] = e1 * dy;
-        gv[5] = dl_dp;
-        gv[6] = dC0 * wgt;
-        gv[7] = dC1 * wgt;
-        gv[8] = dC2 * wgt;
-        wave_sum9_to_lds(gv, s_g, (int)j, l);
+      for (int h = 1; h >= 0; h--) {
+        float ga[kG2D], gb[kG2D];
+        const bool aa = eval(G, g, 2 * h + 1, ga);
+        const bool ab = eval(G, g, 2 * h, gb);
+        if (aa && ab)
+          wave_sum18_to_lds(ga, gb, s_g, (int)G.j[2 * h + 1], (int)G.j[2 * h], l);
+        else if (aa)
+          wave_sum9_to_lds(ga, s_g, (int)G.j[2 * h + 1], l);
+        else if (ab)
+          wave_sum9_to_lds(gb, s_g, (int)G.j[2 * h], l);
       }
     };
     for (int g = ng - 1; g >= 0; g--) {
