@@ -240,3 +240,26 @@ def test_backward_matches_oracle_gradient(name, n, size):
     errs = _group_errors(g, ref)
     _say(name, "grad rel err per group", {k: f"{v:.2e}" for k, v in errs.items()})
     assert all(v < 1e-3 for v in errs.values())
+
+
+@pytest.mark.parametrize("batch", [256, 64])
+def test_backward_chunk_lengths_agree(batch):
+    """The backward walks each tile's list in work items of `chunk` positions,
+    restarted from state the forward saved; any chunk length gives the same
+    gradient up to float32 rounding (c1 at full size: heavy tiles span many
+    chunks).  The default chunk is also the one the oracle comparisons and
+    the finite-difference check use."""
+    w, pn = G.scene("c1")
+    cam = w.cameras[0]
+    dl = torch.from_numpy(synth.upstream_gradient([cam])[0]).to(G.DEV)
+    p = G.to_dev(pn)
+    grads = {}
+    for chunk in (batch, 1024, 16384):
+        r = G.renderer(batch=batch, chunk=chunk)
+        r.forward(p, [cam])
+        grads[chunk] = r.backward(p, [dl]).cpu().numpy().astype(np.float64)
+    ref = grads[16384]
+    for chunk in (batch, 1024):
+        errs = _group_errors(grads[chunk], ref)
+        _say("batch", batch, "chunk", chunk, "vs one chunk per tile", {k: f"{v:.1e}" for k, v in errs.items()})
+        assert all(v < 2e-5 for v in errs.values())
