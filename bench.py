@@ -47,10 +47,11 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a kernel of known traffic that "
                          "scales the HBM byte counters of a profiler run)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "render"],
                     help="c2: the training-step benchmark (default); c3: 16 uneven views batched in one "
                          "captured forward+backward vs 16 per-view launches; c4: 8-view training steps "
-                         "from a 64-camera 1920x1080 pool, one captured graph per camera group")
+                         "from a 64-camera 1920x1080 pool, one captured graph per camera group; render: "
+                         "forward-only frames per second on two 1408x1408 scenes")
     return ap.parse_args()
 
 
@@ -73,6 +74,8 @@ def main():
         return bench_c3(args)
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "render":
+        return bench_render(args)
 
     import numpy as np
     import torch
@@ -327,6 +330,40 @@ def bench_c4(args):
                                   "8 views per step, L1 + Adam + densification statistics",
                       "pairs_max": pmax},
            "final_loss": float(tr.loss), "densify_visible_max": float(dens[1].max())}
+    print(json.dumps(out), flush=True)
+
+
+def bench_render(args):
+    """Forward-only renders (slice, projection, binning and sort, blending) of
+    two 1408x1408 scenes, frames per second; the pair capacity is fixed from a
+    first render, so a frame has no host waits."""
+    import torch
+
+    import synth
+    from paper_2410_04974_amd import Renderer
+
+    res = {}
+    for name in ("r1", "r2"):
+        w = synth.workload(name)
+        cam = w.cameras[0]
+        params = torch.from_numpy(synth.make_scene(w.scene)).to("cuda:0")
+        r = Renderer()
+        img = [torch.empty((3, cam.height, cam.width), device="cuda:0")]
+        r.forward(params, [cam], out=img)
+        torch.cuda.synchronize()
+        sizes = r.ctx.sizes()
+        r.configure(pair_capacity=int(sizes["pairs"] * 1.5) + 4096)
+        for _ in range(args.warmup):
+            r.forward(params, [cam], out=img)
+        ms = _timed(lambda: r.forward(params, [cam], out=img), args.steps)
+        r.ctx.check()
+        res[name] = {"fps": round(1e3 / ms, 2), "ms_per_frame": round(ms, 4),
+                     "mpixels_per_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 3),
+                     "gaussians": int(w.scene.n), "pairs": int(sizes["pairs"]), "description": w.description}
+    out = {"metric": "forward render frames/sec at 1408x1408 (render only)", "workload": "render",
+           "value": res["r2"]["fps"], "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["r2"]["ms_per_frame"], "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None, "config": {"workload": "r2: " + res["r2"]["description"]}, "scenes": res}
     print(json.dumps(out), flush=True)
 
 

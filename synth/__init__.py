@@ -218,8 +218,8 @@ class Workload:
 
 
 def workload(name: str, n_override: int | None = None) -> Workload:
-    """The five synthetic workloads; ``n_override`` shrinks N for quick tests
-    while keeping the recipe."""
+    """The synthetic workloads (c0-c4, and the render-only r1, r2);
+    ``n_override`` shrinks N for quick tests while keeping the recipe."""
     if name == "c0":
         spec = SceneSpec(n=1000)
         cams = [default_camera(128, 128)]
@@ -242,6 +242,16 @@ def workload(name: str, n_override: int | None = None) -> Workload:
         cams = fibonacci_cameras(64, [(1920, 1080)])
         desc = ("1M 6D Gaussians (70% sphere, 30% U[-2,2]^3), direction diagonal exp(N(-2,0.5)), "
                 "64-camera 1920x1080 pool, 8 views per step")
+    elif name == "r1":
+        # render only, shaped like the paper's small volumetric scenes (~10^4 points, 1408^2 views)
+        spec = SceneSpec(n=12_657, means="cube", l_spatial_diag=(-2.0, 0.5), logit=(-1.0, 1.0))
+        cams = [default_camera(1408, 1408)]
+        desc = "12,657 6D Gaussians filling [-1,1]^3 (volumetric), one 1408x1408 camera, forward only"
+    elif name == "r2":
+        # render only, shaped like the paper's larger object scenes (~1.7e5 points, 1408^2 views)
+        spec = SceneSpec(n=174_746, means="sphere")
+        cams = [default_camera(1408, 1408)]
+        desc = "174,746 6D Gaussians on a noisy unit sphere, one 1408x1408 camera, forward only"
     else:
         raise ValueError(name)
     if n_override is not None:

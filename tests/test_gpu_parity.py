@@ -191,7 +191,7 @@ def test_forward_ragged_multi_tile_scene_with_background():
     _compare_pixels(imgs[0], T, ref, refT, amb, "ragged")
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "r1", "r2"])
 def test_forward_sampled_pixels_full_size(name):
     """Full-size workload, 4096 seeded pixels against the oracle."""
     w, p = G.scene(name)
