@@ -65,7 +65,7 @@ class _Set(ctypes.Structure):
                 ("jac_guard", ctypes.c_double), ("dilation", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("t_min", ctypes.c_double), ("amb_alpha_min", ctypes.c_double),
                 ("amb_alpha_max", ctypes.c_double), ("amb_t_min", ctypes.c_double), ("amb_depth", ctypes.c_double),
-                ("amb_impact", ctypes.c_double)]
+                ("amb_impact", ctypes.c_double), ("lambda_raw", ctypes.c_void_p), ("grad_lambda", ctypes.c_void_p)]
 
 
 @dataclass
@@ -90,10 +90,13 @@ class Settings:
     amb_depth: float = 5e-7
     amb_impact: float = 2.5e-5
 
-    def _c(self) -> _Set:
+    def _c(self, lambda_raw=None, grad_lambda=None) -> _Set:
+        """C settings; lambda_raw / grad_lambda are float64 arrays the caller keeps alive."""
         return _Set(self.lambda_opa, self.z_near, (ctypes.c_double * 3)(*self.bg), self.jac_guard,
                     self.dilation, self.alpha_max, self.alpha_min, self.t_min, self.amb_alpha_min,
-                    self.amb_alpha_max, self.amb_t_min, self.amb_depth, self.amb_impact)
+                    self.amb_alpha_max, self.amb_t_min, self.amb_depth, self.amb_impact,
+                    None if lambda_raw is None else _ptr(lambda_raw),
+                    None if grad_lambda is None else _ptr(grad_lambda))
 
 
 _lib = None
@@ -140,12 +143,23 @@ def num_threads(req: int = 0) -> int:
     return int(lib().orc_num_threads(req))
 
 
-def preprocess(params, cam, settings: Settings = Settings()) -> dict:
-    """Per-Gaussian record for one camera: slice, colour, projection, extents."""
+def _lam(lambda_raw, n):
+    """Per-Gaussian raw lambda as a float64 array (or None: the scalar setting)."""
+    if lambda_raw is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(lambda_raw, np.float64).reshape(-1))
+    assert a.shape[0] == n
+    return a
+
+
+def preprocess(params, cam, settings: Settings = Settings(), lambda_raw=None) -> dict:
+    """Per-Gaussian record for one camera: slice, colour, projection, extents.
+    ``lambda_raw`` ([N] or None) gives each Gaussian lambda = sigmoid(raw)."""
     p = _params64(params)
     n = p.shape[1]
     rec = np.zeros((n, NREC), np.float64)
-    c, s = _cam(cam), settings._c()
+    lam = _lam(lambda_raw, n)
+    c, s = _cam(cam), settings._c(lam)
     lib().orc_preprocess(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), _ptr(rec))
     out = {}
     for k, (o, w) in FIELDS.items():
@@ -154,13 +168,14 @@ def preprocess(params, cam, settings: Settings = Settings()) -> dict:
     return out
 
 
-def render(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0):
+def render(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0, lambda_raw=None):
     """Brute-force render.  Returns (color, T_final, n_contrib, ambiguous); with
     ``pixels=None`` color is [3, H, W] and the others [H, W]; otherwise color is
     [npix, 3] and the others [npix] for the listed row-major pixel ids."""
     p = _params64(params)
     n = p.shape[1]
-    c, s = _cam(cam), settings._c()
+    lam = _lam(lambda_raw, n)
+    c, s = _cam(cam), settings._c(lam)
     full = pixels is None
     npix = cam.width * cam.height if full else len(pixels)
     pix = None if full else np.ascontiguousarray(np.asarray(pixels, np.int64))
@@ -178,14 +193,18 @@ def render(params, cam, settings: Settings = Settings(), pixels=None, nthreads: 
     return color, T, nc, amb.astype(bool)
 
 
-def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=None, nthreads: int = 0):
+def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=None, nthreads: int = 0,
+             lambda_raw=None):
     """Analytic gradient of sum(dl_dimage * image) w.r.t. the 76 raw parameter
     rows.  ``dl_dimage`` is [3, H, W] (pixels=None) or [npix, 3].  Returns
     (grad [76, N], g2d [N, 9]) with g2d the per-Gaussian screen-space gradients
-    (du, dv, dQxx, dQxy, dQyy, dalpha_cond, dr, dg, db)."""
+    (du, dv, dQxx, dQxy, dQyy, dalpha_cond, dr, dg, db); with ``lambda_raw``
+    also the gradient w.r.t. it ([N]) as a third element."""
     p = _params64(params)
     n = p.shape[1]
-    c, s = _cam(cam), settings._c()
+    lam = _lam(lambda_raw, n)
+    glam = None if lam is None else np.zeros(n, np.float64)
+    c, s = _cam(cam), settings._c(lam, glam)
     full = pixels is None
     if full:
         npix = cam.width * cam.height
@@ -201,7 +220,7 @@ def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=Non
                             _ptr(dl), _ptr(grad), _ptr(g2d), nthreads)
     if rc != 0:
         raise MemoryError("oracle backward failed")
-    return grad, g2d
+    return (grad, g2d) if lam is None else (grad, g2d, glam)
 
 
 def slice_gaussians(params, dirs, lambda_opa: float):

@@ -93,9 +93,19 @@ typedef struct {
   double amb_t_min;     /* |T' - t_min| */
   double amb_depth;     /* relative depth gap between consecutive contributors */
   double amb_impact;    /* smallest colour change a flip at the 1/255 cut must be able to make */
+  /* learnable per-Gaussian lambda (Sec. 4.2, trained over a window of
+   * iterations per Sec. 5.1): when lambda_raw is not NULL Gaussian i uses
+   * lambda = sigmoid(lambda_raw[i]) instead of lambda_opa, and the backward
+   * adds dL/dlambda_raw into grad_lambda (when that is not NULL either) */
+  const double *lambda_raw;
+  double *grad_lambda;
 } orc_settings;
 
 static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+static double lam_of(const orc_settings *s, int64_t i) {
+  return s->lambda_raw ? sigm(s->lambda_raw[i]) : s->lambda_opa;
+}
 
 /* ---------------------------------------------------------------- algebra */
 static void inv3(const double a[3][3], double out[3][3], double *det_out) {
@@ -307,7 +317,7 @@ static void record_one(const double *params, int64_t n, int64_t i, const orc_cam
   nd = sqrt(nd);
   for (int k = 0; k < 3; k++) d[k] /= nd;
   double mu_c[3], x[3], D, f, ac;
-  slice_dir(&g, d, s->lambda_opa, mu_c, x, &D, &f, &ac);
+  slice_dir(&g, d, lam_of(s, i), mu_c, x, &D, &f, &ac);
   for (int k = 0; k < 3; k++) { rec[F_MUC + k] = mu_c[k]; rec[F_DIR + k] = d[k]; }
   rec[F_SIGC + 0] = g.Sc[0][0]; rec[F_SIGC + 1] = g.Sc[0][1]; rec[F_SIGC + 2] = g.Sc[0][2];
   rec[F_SIGC + 3] = g.Sc[1][1]; rec[F_SIGC + 4] = g.Sc[1][2]; rec[F_SIGC + 5] = g.Sc[2][2];
@@ -666,8 +676,10 @@ static void record_vjp(const double *params, int64_t n, int64_t i, const orc_cam
   double x[3], Ax[3];
   for (int k = 0; k < 3; k++) x[k] = rec[F_DIR + k] - g.mu_d[k];
   for (int r = 0; r < 3; r++) Ax[r] = g.A[r][0] * x[0] + g.A[r][1] * x[1] + g.A[r][2] * x[2];
-  double ac = rec[F_ALPHAC], gac = g2[G_AC], lam = s->lambda_opa;
+  double ac = rec[F_ALPHAC], gac = g2[G_AC], lam = lam_of(s, i);
   double dD = -lam * ac * gac;
+  /* alpha_cond = alpha exp(-lambda D): d alpha_cond / d lambda = -D alpha_cond */
+  if (s->lambda_raw && s->grad_lambda) s->grad_lambda[i] += -rec[F_D] * ac * gac * lam * (1.0 - lam);
   double gx[3];
   for (int k = 0; k < 3; k++)
     gx[k] = g.K[0][k] * gmu[0] + g.K[1][k] * gmu[1] + g.K[2][k] * gmu[2] + 2.0 * dD * Ax[k];

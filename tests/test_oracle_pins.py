@@ -447,6 +447,55 @@ def test_backward_matches_finite_differences_on_tiny_scene():
             assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b)
 
 
+def test_per_gaussian_lambda_constant_equals_scalar_setting():
+    """A per-Gaussian lambda array holding the scalar value everywhere renders
+    and differentiates exactly like the scalar setting (the learnable-lambda
+    path changes where lambda comes from, nothing else)."""
+    p, cam = tiny_scene(6, 47)
+    st = oracle.Settings(bg=(0.3, 0.2, 0.1), lambda_opa=0.35)
+    raw = np.full(p.shape[1], math.log(0.35 / 0.65))
+    w = np.random.default_rng(5).normal(size=(3, cam.height, cam.width))
+    img_s, T_s, *_ = oracle.render(p, cam, st, nthreads=1)
+    img_a, T_a, *_ = oracle.render(p, cam, st, nthreads=1, lambda_raw=raw)
+    assert np.abs(img_s - img_a).max() < 1e-13 and np.abs(T_s - T_a).max() < 1e-13
+    g_s, _ = oracle.backward(p, cam, w, st, nthreads=1)
+    g_a, _, g_lam = oracle.backward(p, cam, w, st, nthreads=1, lambda_raw=raw)
+    assert np.abs(g_s - g_a).max() <= 1e-12 * max(np.abs(g_s).max(), 1.0)
+    assert np.abs(g_lam).max() > 0
+
+
+def test_lambda_gradient_matches_finite_differences():
+    """dL/dlambda_raw of the whole render against FP64 central differences,
+    with a different lambda per Gaussian; lambda -> 0 (raw -> -inf) must
+    remove the view dependence of the opacity, so its gradient vanishes."""
+    n = 6
+    p, cam = tiny_scene(n, 53)
+    st = oracle.Settings(bg=(0.1, 0.3, 0.2))
+    raw = np.random.default_rng(6).normal(0.0, 1.0, n)
+    w = np.random.default_rng(7).normal(size=(3, cam.height, cam.width))
+
+    def loss(r):
+        img, *_ = oracle.render(p, cam, st, nthreads=1, lambda_raw=r)
+        return float((img * w).sum())
+
+    _, _, g = oracle.backward(p, cam, w, st, nthreads=1, lambda_raw=raw)
+    fd = []
+    for i in range(n):
+        h = 1e-6
+        est = []
+        for hh in (h, h / 2):
+            rp = raw.copy(); rp[i] += hh
+            rm = raw.copy(); rm[i] -= hh
+            est.append((loss(rp) - loss(rm)) / (2 * hh))
+        assert abs(est[0] - est[1]) <= 0.1 * max(abs(est[1]), 1e-6)
+        fd.append(est[1])
+    fd = np.array(fd)
+    assert np.abs(fd).max() > 1e-3
+    assert np.abs(g - fd).max() <= 1e-6 * np.abs(fd).max()
+    _, _, g0 = oracle.backward(p, cam, w, st, nthreads=1, lambda_raw=np.full(n, -60.0))
+    assert np.abs(g0).max() < 1e-20
+
+
 def test_backward_pixel_subset_is_restriction_of_full_frame():
     """The gradient of a loss on a pixel subset equals the full-frame gradient
     with the upstream gradient zero elsewhere."""
