@@ -143,6 +143,17 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* ctx, float* params, int64_t n, co
                                    float* m, float* v, const float* lr, float beta1, float beta2, float eps,
                                    int32_t step, float* densify, void* stream);
 
+/* Learnable per-Gaussian lambda (Sec. 4.2; the paper trains it over a window
+ * of iterations, Sec. 5.1).  lambda_raw: device [n] float32 raw values for the
+ * following forwards on this context, Gaussian i using lambda =
+ * sigmoid(lambda_raw[i]) in place of settings.lambda_opa; NULL restores the
+ * scalar setting.  grad_lambda: device [n], or NULL; each backward (and
+ * backward_adam) of a forward that used lambda_raw overwrites it with
+ * dL/dlambda_raw.  Both arrays stay owned by the caller, must hold the n of
+ * the forwards, and lambda_raw must not change between a forward and its
+ * backward.  INVALID_ARG for grad_lambda without lambda_raw. */
+sixdgs_status sixdgs_set_lambda(sixdgs_ctx* ctx, const float* lambda_raw, float* grad_lambda);
+
 /* L1 photometric loss over nimg (1..SIXDGS_MAX_VIEWS) image pairs:
  * loss = mean |I - I*| over every element of every image (written to the
  * device float `loss`), and dL/dI = sign(I - I*) / total_count written to
@@ -165,6 +176,14 @@ sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, 
  * graph of a training step advances Adam on every replay. */
 sixdgs_status sixdgs_adam_devstep(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
                                   float beta1, float beta2, float eps, int32_t* step_counter, void* stream);
+
+/* Adam on one vector of n floats with one learning rate (e.g. the learnable
+ * lambda's raw values).  The bias correction uses `step` (from 1), or, when
+ * step_counter (device int32) is not NULL, *step_counter + 1 without changing
+ * the counter: called before sixdgs_adam_devstep, it shares that training
+ * step's count.  p, m, v are updated in place (device [n]). */
+sixdgs_status sixdgs_adam_vec(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1,
+                              float beta2, float eps, int32_t step, const int32_t* step_counter, void* stream);
 
 /* The integer stage alone, on caller-given projected records: bins entries
  * e = view*n + i (arrays of length n*ncam, device) with extents (u +- ex,

@@ -69,6 +69,8 @@ def lib():
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
         L.sixdgs_adam_devstep.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, P, P]
+        L.sixdgs_adam_vec.argtypes = [P, P, P, P, I64, F, F, F, F, I32, P, P]
+        L.sixdgs_set_lambda.argtypes = [P, P, P]
         L.sixdgs_bin.argtypes = [P, I64, ctypes.POINTER(Camera), I32, P, P, P, P, P, P, P]
         L.sixdgs_export.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
         L.sixdgs_check.argtypes = [P]
@@ -86,7 +88,8 @@ def lib():
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
             "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
-            "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
+            "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_bin",
+            "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
 
 
 def default_settings(**kw) -> Settings:
@@ -156,6 +159,16 @@ class Context:
     def _rc(self, rc):
         if rc != OK:
             raise SixDGSError(rc, lib().sixdgs_last_error(self._h).decode())
+
+    def set_lambda(self, lambda_raw=None, grad_lambda=None):
+        """Learnable per-Gaussian lambda: float32 CUDA tensors [n] (or None), kept
+        referenced here while attached."""
+        for t, nm in ((lambda_raw, "lambda_raw"), (grad_lambda, "grad_lambda")):
+            if t is not None:
+                _check_f32_cuda(t, nm)
+        self._lambda = (lambda_raw, grad_lambda)
+        self._rc(lib().sixdgs_set_lambda(self._h, None if lambda_raw is None else ctypes.c_void_p(lambda_raw.data_ptr()),
+                                         None if grad_lambda is None else ctypes.c_void_p(grad_lambda.data_ptr())))
 
     def set_settings(self, **kw):
         for k, v in kw.items():
@@ -274,6 +287,26 @@ class Context:
         n = ctypes.c_int64()
         self._rc(lib().sixdgs_kernel_time(self._h, kernel, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def adam_vec(p, grad, m, v, lr, step=1, step_counter=None, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """Adam on one float32 CUDA vector with one learning rate; with a device
+    step counter the step is counter + 1 and the counter is left as it is."""
+    import torch
+    for t, nm in ((p, "p"), (grad, "grad"), (m, "m"), (v, "v")):
+        _check_f32_cuda(t, nm)
+        if t.shape != p.shape:
+            raise ValueError("p, grad, m and v must share one shape")
+    if step_counter is not None and not (step_counter.is_cuda and step_counter.dtype == torch.int32
+                                         and step_counter.numel() == 1):
+        raise ValueError("step_counter must be a one-element int32 CUDA tensor")
+    rc = lib().sixdgs_adam_vec(ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                               ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), p.numel(), float(lr),
+                               beta1, beta2, eps, int(step),
+                               None if step_counter is None else ctypes.c_void_p(step_counter.data_ptr()),
+                               ctypes.c_void_p(_stream(stream)))
+    if rc != OK:
+        raise SixDGSError(rc, "adam_vec failed (bad arguments)")
 
 
 def adam_devstep(params, grad, m, v, lr, step_counter, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -64,6 +64,10 @@ struct sixdgs_ctx {
   DevBuf<uint2> items;
   int64_t bwd_grid = 0;
   int32_t fwd_chunk = 256;   // chunk length the last forward saved its boundary state for
+  // learnable per-Gaussian lambda (caller-owned device arrays, sixdgs_set_lambda)
+  const float* lambda_raw = nullptr;
+  float* grad_lambda = nullptr;
+  const float* fwd_lambda = nullptr;  // what the last forward used
   // backward and loss
   DevBuf<float> g2d, l1_partial;
   // scratch
@@ -185,6 +189,8 @@ DevSettings dev_settings(const sixdgs_settings& s) {
   d.lambda_opa = s.lambda_opa;
   d.z_near = s.z_near;
   for (int k = 0; k < 3; k++) d.bg[k] = s.bg[k];
+  d.lambda_raw = nullptr;
+  d.grad_lambda = nullptr;
   return d;
 }
 
@@ -440,7 +446,9 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
   const bool want_counts = (c->s.flags & SIXDGS_FLAG_COUNTS) != 0;
   if (want_counts && !c->counts.ensure(total_px)) return fail(c, SIXDGS_ERR_OOM, "pixel counts");
   c->vt = vt;
-  const DevSettings ds = dev_settings(c->s);
+  DevSettings ds = dev_settings(c->s);
+  ds.lambda_raw = c->lambda_raw;
+  c->fwd_lambda = c->lambda_raw;
   {
     Timer t(c, SIXDGS_K_PREPROCESS, st);
     launch_preprocess(params, n, vt, ds, c->rec.p, c->tiles.p, st);
@@ -493,7 +501,9 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, con
   }
   if (n == 0) return SIXDGS_OK;
   if (!c->g2d.ensure(c->fwd_E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
-  const DevSettings ds = dev_settings(c->s);
+  DevSettings ds = dev_settings(c->s);
+  ds.lambda_raw = c->fwd_lambda;
+  ds.grad_lambda = c->fwd_lambda ? c->grad_lambda : nullptr;
   launch_zero_g2d(c->sb, c->g2d.p, st);
   const BlendState bs = blend_state(c);
   {
@@ -529,7 +539,9 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, cons
   }
   if (n == 0) return SIXDGS_OK;
   if (!c->g2d.ensure(c->fwd_E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
-  const DevSettings ds = dev_settings(c->s);
+  DevSettings ds = dev_settings(c->s);
+  ds.lambda_raw = c->fwd_lambda;
+  ds.grad_lambda = c->fwd_lambda ? c->grad_lambda : nullptr;
   launch_zero_g2d(c->sb, c->g2d.p, st);
   const BlendState bs = blend_state(c);
   {
@@ -567,7 +579,7 @@ sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, 
                           float beta1, float beta2, float eps, int32_t step, void* stream) {
   if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || !lr || step < 1) return SIXDGS_ERR_INVALID_ARG;
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return SIXDGS_ERR_INVALID_ARG;
-  launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, nullptr, (hipStream_t)stream);
+  launch_adam(params, grad, m, v, kRows, n, lr, beta1, beta2, eps, step, nullptr, false, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
 }
 
@@ -575,8 +587,26 @@ sixdgs_status sixdgs_adam_devstep(float* params, const float* grad, float* m, fl
                                   float beta1, float beta2, float eps, int32_t* step_counter, void* stream) {
   if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || !lr || !step_counter) return SIXDGS_ERR_INVALID_ARG;
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return SIXDGS_ERR_INVALID_ARG;
-  launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, 1, step_counter, (hipStream_t)stream);
+  launch_adam(params, grad, m, v, kRows, n, lr, beta1, beta2, eps, 1, step_counter, true, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_adam_vec(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1,
+                              float beta2, float eps, int32_t step, const int32_t* step_counter, void* stream) {
+  if (n < 0 || (n > 0 && (!p || !g || !m || !v)) || (!step_counter && step < 1)) return SIXDGS_ERR_INVALID_ARG;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return SIXDGS_ERR_INVALID_ARG;
+  const float lrs[6] = {lr, lr, lr, lr, lr, lr};
+  launch_adam(p, g, m, v, 1, n, lrs, beta1, beta2, eps, step_counter ? 1 : step, const_cast<int32_t*>(step_counter),
+              false, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_set_lambda(sixdgs_ctx* c, const float* lambda_raw, float* grad_lambda) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (!lambda_raw && grad_lambda) return fail(c, SIXDGS_ERR_INVALID_ARG, "grad_lambda needs lambda_raw");
+  c->lambda_raw = lambda_raw;
+  c->grad_lambda = grad_lambda;
+  return SIXDGS_OK;
 }
 
 sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, int32_t ncam, const float* u,

@@ -49,6 +49,8 @@ struct DevSettings {
   float lambda_opa;
   float z_near;
   float bg[3];
+  const float* lambda_raw;  // [n] learnable per-Gaussian lambda = sigmoid(raw), or nullptr: lambda_opa
+  float* grad_lambda;       // [n] backward output dL/dlambda_raw, or nullptr
 };
 constexpr float kDilation = 0.3f;
 constexpr float kGuard = 1.3f;
@@ -190,7 +192,10 @@ int64_t chunk_scan_words(int64_t total_tiles);
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,
                float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
 int64_t l1_partial_count(int nimg, const int64_t* numel);
-void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
-                 float eps, int step, int32_t* step_dev, hipStream_t st);
+// Adam over `rows` rows of n floats (rows = 76: the parameter layout, one lr
+// per row group; rows = 1: a single vector with lr[0]).  With step_dev the
+// step is *step_dev + 1, and the counter is advanced when `advance`.
+void launch_adam(float* p, const float* g, float* m, float* v, int rows, int64_t n, const float lr[6], float b1,
+                 float b2, float eps, int step, int32_t* step_dev, bool advance, hipStream_t st);
 
 }  // namespace sixdgs

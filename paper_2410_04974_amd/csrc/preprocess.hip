@@ -10,6 +10,12 @@ namespace {
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
+// The directional-opacity strength of Gaussian g (Sec. 4.2): the setting, or a
+// learnable per-Gaussian sigmoid(raw) (trained over an iteration window, Sec. 5.1).
+__device__ __forceinline__ float gaussian_lambda(const DevSettings& ds, int64_t g) {
+  return ds.lambda_raw ? sigmoidf(ds.lambda_raw[g]) : ds.lambda_opa;
+}
+
 // Index of Cholesky entry (i, j), j <= i, in the packed lower triangle.
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -219,12 +225,13 @@ __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__
   if (g >= n) return;
   Static s;
   load_static(params, n, g, s);
+  const float lam = gaussian_lambda(ds, g);
   for (int vi = 0; vi < vt.nview; vi++) {
     const ViewDesc& vd = vt.v[vi];
     const int64_t e = (int64_t)vi * n + g;
     ViewState w;
     uint32_t count = 0;
-    if (view_state(s, vd, ds.lambda_opa, ds.z_near, w) && w.ac * 255.0f >= 1.0f) {
+    if (view_state(s, vd, lam, ds.z_near, w) && w.ac * 255.0f >= 1.0f) {
       const float qmax = 2.0f * logf(255.0f * w.ac);
       const float ex = sqrtf(qmax * w.cov[0]);
       const float ey = sqrtf(qmax * w.cov[2]);
@@ -294,6 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
   // of the whole wavefront instead of two partial ones.
   if (__ballot(any) == 0) {
     for (int r = 0; r < kRows; r++) sink.put(r, n, g, 0.f);
+    if (ds.lambda_raw && ds.grad_lambda) ds.grad_lambda[g] = 0.f;
     return;
   }
   Static s;
@@ -317,13 +325,15 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
   float g_Spd_mu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // mu_cond part of dL/dSigma_pd
   float g_A_mu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};    // mu_cond and D parts of dL/dA
   float dens_norm = 0.f, dens_cnt = 0.f;
+  const float lam = gaussian_lambda(ds, g);
+  float g_lam = 0.f;  // dL/dlambda
 
   for (int vi = 0; vi < vt.nview; vi++) {
     const ViewDesc& vd = vt.v[vi];
     const int64_t e = (int64_t)vi * n + g;
     if (tiles[e] == 0) continue;
     ViewState w;
-    view_state(s, vd, ds.lambda_opa, ds.z_near, w);
+    view_state(s, vd, lam, ds.z_near, w);
     const float* gp = g2d + e * kG2D;
     const float gu = gp[0], gv = gp[1], gqxx = gp[2], gqxy = gp[3], gqyy = gp[4], gac = gp[5];
     const float z = w.p[2], fx = vd.fx, fy = vd.fy;
@@ -405,7 +415,8 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
 #pragma unroll
     for (int k = 0; k < 3; k++) gmu[k] += (gs[k] - w.sdir[k] * sdot) / w.ns;
     // slice (Sec. 3.2): mu_c = mu_p + K x, D = x^T A x, alpha_c = alpha exp(-lambda D)
-    const float dD = -ds.lambda_opa * w.ac * gac;
+    const float dD = -lam * w.ac * gac;
+    g_lam -= w.D * w.ac * gac;  // d alpha_c / d lambda = -D alpha_c
     float gx[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) gx[k] = s.K[0][k] * gmu[0] + s.K[1][k] * gmu[1] + s.K[2][k] * gmu[2] + 2.f * dD * w.Ax[k];
@@ -494,6 +505,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
     densify[g] += dens_norm;
     densify[n + g] += dens_cnt;
   }
+  if (ds.lambda_raw && ds.grad_lambda) ds.grad_lambda[g] = any ? g_lam * lam * (1.f - lam) : 0.f;
 }
 
 }  // namespace

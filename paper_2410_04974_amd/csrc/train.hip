@@ -134,22 +134,22 @@ AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int st
   return a;
 }
 
-void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, const float lr[6], float b1, float b2,
-                 float eps, int step, int32_t* step_dev, hipStream_t st) {
-  if (n <= 0) return;
+void launch_adam(float* p, const float* g, float* m, float* v, int rows, int64_t n, const float lr[6], float b1,
+                 float b2, float eps, int step, int32_t* step_dev, bool advance, hipStream_t st) {
+  if (n <= 0 || rows <= 0) return;
   const AdamArgs a = make_adam_args(lr, b1, b2, eps, step_dev ? 1 : step);
   const bool vec = (n % 4 == 0) && ((uintptr_t)p % 16 == 0) && ((uintptr_t)g % 16 == 0) &&
                    ((uintptr_t)m % 16 == 0) && ((uintptr_t)v % 16 == 0);
   if (vec) {
     const int64_t n4 = n / 4;
-    const dim3 grid((unsigned)((n4 + kBlock - 1) / kBlock), kRows);
+    const dim3 grid((unsigned)((n4 + kBlock - 1) / kBlock), (unsigned)rows);
     hipLaunchKernelGGL(k_adam4, grid, dim3(kBlock), 0, st, (float4*)p, (const float4*)g, (float4*)m, (float4*)v, n4, a,
                        (const int32_t*)step_dev);
   } else {
-    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock), kRows);
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)rows);
     hipLaunchKernelGGL(k_adam1, grid, dim3(kBlock), 0, st, p, g, m, v, n, a, (const int32_t*)step_dev);
   }
-  if (step_dev) hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step_dev);
+  if (step_dev && advance) hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step_dev);
 }
 
 }  // namespace sixdgs

@@ -75,7 +75,13 @@ class Trainer:
     library, on the current stream, with no host synchronisation once the
     renderer has a fixed pair capacity."""
 
-    def __init__(self, params, renderer, lr=DEFAULT_LR, betas=(0.9, 0.999), eps=1e-15):
+    def __init__(self, params, renderer, lr=DEFAULT_LR, betas=(0.9, 0.999), eps=1e-15, lambda_raw=None,
+                 lr_lambda=1e-2):
+        """``lambda_raw`` (float32 CUDA [n], or None for the renderer's scalar
+        lambda) makes the directional-opacity strength a learnable
+        per-Gaussian sigmoid(raw); it is updated by its own Adam while
+        ``train_lambda`` is True (the paper trains it over a window of
+        iterations and keeps it fixed otherwise)."""
         self.params = params
         self.renderer = renderer
         self.m = torch.zeros_like(params)
@@ -91,6 +97,20 @@ class Trainer:
         self._imgs = None
         self._dl = None
         self.graphs = {}
+        self.lambda_raw = lambda_raw
+        self.lr_lambda = lr_lambda
+        self.train_lambda = lambda_raw is not None
+        if lambda_raw is not None:
+            self.grad_lambda = torch.zeros_like(lambda_raw)
+            self.m_lambda = torch.zeros_like(lambda_raw)
+            self.v_lambda = torch.zeros_like(lambda_raw)
+            renderer.ctx.set_lambda(lambda_raw, self.grad_lambda)
+
+    def _adam_lambda(self):
+        # shares the step's device counter; runs before the parameter Adam advances it
+        if self.lambda_raw is not None and self.train_lambda:
+            _lib.adam_vec(self.lambda_raw, self.grad_lambda, self.m_lambda, self.v_lambda, self.lr_lambda,
+                          step_counter=self.step_counter, beta1=self.betas[0], beta2=self.betas[1], eps=self.eps)
 
     def step(self, cams, targets, densify=None, fused=False):
         """Render, L1 loss, backward, Adam.  fused=True applies Adam inside the
@@ -107,9 +127,11 @@ class Trainer:
         if fused:
             self.renderer.ctx.backward_adam(self.params, self._dl, self.m, self.v, self.lr, self.step_count,
                                             self.betas[0], self.betas[1], self.eps, densify=densify)
+            self._adam_lambda()
             self.step_counter += 1
         else:
             self.renderer.backward(self.params, self._dl, grad=self.grad, densify=densify)
+            self._adam_lambda()
             _lib.adam_devstep(self.params, self.grad, self.m, self.v, self.lr, self.step_counter, self.betas[0],
                               self.betas[1], self.eps)
         return self.loss
@@ -149,6 +171,10 @@ class Trainer:
         arrays = {"params": self.params.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
                   "step_count": np.array(self.step_count, np.int64),
                   "step_counter": self.step_counter.cpu().numpy()}
+        if self.lambda_raw is not None:
+            arrays["lambda_raw"] = self.lambda_raw.cpu().numpy()
+            arrays["m_lambda"] = self.m_lambda.cpu().numpy()
+            arrays["v_lambda"] = self.v_lambda.cpu().numpy()
         for k, t in (extra or {}).items():
             arrays["extra_" + k] = t.cpu().numpy()
         np.savez(path, **arrays)
@@ -168,6 +194,17 @@ class Trainer:
             self.v.copy_(torch.from_numpy(z["v"]))
             self.step_count = int(z["step_count"])
             self.step_counter.copy_(torch.from_numpy(z["step_counter"]))
+            if "lambda_raw" in z.files:
+                if self.lambda_raw is None or tuple(self.lambda_raw.shape) != tuple(z["lambda_raw"].shape):
+                    self.lambda_raw = torch.empty(tuple(z["lambda_raw"].shape), device=dev, dtype=torch.float32)
+                    self.grad_lambda = torch.zeros_like(self.lambda_raw)
+                    self.m_lambda = torch.zeros_like(self.lambda_raw)
+                    self.v_lambda = torch.zeros_like(self.lambda_raw)
+                    self.train_lambda = True
+                self.lambda_raw.copy_(torch.from_numpy(z["lambda_raw"]))
+                self.m_lambda.copy_(torch.from_numpy(z["m_lambda"]))
+                self.v_lambda.copy_(torch.from_numpy(z["v_lambda"]))
+                self.renderer.ctx.set_lambda(self.lambda_raw, self.grad_lambda)
             extra = {k[len("extra_"):]: torch.from_numpy(z[k]).to(dev) for k in z.files if k.startswith("extra_")}
         self.graphs = {}
         return extra
