@@ -154,6 +154,47 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* ctx, float* params, int64_t n, co
  * backward.  INVALID_ARG for grad_lambda without lambda_raw. */
 sixdgs_status sixdgs_set_lambda(sixdgs_ctx* ctx, const float* lambda_raw, float* grad_lambda);
 
+/* ---- adaptive density control (Sec. 4.3) ------------------------------ */
+
+/* Rotation and scale of every Gaussian from the SVD of its conditional
+ * covariance (direction independent): Sigma_cond = R diag(S^2) R^T with S
+ * descending, R proper (det +1).  The SVD fixes each axis only up to sign;
+ * here the first two axes have their largest component positive and the third
+ * is their cross product -- the paper's sign(det R) correction of the last
+ * column.  params: device [76][n]; R: device [9][n] (row-major entries),
+ * S: device [3][n], both overwritten. */
+sixdgs_status sixdgs_decompose(const float* params, int64_t n, float* R, float* S, void* stream);
+
+typedef struct {
+  float grad_threshold; /* densify when the mean screen-space gradient norm over the
+                           views a Gaussian was visible in reaches this (3DGS: 2e-4) */
+  float percent_dense;  /* clone when max(S) <= percent_dense * extent, else split (0.01) */
+  float extent;         /* scene extent in world units */
+  float min_opacity;    /* prune when sigmoid(opacity logit) < this (Sec. 5.1: 0.01) */
+} sixdgs_density_settings;
+
+/* Plans one density-control step: per Gaussian prune (0 outputs), keep (1),
+ * clone (the Gaussian and an identical copy) or split (two children whose
+ * spatial means are mu_p + R (S * z_k) and whose spatial Cholesky block L_p
+ * is divided by 1.6, so S shrinks by 1.6 and R is kept), from stats (device
+ * [2][n]: the summed screen-space gradient norm and the visible-view count
+ * that sixdgs_backward accumulates into `densify`).  Waits for the stream and
+ * writes the number of output Gaussians to *n_out (host).  The plan stays in
+ * ctx for the next sixdgs_densify_apply with the same params and n. */
+sixdgs_status sixdgs_densify_plan(sixdgs_ctx* ctx, const float* params, int64_t n, const float* stats,
+                                  const sixdgs_density_settings* settings, int64_t* n_out, void* stream);
+
+/* Applies the planned step: params_out (device [76][n_out]) receives the
+ * outputs in the parents' order, each parent's outputs consecutive.  noise:
+ * device [2][3][n] standard normal draws (z_0, z_1 of a split).  m, v (device
+ * [76][n], Adam moments) and m_out, v_out: all four or none; moments are kept
+ * for kept Gaussians and the first output of a clone and zero for clone copies
+ * and split children.  lambda_raw ([n]) / lambda_out ([n_out]): both or
+ * neither; copied to every output.  STATE without a matching plan. */
+sixdgs_status sixdgs_densify_apply(sixdgs_ctx* ctx, const float* params, const float* m, const float* v,
+                                   const float* lambda_raw, int64_t n, const float* noise, float* params_out,
+                                   float* m_out, float* v_out, float* lambda_out, int64_t n_out, void* stream);
+
 /* L1 photometric loss over nimg (1..SIXDGS_MAX_VIEWS) image pairs:
  * loss = mean |I - I*| over every element of every image (written to the
  * device float `loss`), and dL/dI = sign(I - I*) / total_count written to

@@ -11,7 +11,9 @@ prune rules are those of 3DGS with the minimum opacity tau = 0.01 (Sec. 4.3,
 Sec. 5.1).
 
 Readings where the paper is silent (listed with the others in the design notes):
-  * order: singular values descending (the SVD convention);
+  * order: singular values descending (the SVD convention); signs: the first
+    two axes with their largest component positive, the third their cross
+    product (the paper's sign(det R) correction of the last column);
   * a Gaussian is densified when its mean screen-space gradient over the views
     it was visible in reaches ``grad_threshold`` (3DGS: 2e-4); it is cloned when
     max(S) <= ``percent_dense`` * ``extent`` (3DGS: 0.01 of the scene extent) and
@@ -50,7 +52,13 @@ def decompose(params):
     _, sig, _, _, _ = slice_gaussians(p, dirs, 0.35)
     w, U = np.linalg.eigh(sig)  # ascending
     w, U = w[:, ::-1], U[:, :, ::-1].copy()
-    U[:, :, 2] *= np.sign(np.linalg.det(U))[:, None]
+    # the SVD fixes each axis only up to sign: the first two axes are taken with
+    # their largest component positive, and the third as their cross product,
+    # which is the paper's last-column sign(det R) correction
+    for k in range(2):
+        big = np.take_along_axis(U[:, :, k], np.argmax(np.abs(U[:, :, k]), axis=1)[:, None], axis=1)[:, 0]
+        U[:, :, k] *= np.where(big < 0, -1.0, 1.0)[:, None]
+    U[:, :, 2] = np.cross(U[:, :, 0], U[:, :, 1])
     return U, np.sqrt(np.clip(w, 0.0, None))
 
 

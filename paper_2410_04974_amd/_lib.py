@@ -37,6 +37,11 @@ class Settings(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("flags", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
+class DensitySettings(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("percent_dense", ctypes.c_float), ("extent", ctypes.c_float),
+                ("min_opacity", ctypes.c_float)]
+
+
 class SixDGSError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"lib6dgs status {status}: {msg}")
@@ -71,6 +76,9 @@ def lib():
         L.sixdgs_adam_devstep.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, P, P]
         L.sixdgs_adam_vec.argtypes = [P, P, P, P, I64, F, F, F, F, I32, P, P]
         L.sixdgs_set_lambda.argtypes = [P, P, P]
+        L.sixdgs_decompose.argtypes = [P, I64, P, P, P]
+        L.sixdgs_densify_plan.argtypes = [P, P, I64, P, ctypes.POINTER(DensitySettings), ctypes.POINTER(I64), P]
+        L.sixdgs_densify_apply.argtypes = [P, P, P, P, P, I64, P, P, P, P, P, I64, P]
         L.sixdgs_bin.argtypes = [P, I64, ctypes.POINTER(Camera), I32, P, P, P, P, P, P, P]
         L.sixdgs_export.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
         L.sixdgs_check.argtypes = [P]
@@ -88,7 +96,8 @@ def lib():
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
             "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
-            "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_bin",
+            "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_decompose",
+            "sixdgs_densify_plan", "sixdgs_densify_apply", "sixdgs_bin",
             "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
 
 
@@ -169,6 +178,26 @@ class Context:
         self._lambda = (lambda_raw, grad_lambda)
         self._rc(lib().sixdgs_set_lambda(self._h, None if lambda_raw is None else ctypes.c_void_p(lambda_raw.data_ptr()),
                                          None if grad_lambda is None else ctypes.c_void_p(grad_lambda.data_ptr())))
+
+    def densify(self, params, stats, noise, grad_threshold=2e-4, percent_dense=0.01, extent=1.0, min_opacity=0.01,
+                m=None, v=None, lambda_raw=None, stream=None):
+        """One density-control step (plan, then apply); returns the new params
+        and, when given, m, v and lambda_raw, as new tensors."""
+        import torch
+        _check_f32_cuda(params, "params")
+        n = params.shape[1]
+        d = DensitySettings(grad_threshold, percent_dense, extent, min_opacity)
+        n_out = ctypes.c_int64()
+        self._rc(lib().sixdgs_densify_plan(self._h, _vp(params), n, _vp(stats), ctypes.byref(d), ctypes.byref(n_out),
+                                           ctypes.c_void_p(_stream(stream))))
+        k = n_out.value
+        new = lambda: torch.empty((76, k), device=params.device, dtype=torch.float32)
+        po = new()
+        mo, vo = (new(), new()) if m is not None else (None, None)
+        lo = torch.empty(k, device=params.device, dtype=torch.float32) if lambda_raw is not None else None
+        self._rc(lib().sixdgs_densify_apply(self._h, _vp(params), _vp(m), _vp(v), _vp(lambda_raw), n, _vp(noise),
+                                            _vp(po), _vp(mo), _vp(vo), _vp(lo), k, ctypes.c_void_p(_stream(stream))))
+        return po, mo, vo, lo
 
     def set_settings(self, **kw):
         for k, v in kw.items():
@@ -287,6 +316,23 @@ class Context:
         n = ctypes.c_int64()
         self._rc(lib().sixdgs_kernel_time(self._h, kernel, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def _vp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def decompose(params, stream=None):
+    """Rotation R [3, 3, N] and scale S [3, N] of every Gaussian's conditional covariance."""
+    import torch
+    _check_f32_cuda(params, "params")
+    n = params.shape[1]
+    R = torch.empty((3, 3, n), device=params.device, dtype=torch.float32)
+    S = torch.empty((3, n), device=params.device, dtype=torch.float32)
+    rc = lib().sixdgs_decompose(_vp(params), n, _vp(R), _vp(S), ctypes.c_void_p(_stream(stream)))
+    if rc != OK:
+        raise SixDGSError(rc, "decompose failed")
+    return R, S
 
 
 def adam_vec(p, grad, m, v, lr, step=1, step_counter=None, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

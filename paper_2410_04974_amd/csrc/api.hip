@@ -68,6 +68,11 @@ struct sixdgs_ctx {
   const float* lambda_raw = nullptr;
   float* grad_lambda = nullptr;
   const float* fwd_lambda = nullptr;  // what the last forward used
+  // density control: the last plan (decision, output count and offset per Gaussian)
+  DevBuf<uint8_t> dens_dec;
+  DevBuf<uint32_t> dens_cnt, dens_off, dens_state;
+  const float* dens_params = nullptr;
+  int64_t dens_n = -1, dens_total = -1;
   // backward and loss
   DevBuf<float> g2d, l1_partial;
   // scratch
@@ -99,7 +104,7 @@ sixdgs_status fail(sixdgs_ctx* c, sixdgs_status st, const std::string& msg) {
 }
 
 // counters: [0] binned entries, [1] pairs, [2] pair overflow flag, [3] look-back
-// timeout flag, [4] backward work items
+// timeout flag, [4] backward work items, [5] density-control outputs
 constexpr int kCounters = 8;
 
 // Bound on entries and pairs: the radix sort's look-back words hold 30-bit counts.
@@ -404,6 +409,10 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   c->g2d.release();
   c->l1_partial.release();
   c->rstate.release();
+  c->dens_dec.release();
+  c->dens_cnt.release();
+  c->dens_off.release();
+  c->dens_state.release();
   c->blk_start.release();
   c->counters.release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
@@ -599,6 +608,56 @@ sixdgs_status sixdgs_adam_vec(float* p, const float* g, float* m, float* v, int6
   launch_adam(p, g, m, v, 1, n, lrs, beta1, beta2, eps, step_counter ? 1 : step, const_cast<int32_t*>(step_counter),
               false, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_decompose(const float* params, int64_t n, float* R, float* S, void* stream) {
+  if (n < 0 || (n > 0 && (!params || !R || !S))) return SIXDGS_ERR_INVALID_ARG;
+  launch_decompose(params, n, R, S, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_densify_plan(sixdgs_ctx* c, const float* params, int64_t n, const float* stats,
+                                  const sixdgs_density_settings* d, int64_t* n_out, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (n < 0 || n > kMaxItems) return fail(c, SIXDGS_ERR_INVALID_ARG, "n out of range");
+  if (!d || !n_out || (n > 0 && (!params || !stats))) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  if (!(d->grad_threshold > 0.f && d->percent_dense >= 0.f && d->extent > 0.f && d->min_opacity >= 0.f))
+    return fail(c, SIXDGS_ERR_INVALID_ARG, "density settings out of range");
+  c->dens_n = -1;
+  const int64_t n1 = std::max<int64_t>(n, 1);
+  if (!c->dens_dec.ensure(n1) || !c->dens_cnt.ensure(n1) || !c->dens_off.ensure(n1) ||
+      !c->dens_state.ensure(chunk_scan_words(n1)))
+    return fail(c, SIXDGS_ERR_OOM, "density plan buffers");
+  launch_density_plan(params, n, stats, *d, c->dens_dec.p, c->dens_cnt.p, st);
+  launch_count_scan(c->dens_cnt.p, n, c->dens_off.p, c->counters.p + 5, c->dens_state.p, c->counters.p + 3, st);
+  uint32_t total = 0;
+  if (hipMemcpyAsync(c->host_counters, c->counters.p + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(c, SIXDGS_ERR_HIP, "density plan read-back failed");
+  total = c->host_counters[0];
+  c->dens_params = params;
+  c->dens_n = n;
+  c->dens_total = total;
+  *n_out = total;
+  return check_launch(c, "density plan");
+}
+
+sixdgs_status sixdgs_densify_apply(sixdgs_ctx* c, const float* params, const float* m, const float* v,
+                                   const float* lambda_raw, int64_t n, const float* noise, float* params_out,
+                                   float* m_out, float* v_out, float* lambda_out, int64_t n_out, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (c->dens_n < 0 || c->dens_n != n || c->dens_params != params || c->dens_total != n_out)
+    return fail(c, SIXDGS_ERR_STATE, "no matching sixdgs_densify_plan for these params, n and n_out");
+  const bool mom = m || v || m_out || v_out;
+  if (mom && !(m && v && m_out && v_out)) return fail(c, SIXDGS_ERR_INVALID_ARG, "m, v, m_out, v_out: all or none");
+  if ((lambda_raw != nullptr) != (lambda_out != nullptr))
+    return fail(c, SIXDGS_ERR_INVALID_ARG, "lambda_raw and lambda_out: both or neither");
+  if (n > 0 && (!noise || (n_out > 0 && !params_out))) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  launch_density_apply(params, m, v, lambda_raw, n, noise, c->dens_dec.p, c->dens_off.p, params_out,
+                       mom ? m_out : nullptr, mom ? v_out : nullptr, lambda_out, n_out, (hipStream_t)stream);
+  return check_launch(c, "density apply");
 }
 
 sixdgs_status sixdgs_set_lambda(sixdgs_ctx* c, const float* lambda_raw, float* grad_lambda) {

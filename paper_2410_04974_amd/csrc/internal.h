@@ -187,6 +187,19 @@ void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec,
 void launch_chunk_items(const uint32_t* tile_nch, int64_t total_tiles, uint2* items, int64_t items_cap,
                         uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st);
 int64_t chunk_scan_words(int64_t total_tiles);
+// sort.hip: exclusive scan of n counts into off, the sum into *total (device);
+// `state` holds chunk_scan_words(n) words (zeroed here).
+void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* total, uint32_t* state,
+                       uint32_t* err, hipStream_t st);
+
+// density.hip: rotation and scale of Sigma_cond; the density-control plan
+// (decision and output count per Gaussian) and its application.
+void launch_decompose(const float* params, int64_t n, float* R, float* S, hipStream_t st);
+void launch_density_plan(const float* params, int64_t n, const float* stats, const sixdgs_density_settings& d,
+                         uint8_t* dec, uint32_t* cnt, hipStream_t st);
+void launch_density_apply(const float* params, const float* m, const float* v, const float* lam, int64_t n,
+                          const float* noise, const uint8_t* dec, const uint32_t* off, float* po, float* mo,
+                          float* vo, float* lo, int64_t n_out, hipStream_t st);
 
 // train.hip
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,

@@ -610,6 +610,30 @@ struct ExpandItems {
 
 int64_t chunk_scan_words(int64_t total_tiles) { return 2 + 2 * ((total_tiles + kChunk - 1) / kChunk + 1); }
 
+namespace {
+struct CountVal {
+  const uint32_t* c;
+  __device__ uint32_t operator()(int64_t i) const { return c[i]; }
+};
+struct CountOffset {
+  uint32_t* off;
+  __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { off[i] = pre; }
+};
+__global__ void __launch_bounds__(kBlock) k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+}  // namespace
+
+void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* total, uint32_t* state,
+                       uint32_t* err, hipStream_t st) {
+  const int64_t words = chunk_scan_words(n);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, state, words);
+  const uint32_t N = (uint32_t)n;
+  scan1<false>(CountVal{cnt}, CountOffset{off}, nullptr, N, N, n, state, reinterpret_cast<uint64_t*>(state + 2), total,
+               (uint32_t*)nullptr, err, st);
+}
+
 void launch_chunk_items(const uint32_t* tile_nch, int64_t total_tiles, uint2* items, int64_t items_cap,
                         uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st) {
   const uint32_t T = (uint32_t)total_tiles;

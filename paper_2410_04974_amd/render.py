@@ -162,6 +162,27 @@ class Trainer:
         self.step_count += 1
         return self.loss
 
+    # -- adaptive density control (Sec. 4.3) -------------------------------------
+    def densify(self, stats, extent, grad_threshold=2e-4, percent_dense=0.01, min_opacity=0.01, generator=None):
+        """Clone / split / prune from the accumulated statistics ``stats`` ([2, n],
+        as filled by ``step(densify=stats)``); the parameters, Adam moments and
+        a learnable lambda are replaced by the new set (captured graphs are
+        dropped: they refer to the old buffers).  Returns the new count."""
+        n = self.params.shape[1]
+        noise = torch.randn((2, 3, n), device=self.params.device, generator=generator)
+        p, m, v, lam = self.renderer.ctx.densify(self.params, stats, noise, grad_threshold, percent_dense, extent,
+                                                 min_opacity, m=self.m, v=self.v, lambda_raw=self.lambda_raw)
+        self.params, self.m, self.v = p, m, v
+        self.grad = torch.empty_like(p)
+        if self.lambda_raw is not None:
+            self.lambda_raw = lam
+            self.grad_lambda = torch.zeros_like(lam)
+            self.m_lambda = torch.zeros_like(lam)
+            self.v_lambda = torch.zeros_like(lam)
+            self.renderer.ctx.set_lambda(self.lambda_raw, self.grad_lambda)
+        self.graphs = {}
+        return p.shape[1]
+
     # -- checkpoint / resume ----------------------------------------------------
     def save(self, path, extra=None):
         """Writes params, Adam moments, the step count and any extra tensors
