@@ -258,6 +258,7 @@ def record_vjp(params, cam, g2d, settings: Settings = Settings()) -> np.ndarray:
 from .binning import bin_records, tile_grid  # noqa: E402
 from .train import adam_step, l1_loss, densify_stats  # noqa: E402
 from .density import decompose, decisions, densify  # noqa: E402
+from .dssim import l1_dssim_loss, ssim  # noqa: E402
 
 __all__ = ["Settings", "build", "preprocess", "render", "backward", "slice_gaussians", "sh_basis",
            "record_vjp", "bin_records", "tile_grid", "adam_step", "l1_loss", "densify_stats", "num_threads"]
