@@ -203,6 +203,18 @@ sixdgs_status sixdgs_densify_apply(sixdgs_ctx* ctx, const float* params, const f
 sixdgs_status sixdgs_l1_loss(sixdgs_ctx* ctx, int32_t nimg, const float* const* images, const float* const* targets,
                              const int64_t* numel, float* const* dl_dimages, float* loss, void* stream);
 
+/* The full 3DGS photometric loss (Sec. 4.4, Sec. 5.1: the paper keeps it):
+ * loss = (1 - lambda_dssim) L1 + lambda_dssim (1 - SSIM) over nimg
+ * (1..SIXDGS_MAX_VIEWS) views, both terms means over every channel and pixel
+ * of every view (3DGS: lambda_dssim = 0.2).  SSIM per channel and pixel under
+ * an 11x11 Gaussian window (sigma 1.5) zero-padded at the border, C1 = 1e-4,
+ * C2 = 9e-4.  images / targets / dl_dimages: host arrays of device pointers,
+ * each [3][heights[k]][widths[k]]; dl_dimages[k] is overwritten with dL/dI;
+ * loss is one device float.  Scratch (36 B per pixel) is owned by ctx. */
+sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* ctx, int32_t nimg, const float* const* images,
+                                   const float* const* targets, const int32_t* heights, const int32_t* widths,
+                                   float lambda_dssim, float* const* dl_dimages, float* loss, void* stream);
+
 /* One Adam step (Kingma and Ba, bias-corrected) on params [76][n] in place,
  * with moments m, v (device [76][n], updated in place; zero before step 1).
  * lr[6] (host) holds the learning rate of the row groups mu_p, mu_d,

@@ -76,6 +76,7 @@ def lib():
         L.sixdgs_adam_devstep.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, P, P]
         L.sixdgs_adam_vec.argtypes = [P, P, P, P, I64, F, F, F, F, I32, P, P]
         L.sixdgs_set_lambda.argtypes = [P, P, P]
+        L.sixdgs_l1_dssim_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I32), ctypes.POINTER(I32), F, PP, P, P]
         L.sixdgs_decompose.argtypes = [P, I64, P, P, P]
         L.sixdgs_densify_plan.argtypes = [P, P, I64, P, ctypes.POINTER(DensitySettings), ctypes.POINTER(I64), P]
         L.sixdgs_densify_apply.argtypes = [P, P, P, P, P, I64, P, P, P, P, P, I64, P]
@@ -96,6 +97,7 @@ def lib():
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
             "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
+            "sixdgs_l1_dssim_loss",
             "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_decompose",
             "sixdgs_densify_plan", "sixdgs_densify_apply", "sixdgs_bin",
             "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
@@ -268,6 +270,20 @@ class Context:
         self._rc(lib().sixdgs_l1_loss(self._h, len(images), _ptrs(images), _ptrs(targets), numel,
                                       _ptrs(dl_dimages), ctypes.c_void_p(loss.data_ptr()),
                                       ctypes.c_void_p(_stream(stream))))
+
+    def l1_dssim_loss(self, images, targets, dl_dimages, loss, lambda_dssim=0.2, stream=None):
+        """(1 - lambda) L1 + lambda (1 - SSIM) over [3, H, W] views, dL/dI into dl_dimages."""
+        for a, b, g in zip(images, targets, dl_dimages):
+            for t in (a, b, g):
+                _check_f32_cuda(t, "image")
+            if not (a.dim() == 3 and a.shape[0] == 3 and a.shape == b.shape == g.shape):
+                raise ValueError("images, targets and gradients must share one [3, H, W] shape per view")
+        _check_f32_cuda(loss, "loss")
+        hs = (ctypes.c_int32 * len(images))(*[t.shape[1] for t in images])
+        ws = (ctypes.c_int32 * len(images))(*[t.shape[2] for t in images])
+        self._rc(lib().sixdgs_l1_dssim_loss(self._h, len(images), _ptrs(images), _ptrs(targets), hs, ws,
+                                            float(lambda_dssim), _ptrs(dl_dimages), ctypes.c_void_p(loss.data_ptr()),
+                                            ctypes.c_void_p(_stream(stream))))
 
     def bin(self, n, cams, u, v, ex, ey, depth, alive, stream=None):
         import torch

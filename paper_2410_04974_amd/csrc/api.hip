@@ -74,7 +74,7 @@ struct sixdgs_ctx {
   const float* dens_params = nullptr;
   int64_t dens_n = -1, dens_total = -1;
   // backward and loss
-  DevBuf<float> g2d, l1_partial;
+  DevBuf<float> g2d, l1_partial, ssim_maps, ssim_partial;
   // scratch
   DevBuf<uint32_t> rstate, blk_start, counters;
   uint32_t* host_counters = nullptr;  // pinned
@@ -408,6 +408,8 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   c->counts.release();
   c->g2d.release();
   c->l1_partial.release();
+  c->ssim_maps.release();
+  c->ssim_partial.release();
   c->rstate.release();
   c->dens_dec.release();
   c->dens_cnt.release();
@@ -582,6 +584,29 @@ sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* im
   if (!c->l1_partial.ensure(parts)) return fail(c, SIXDGS_ERR_OOM, "loss partials");
   launch_l1(nimg, images, targets, numel, dl_dimages, c->l1_partial.p, c->l1_partial.cap, loss, (hipStream_t)stream);
   return check_launch(c, "l1 loss");
+}
+
+sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images,
+                                   const float* const* targets, const int32_t* heights, const int32_t* widths,
+                                   float lambda_dssim, float* const* dl_dimages, float* loss, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (nimg < 1 || nimg > kMaxViews) return fail(c, SIXDGS_ERR_INVALID_ARG, "nimg out of range");
+  if (!images || !targets || !heights || !widths || !dl_dimages || !loss)
+    return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  if (!(lambda_dssim >= 0.f && lambda_dssim <= 1.f)) return fail(c, SIXDGS_ERR_INVALID_ARG, "lambda_dssim not in [0, 1]");
+  int64_t px = 0, blocks = 0;
+  for (int k = 0; k < nimg; k++) {
+    if (!images[k] || !targets[k] || !dl_dimages[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL image pointer");
+    if (heights[k] < 1 || widths[k] < 1 || heights[k] > 65535 * 16 || widths[k] > 65535 * 16)
+      return fail(c, SIXDGS_ERR_INVALID_ARG, "image size out of range");
+    px += (int64_t)heights[k] * widths[k];
+    blocks += ssim_blocks(heights[k], widths[k]);
+  }
+  if (!c->ssim_maps.ensure(9 * px) || !c->ssim_partial.ensure(2 * blocks))
+    return fail(c, SIXDGS_ERR_OOM, "ssim scratch");
+  launch_l1_dssim(nimg, images, targets, heights, widths, lambda_dssim, dl_dimages, c->ssim_maps.p,
+                  c->ssim_partial.p, loss, (hipStream_t)stream);
+  return check_launch(c, "l1 + d-ssim loss");
 }
 
 sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,

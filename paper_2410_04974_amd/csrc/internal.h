@@ -205,6 +205,11 @@ void launch_density_apply(const float* params, const float* m, const float* v, c
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,
                float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
 int64_t l1_partial_count(int nimg, const int64_t* numel);
+// (1 - lam) L1 + lam (1 - SSIM) over nimg [3][H][W] views: maps holds
+// 9 floats per pixel of every view, partial 2 floats per 16x16 tile and channel.
+int64_t ssim_blocks(int H, int W);
+void launch_l1_dssim(int nimg, const float* const* img, const float* const* tgt, const int32_t* H, const int32_t* W,
+                     float lam, float* const* dimg, float* maps, float* partial, float* loss, hipStream_t st);
 // Adam over `rows` rows of n floats (rows = 76: the parameter layout, one lr
 // per row group; rows = 1: a single vector with lr[0]).  With step_dev the
 // step is *step_dev + 1, and the counter is advanced when `advance`.

@@ -51,7 +51,160 @@ int l1_blocks(int64_t numel) {
 }
 
 
-// With a device step counter the bias corrections are formed on the device
+// ------------------------------------------------------------- D-SSIM
+// SSIM (Wang et al. 2004) per channel and pixel under an 11x11 Gaussian window
+// (sigma 1.5), zero-padded at the border, C1 = 0.01^2, C2 = 0.03^2; the 3DGS
+// loss mixes (1 - lambda) L1 + lambda (1 - mean SSIM), lambda = 0.2 (Sec. 4.4,
+// Sec. 5.1: the paper keeps the 3DGS losses).  Tiles of 16x16 outputs with a
+// 5-pixel halo in LDS, separable passes (rows, then columns).
+constexpr int kSsimTile = 16;
+constexpr int kSsimHalo = 5;
+constexpr int kSsimSpan = kSsimTile + 2 * kSsimHalo;  // 26
+constexpr float kSsimC1 = 0.01f * 0.01f;
+constexpr float kSsimC2 = 0.03f * 0.03f;
+
+struct SsimWin {
+  float g[2 * kSsimHalo + 1];  // normalised 1D Gaussian
+};
+
+// Forward: the five window statistics, SSIM, the partials of SSIM the
+// gradient needs (three maps), and per-block sums of SSIM and |x - y|.
+__global__ void __launch_bounds__(kBlock) k_ssim_fwd(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                     int H, int W, SsimWin win, float* __restrict__ maps,
+                                                     float* __restrict__ partial) {
+  __shared__ float sx[kSsimSpan][kSsimSpan], sy[kSsimSpan][kSsimSpan];
+  __shared__ float hs[5][kSsimSpan][kSsimTile];
+  const int t = threadIdx.x, ch = blockIdx.z;
+  const int64_t HW = (int64_t)H * W;
+  const float* x = img + ch * HW;
+  const float* y = tgt + ch * HW;
+  const int X0 = blockIdx.x * kSsimTile - kSsimHalo, Y0 = blockIdx.y * kSsimTile - kSsimHalo;
+  for (int i = t; i < kSsimSpan * kSsimSpan; i += kBlock) {
+    const int r = i / kSsimSpan, c = i % kSsimSpan, gy = Y0 + r, gx = X0 + c;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    sx[r][c] = in ? x[(int64_t)gy * W + gx] : 0.f;
+    sy[r][c] = in ? y[(int64_t)gy * W + gx] : 0.f;
+  }
+  __syncthreads();
+  for (int i = t; i < kSsimSpan * kSsimTile; i += kBlock) {
+    const int r = i / kSsimTile, c = i % kSsimTile;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+    for (int k = 0; k <= 2 * kSsimHalo; k++) {
+      const float u = sx[r][c + k], v = sy[r][c + k], w = win.g[k];
+      a0 += w * u;
+      a1 += w * v;
+      a2 += w * u * u;
+      a3 += w * v * v;
+      a4 += w * u * v;
+    }
+    hs[0][r][c] = a0;
+    hs[1][r][c] = a1;
+    hs[2][r][c] = a2;
+    hs[3][r][c] = a3;
+    hs[4][r][c] = a4;
+  }
+  __syncthreads();
+  const int ty = t / kSsimTile, tx = t % kSsimTile;
+  float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k <= 2 * kSsimHalo; k++)
+#pragma unroll
+    for (int q = 0; q < 5; q++) m[q] += win.g[k] * hs[q][ty + k][tx];
+  const int px = blockIdx.x * kSsimTile + tx, py = blockIdx.y * kSsimTile + ty;
+  float ssim = 0.f, l1 = 0.f;
+  if (px < W && py < H) {
+    const float mx = m[0], my = m[1];
+    const float vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
+    const float A1 = 2.f * mx * my + kSsimC1, A2 = 2.f * cxy + kSsimC2;
+    const float B1 = mx * mx + my * my + kSsimC1, B2 = vx + vy + kSsimC2;
+    const float iB = 1.f / (B1 * B2);
+    const float S = A1 * A2 * iB;
+    const float f_mx = 2.f * my * A2 * iB - S * 2.f * mx / B1;
+    const float f_vx = -S / B2;
+    const float f_cxy = 2.f * A1 * iB;
+    const int64_t pix = (int64_t)py * W + px;
+    float* mp = maps + (int64_t)ch * 3 * HW;
+    mp[pix] = f_mx - 2.f * mx * f_vx - my * f_cxy;
+    mp[HW + pix] = f_vx;
+    mp[2 * HW + pix] = f_cxy;
+    ssim = S;
+    l1 = fabsf(sx[ty + kSsimHalo][tx + kSsimHalo] - sy[ty + kSsimHalo][tx + kSsimHalo]);
+  }
+  const float bs = block_sum(ssim);
+  const float bl = block_sum(l1);
+  if (t == 0) {
+    const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    partial[2 * b] = bs;
+    partial[2 * b + 1] = bl;
+  }
+}
+
+// Backward: dL/dI = (1 - lambda) sign(x - y) / count - lambda / count *
+// (w*a + 2 x (w*b) + y (w*c)) from the three maps of the forward.
+__global__ void __launch_bounds__(kBlock) k_ssim_bwd(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                     int H, int W, SsimWin win, const float* __restrict__ maps,
+                                                     float lam, float inv_count, float* __restrict__ dimg) {
+  __shared__ float sm[3][kSsimSpan][kSsimSpan];
+  __shared__ float hs[3][kSsimSpan][kSsimTile];
+  const int t = threadIdx.x, ch = blockIdx.z;
+  const int64_t HW = (int64_t)H * W;
+  const float* mp = maps + (int64_t)ch * 3 * HW;
+  const int X0 = blockIdx.x * kSsimTile - kSsimHalo, Y0 = blockIdx.y * kSsimTile - kSsimHalo;
+  for (int i = t; i < kSsimSpan * kSsimSpan; i += kBlock) {
+    const int r = i / kSsimSpan, c = i % kSsimSpan, gy = Y0 + r, gx = X0 + c;
+    const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+    const int64_t pix = (int64_t)gy * W + gx;
+#pragma unroll
+    for (int q = 0; q < 3; q++) sm[q][r][c] = in ? mp[q * HW + pix] : 0.f;
+  }
+  __syncthreads();
+  for (int i = t; i < kSsimSpan * kSsimTile; i += kBlock) {
+    const int r = i / kSsimTile, c = i % kSsimTile;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+    for (int k = 0; k <= 2 * kSsimHalo; k++) {
+      const float w = win.g[k];
+      a0 += w * sm[0][r][c + k];
+      a1 += w * sm[1][r][c + k];
+      a2 += w * sm[2][r][c + k];
+    }
+    hs[0][r][c] = a0;
+    hs[1][r][c] = a1;
+    hs[2][r][c] = a2;
+  }
+  __syncthreads();
+  const int ty = t / kSsimTile, tx = t % kSsimTile;
+  const int px = blockIdx.x * kSsimTile + tx, py = blockIdx.y * kSsimTile + ty;
+  if (px >= W || py >= H) return;
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+#pragma unroll
+  for (int k = 0; k <= 2 * kSsimHalo; k++) {
+    const float w = win.g[k];
+    c0 += w * hs[0][ty + k][tx];
+    c1 += w * hs[1][ty + k][tx];
+    c2 += w * hs[2][ty + k][tx];
+  }
+  const int64_t pix = ch * HW + (int64_t)py * W + px;
+  const float xv = img[pix], yv = tgt[pix], d = xv - yv;
+  const float gs = c0 + 2.f * xv * c1 + yv * c2;
+  const float g1 = (d > 0.f) ? 1.f : ((d < 0.f) ? -1.f : 0.f);
+  dimg[pix] = ((1.f - lam) * g1 - lam * gs) * inv_count;
+}
+
+__global__ void __launch_bounds__(kBlock) k_ssim_final(const float* __restrict__ partial, int64_t nblocks,
+                                                       float lam, float inv_count, float* __restrict__ loss) {
+  float s = 0.f, l = 0.f;
+  for (int64_t i = threadIdx.x; i < nblocks; i += kBlock) {
+    s += partial[2 * i];
+    l += partial[2 * i + 1];
+  }
+  const float ts = block_sum(s);
+  const float tl = block_sum(l);
+  if (threadIdx.x == 0) *loss = (1.f - lam) * tl * inv_count + lam * (1.f - ts * inv_count);
+}
+
+// With a device step counter the bias corrections are formed on the device// With a device step counter the bias corrections are formed on the device
 // from the step about to be taken (*step + 1), so a captured graph advances
 // the step on every replay; k_step_inc then moves the counter on.
 __device__ __forceinline__ void device_bias(AdamArgs& a, const int32_t* step_dev) {
@@ -121,6 +274,36 @@ void launch_l1(int nimg, const float* const* img, const float* const* tgt, const
     off += nb;
   }
   hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, off, inv, loss);
+}
+
+int64_t ssim_blocks(int H, int W) {
+  return (int64_t)((W + kSsimTile - 1) / kSsimTile) * ((H + kSsimTile - 1) / kSsimTile) * 3;
+}
+
+void launch_l1_dssim(int nimg, const float* const* img, const float* const* tgt, const int32_t* H, const int32_t* W,
+                     float lam, float* const* dimg, float* maps, float* partial, float* loss, hipStream_t st) {
+  SsimWin win;
+  double g[2 * kSsimHalo + 1], sum = 0;
+  for (int k = 0; k <= 2 * kSsimHalo; k++) {
+    const double d = k - kSsimHalo;
+    g[k] = __builtin_exp(-d * d / (2.0 * 1.5 * 1.5));
+    sum += g[k];
+  }
+  for (int k = 0; k <= 2 * kSsimHalo; k++) win.g[k] = (float)(g[k] / sum);
+  int64_t count = 0;
+  for (int k = 0; k < nimg; k++) count += 3 * (int64_t)H[k] * W[k];
+  const float inv = 1.0f / (float)count;
+  int64_t boff = 0, moff = 0;
+  for (int k = 0; k < nimg; k++) {
+    const dim3 grid((W[k] + kSsimTile - 1) / kSsimTile, (H[k] + kSsimTile - 1) / kSsimTile, 3);
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(kBlock), 0, st, img[k], tgt[k], H[k], W[k], win, maps + moff,
+                       partial + 2 * boff);
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(kBlock), 0, st, img[k], tgt[k], H[k], W[k], win, maps + moff, lam, inv,
+                       dimg[k]);
+    boff += ssim_blocks(H[k], W[k]);
+    moff += 9 * (int64_t)H[k] * W[k];
+  }
+  hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(kBlock), 0, st, partial, boff, lam, inv, loss);
 }
 
 AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int step) {

@@ -76,13 +76,16 @@ class Trainer:
     renderer has a fixed pair capacity."""
 
     def __init__(self, params, renderer, lr=DEFAULT_LR, betas=(0.9, 0.999), eps=1e-15, lambda_raw=None,
-                 lr_lambda=1e-2):
+                 lr_lambda=1e-2, lambda_dssim=0.0):
         """``lambda_raw`` (float32 CUDA [n], or None for the renderer's scalar
         lambda) makes the directional-opacity strength a learnable
         per-Gaussian sigmoid(raw); it is updated by its own Adam while
         ``train_lambda`` is True (the paper trains it over a window of
-        iterations and keeps it fixed otherwise)."""
+        iterations and keeps it fixed otherwise).  ``lambda_dssim`` > 0 trains
+        with the full 3DGS loss (1 - l) L1 + l (1 - SSIM) (3DGS: l = 0.2);
+        0 keeps the plain L1 term."""
         self.params = params
+        self.lambda_dssim = lambda_dssim
         self.renderer = renderer
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
@@ -122,7 +125,10 @@ class Trainer:
             self._imgs = [torch.empty((3, c.height, c.width), device=self.params.device) for c in cams]
             self._dl = [torch.empty_like(i) for i in self._imgs]
         self.renderer.forward(self.params, cams, out=self._imgs)
-        self.renderer.ctx.l1_loss(self._imgs, targets, self._dl, self.loss)
+        if self.lambda_dssim > 0:
+            self.renderer.ctx.l1_dssim_loss(self._imgs, targets, self._dl, self.loss, self.lambda_dssim)
+        else:
+            self.renderer.ctx.l1_loss(self._imgs, targets, self._dl, self.loss)
         self.step_count += 1
         if fused:
             self.renderer.ctx.backward_adam(self.params, self._dl, self.m, self.v, self.lr, self.step_count,
