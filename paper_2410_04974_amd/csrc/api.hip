@@ -52,6 +52,8 @@ struct sixdgs_ctx {
   // per-entry workspace
   DevBuf<Rec> rec;
   DevBuf<uint32_t> tiles, dkey0, dkey1, dval0, dval1, poff;
+  DevBuf<float> depth;                  // [E] camera depth per entry (written by the preprocess)
+  const float* bin_depth = nullptr;     // the caller's depth array during sixdgs_bin
   // per-pair workspace
   DevBuf<uint32_t> pkey0, pkey1, pval0, pval1;
   DevBuf<uint2> ranges;
@@ -202,7 +204,7 @@ DevSettings dev_settings(const sixdgs_settings& s) {
 bool ensure_entries(sixdgs_ctx* c, int64_t E) {
   const int64_t e1 = E > 0 ? E : 1;
   return c->rec.ensure(e1) && c->tiles.ensure(e1) && c->dkey0.ensure(e1) && c->dkey1.ensure(e1) &&
-         c->dval0.ensure(e1) && c->dval1.ensure(e1) && c->poff.ensure(e1);
+         c->dval0.ensure(e1) && c->dval1.ensure(e1) && c->poff.ensure(e1) && c->depth.ensure(e1);
 }
 
 bool ensure_scratch(sixdgs_ctx* c, int64_t E, int64_t pcap) {
@@ -238,6 +240,7 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.E = E;
   b.tiles = c->tiles.p;
   b.rec = c->rec.p;
+  b.depth = c->bin_depth ? c->bin_depth : c->depth.p;
   b.dkey[0] = c->dkey0.p;
   b.dkey[1] = c->dkey1.p;
   b.dval[0] = c->dval0.p;
@@ -388,6 +391,7 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   collect_timing(c);
   for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
   c->rec.release();
+  c->depth.release();
   c->tiles.release();
   c->dkey0.release();
   c->dkey1.release();
@@ -462,7 +466,7 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
   c->fwd_lambda = c->lambda_raw;
   {
     Timer t(c, SIXDGS_K_PREPROCESS, st);
-    launch_preprocess(params, n, vt, ds, c->rec.p, c->tiles.p, st);
+    launch_preprocess(params, n, vt, ds, c->rec.p, c->tiles.p, c->depth.p, st);
   }
   sixdgs_status rc = check_launch(c, "preprocess");
   if (rc != SIXDGS_OK) return rc;
@@ -710,7 +714,9 @@ sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, in
   if (!ensure_entries(c, E)) return fail(c, SIXDGS_ERR_OOM, "entry buffers");
   c->vt = vt;
   launch_import_records(u, v, ex, ey, depth, alive, vt, c->rec.p, c->tiles.p, st);
+  c->bin_depth = depth;
   sixdgs_status rc = run_binning(c, E, st);
+  c->bin_depth = nullptr;
   c->fwd_E = E;
   c->fwd_px = 0;
   c->fwd_n = n;

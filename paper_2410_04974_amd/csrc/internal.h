@@ -108,7 +108,7 @@ __device__ __forceinline__ void adam_update(float& p, float g, float& m, float& 
 // ----------------------------------------------------------- host launchers
 // preprocess.hip
 void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
-                       uint32_t* tiles, hipStream_t st);
+                       uint32_t* tiles, float* depth, hipStream_t st);
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st);
 // The same chain rule with an Adam step applied to params/m/v in place of writing the gradient.
@@ -124,6 +124,7 @@ struct SortBuffers {
   int64_t E;
   uint32_t* tiles;      // [E] tiles touched (input)
   const Rec* rec;       // [E]
+  const float* depth;   // [E] camera depth of every binned entry
   uint32_t* dkey[2];    // [E] depth keys (ping-pong)
   uint32_t* dval[2];    // [E] entry ids
   uint32_t* poff;       // [E] exclusive pair offsets of the depth-sorted entries

@@ -146,7 +146,7 @@ __device__ __forceinline__ bool view_state(const Static& s, const ViewDesc& vd, 
 
 __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__ params, int64_t n, ViewTable vt,
                                                        DevSettings ds, Rec* __restrict__ rec,
-                                                       uint32_t* __restrict__ tiles) {
+                                                       uint32_t* __restrict__ tiles, float* __restrict__ depth) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= n) return;
   Static s;
@@ -182,6 +182,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__
         r.b = make_float4(w.Q[2], w.ac, ex, ey);
         r.c = make_float4(col[0], col[1], col[2], w.p[2]);
         rec[e] = r;
+        depth[e] = w.p[2];  // also on its own, for the integer stage's coalesced reads
       }
     }
     tiles[e] = count;
@@ -437,10 +438,10 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
 }  // namespace
 
 void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
-                       uint32_t* tiles, hipStream_t st) {
+                       uint32_t* tiles, float* depth, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, rec, tiles);
+  hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, rec, tiles, depth);
 }
 
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,

@@ -66,7 +66,8 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t& total)
 // word instead of spinning forever.
 constexpr int kRItems = 16;
 constexpr int kRChunk = kBlock * kRItems;  // items per workgroup and pass over the pairs
-constexpr int kRItemsSmall = 4;           // the depth sort: 1024 items per workgroup, 4x the workgroups
+constexpr int kRItemsSmall = 4;           // short depth sorts: 1024 items per workgroup, 4x the workgroups
+constexpr int64_t kLargeSort = 1 << 20;    // from this many entries the depth sort uses kRItems
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStIncl = 2u << 30;
 constexpr uint32_t kStVal = kStAgg - 1u;
@@ -405,11 +406,11 @@ struct BinnedFlag {
   __device__ uint32_t operator()(int64_t i) const { return tiles[i] > 0 ? 1u : 0u; }
 };
 struct CompactDepth {
-  const Rec* rec;
+  const float* depth;
   uint32_t* dkey;
   uint32_t* dval;
   // depths of binned entries exceed z_near > 0, so their bit patterns order as the values
-  __device__ uint32_t key(int64_t i) const { return __float_as_uint(rec[i].c.w); }
+  __device__ uint32_t key(int64_t i) const { return __float_as_uint(depth[i]); }
   __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const {
     if (v) {
       dkey[pre] = key(i);
@@ -503,15 +504,26 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
     if (s_h[p][t]) atomicAdd(&ghist[p * 256 + t], s_h[p][t]);
 }
 
+constexpr int kRangeItems = 8;  // consecutive pairs per thread
+
 __global__ void __launch_bounds__(kBlock) k_ranges(const uint32_t* __restrict__ pkey, const uint32_t* counters,
                                                    uint32_t pcap, uint32_t total_tiles, uint2* __restrict__ ranges) {
   const uint32_t P = counters[1];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (P > pcap || i >= P) return;  // on overflow the pair lists were not written: leave every range empty
-  const uint32_t k = pkey[i];
-  if (k >= total_tiles) return;
-  if (i == 0 || pkey[i - 1] != k) ranges[k].x = (uint32_t)i;
-  if (i == (int64_t)P - 1 || pkey[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kRangeItems;
+  if (P > pcap || i0 >= P) return;  // on overflow the pair lists were not written: leave every range empty
+  uint32_t k[kRangeItems + 2];  // pairs i0 - 1 .. i0 + kRangeItems; past either end: no tile
+#pragma unroll
+  for (int j = 0; j < kRangeItems + 2; j++) {
+    const int64_t i = i0 - 1 + j;
+    k[j] = (i >= 0 && i < (int64_t)P) ? pkey[i] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 1; j <= kRangeItems; j++) {
+    const uint32_t key = k[j];
+    if (key >= total_tiles) continue;  // also the slots past P
+    if (k[j - 1] != key) ranges[key].x = (uint32_t)(i0 + j - 1);
+    if (k[j + 1] != key) ranges[key].y = (uint32_t)(i0 + j);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_zero_g2d(const uint32_t* __restrict__ dval, const uint32_t* counters,
@@ -550,14 +562,15 @@ __global__ void __launch_bounds__(kBlock) k_import(const float* __restrict__ u, 
 
 void launch_bin_count(SortBuffers& b, hipStream_t st) {
   const uint32_t E = (uint32_t)b.E;
-  const RadixState rs = radix_state(b.rstate_depth, b.E, kRItemsSmall, true);
+  // short sorts take small workgroups (more of them in flight); long ones the pairs' size
+  const RadixState rs = radix_state(b.rstate_depth, b.E, b.E >= kLargeSort ? kRItems : kRItemsSmall, true);
   const RadixPlan plan{4, 8};
   const unsigned gprep = (unsigned)((rs.words() / 4 + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_stage_prep, dim3(gprep), dim3(kBlock), 0, st, rs, (uint2*)nullptr, (int64_t)0,
                      (const uint32_t*)b.counters, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
                      (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0, (uint32_t*)nullptr, (int64_t)0);
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
-  scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.rec, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
+  scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.depth, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
               rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
   // depth order (stable: equal depths keep entry order)
   b.dsorted = radix_sort(b.dkey, b.dval, &b.counters[0], b.E, plan, rs, &b.counters[3], st);
@@ -587,7 +600,7 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
                        b.blk_start, b.counters, (uint32_t)b.pcap, plan.npass, plan.dbits, rs.ghist, b.pkey[0],
                        b.pval[0]);
   b.psorted = radix_sort(b.pkey, b.pval, &b.counters[1], bound, plan, rs, &b.counters[3], st);
-  const unsigned gp = (unsigned)((bound + kBlock - 1) / kBlock);
+  const unsigned gp = (unsigned)((bound + (int64_t)kBlock * kRangeItems - 1) / ((int64_t)kBlock * kRangeItems));
   if (gp)
     hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
                        (uint32_t)vt.total_tiles, b.ranges);
