@@ -75,7 +75,7 @@ typedef struct {
   float bg[3];         /* background colour */
   int32_t tile_w;      /* screen tile width in pixels: 8, 16 or 32 */
   int32_t tile_h;      /* screen tile height: tile_w * tile_h must be 256 */
-  int32_t batch;       /* Gaussians staged in LDS per tile batch: 64, 128 or 256 */
+  int32_t batch;       /* Gaussians staged in LDS per backward batch: 64, 128 or 256 */
   int64_t pair_capacity; /* 0: grow the (tile, Gaussian) pair buffers on demand
                             (sixdgs_forward then waits once on the stream to
                             read the pair count); > 0: fixed capacity, no host

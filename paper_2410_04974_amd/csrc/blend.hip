@@ -3,14 +3,15 @@
 // the last contributor saved per pixel, and the reverse walk that turns dL/dI
 // into per-Gaussian screen-space gradients.
 //
-// One workgroup of 256 threads per screen tile, one pixel per thread; each
-// 64-lane wavefront owns an 8x8 block of the tile.  The tile's depth-ordered
-// list is staged through LDS in batches; while staging, each Gaussian's
-// alpha >= 1/255 ellipse is tested exactly against the four blocks and every
-// wavefront gets its own order-preserving list of the Gaussians that can reach
-// its pixels, so the per-pixel loop -- the kernels' critical path, since a
-// screen this size has fewer wavefronts than the chip can hold -- never
-// visits a Gaussian its block cannot see.
+// One workgroup of 256 threads per screen tile (forward) or per chunk of a
+// tile's list (backward), one pixel per thread; each 64-lane wavefront owns an
+// 8x8 block of the tile.  Each Gaussian's alpha >= 1/255 ellipse is tested
+// exactly against a block before that block's pixels see it, so the
+// per-pixel loop -- the kernels' critical path -- never visits a Gaussian its
+// block cannot reach.  The forward's wavefronts walk the list independently
+// (a tile's blocks differ in depth complexity, and a shared batch would hold
+// every wavefront to the slowest); the backward stages one LDS batch for the
+// workgroup and builds the four per-block lists from it.
 #include "internal.h"
 
 namespace sixdgs {
@@ -175,57 +176,75 @@ __device__ __forceinline__ void fetch_group(const BatchLDS& L, uint32_t lw, uint
   }
 }
 
+// Forward staging: every wavefront walks the tile's list on its own, 64 list
+// entries per step, keeps the Gaussians whose alpha >= 1/255 ellipse meets
+// its 8x8 block, compacted in its own LDS buffer, and composites them once 64
+// have gathered (or at a chunk boundary, or at the list's end).  No wavefront
+// waits for another, and the loads of the next step are in flight while the
+// current one is tested and blended.
+constexpr int kFwdStep = 64;
+constexpr int kFwdBuf = 128;  // pending hits stay below 64 before a step adds at most 64
+struct FwdWaveLDS {
+  float4 a[kFwdBuf];  // u, v, cA, cB
+  float2 b[kFwdBuf];  // cC, log2(alpha_cond)
+  float4 c[kFwdBuf];  // r, g, b, 1-based list position (bits)
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int TW>
 __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings ds, const Rec* __restrict__ rec,
                                                       const uint2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ pval, BlendState bs, int batch) {
-  __shared__ BatchLDS L;
+                                                      const uint32_t* __restrict__ pval, BlendState bs) {
+  __shared__ FwdWaveLDS W[kWaves];
+  __shared__ uint32_t s_maxlast;
   const int tile = blockIdx.x;
   const int vi = find_view(vt, tile);
   const ViewDesc& vd = vt.v[vi];
   const int local = tile - vd.tile_base;
   const int tx = local % vd.ntx, ty = local / vd.ntx;
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const float ox = (float)(tx * TW) + 0.5f, oy = (float)(ty * TileMap<TW>::TH) + 0.5f;
+  const float bx0 = (float)(tx * TW + TileMap<TW>::bx(wv)) + 0.5f;
+  const float by0 = (float)(ty * TileMap<TW>::TH + TileMap<TW>::by(wv)) + 0.5f;
   const int px = tx * TW + TileMap<TW>::bx(wv) + (l & 7);
   const int py = ty * TileMap<TW>::TH + TileMap<TW>::by(wv) + (l >> 3);
   const bool inside = px < vd.W && py < vd.H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const uint32_t* list4 = reinterpret_cast<const uint32_t*>(L.list[wv]);
+  FwdWaveLDS& B = W[wv];
+  const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
 
-  __shared__ uint32_t s_maxlast;
   if (threadIdx.x == 0) s_maxlast = 0;
+  __syncthreads();
   const uint2 rg = ranges[tile];
+  const uint32_t n = rg.y - rg.x;
+  const uint32_t* pv = pval + rg.x;
+  const uint32_t chunk = bs.chunk;
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // colour of the current backward chunk alone
+  float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // colour of the current chunk alone
   uint32_t last = 0, cnt = 0, nbd = 0;
   bool done = !inside;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += batch) {
-    if (__syncthreads_count(!done) == 0) break;
-    const uint32_t rel = b0 - rg.x;
-    if (rel != 0 && (rel & (bs.chunk - 1)) == 0) {
-      // a backward work item starts here: keep this pixel's transmittance and
-      // the colour of the chunk that ends here
-      const int64_t slot = b0 / bs.chunk;
-      if (slot < bs.nbound) bs.bound[slot * kBlock + threadIdx.x] = make_float4(T, K0, K1, K2);
-      K0 = K1 = K2 = 0.f;
-      nbd++;
-    }
-    const uint32_t nb = min((uint32_t)batch, rg.y - b0);
-    const uint32_t wn = stage_batch<TW>(L, rec, pval, b0, nb, ox, oy);
-    const uint32_t pos0 = b0 - rg.x + 1;
-    // groups of four list slots (slots past wn hold stale but in-range bytes)
-    const uint32_t lw = list4[l];
-    const uint32_t ng = (wn + 3) >> 2;
-    auto blend = [&](const Group4& G, uint32_t g) {
-      const uint32_t nu = min(4u, wn - 4 * g);
+
+  auto composite = [&](uint32_t nh) {
+    for (uint32_t g = 0; 4 * g < nh; g++) {
+      if (__ballot(!done) == 0) break;
+      const uint32_t nu = min(4u, nh - 4 * g);
+      float4 A[4], Cc[4];
+      float2 Bq[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        A[u] = B.a[4 * g + u];
+        Bq[u] = B.b[4 * g + u];
+        Cc[u] = B.c[4 * g + u];
+      }
       // predicated rather than branched: the lanes of a wavefront rarely agree
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         if ((uint32_t)u >= nu) break;
-        const float4 A = G.a[u];
-        const float4 B = make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f);
-        const float p = log2_alpha(A, B, fx - A.x, fy - A.y);
+        const float p = log2_alpha(A[u], make_float4(Bq[u].x, Bq[u].y, 0.f, 0.f), fx - A[u].x, fy - A[u].y);
         const float a = fminf(kAlphaMax, exp2_fast(p));
         const float Tn = T * (1.0f - a);
         const bool take = !done && p >= kLog2AlphaMin;
@@ -233,27 +252,79 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
         done = done || stop;
         const bool use = take && !stop;
         const float wgt = use ? a * T : 0.f;
-        C0 += G.c[u].x * wgt;
-        C1 += G.c[u].y * wgt;
-        C2 += G.c[u].z * wgt;
-        K0 += G.c[u].x * wgt;
-        K1 += G.c[u].y * wgt;
-        K2 += G.c[u].z * wgt;
+        C0 += Cc[u].x * wgt;
+        C1 += Cc[u].y * wgt;
+        C2 += Cc[u].z * wgt;
+        K0 += Cc[u].x * wgt;
+        K1 += Cc[u].y * wgt;
+        K2 += Cc[u].z * wgt;
         T = use ? Tn : T;
-        last = use ? pos0 + G.j[u] : last;
+        last = use ? __float_as_uint(Cc[u].w) : last;
         cnt += use ? 1u : 0u;
       }
-    };
-    for (uint32_t g = 0; g < ng; g++) {
-      if (__ballot(!done) == 0) break;
-      Group4 X;
-      fetch_group(L, lw, g, X);
-      blend(X, g);
     }
+  };
+
+  // software pipeline: entry ids two steps ahead, records one step ahead
+  uint32_t e_cur = 0, e_nxt = 0;
+  Rec r_cur{};
+  if ((uint32_t)l < n) e_cur = pv[l];
+  if ((uint32_t)(kFwdStep + l) < n) e_nxt = pv[kFwdStep + l];
+  if ((uint32_t)l < n) r_cur = rec[e_cur];
+  uint32_t nh = 0;  // pending hits in B (uniform)
+  for (uint32_t s0 = 0; s0 < n; s0 += kFwdStep) {
+    if (__ballot(!done) == 0) break;
+    Rec r_nxt{};
+    uint32_t e_nn = 0;
+    if (s0 + kFwdStep + l < n) r_nxt = rec[e_nxt];
+    if (s0 + 2 * kFwdStep + l < n) e_nn = pv[s0 + 2 * kFwdStep + l];
+    if (s0 != 0 && (s0 & (chunk - 1)) == 0) {
+      // a backward work item starts here: finish the chunk, then keep this
+      // pixel's transmittance and the colour of the chunk that ends here
+      composite(nh);
+      nh = 0;
+      const int64_t slot = ((int64_t)rg.x + s0) / chunk;
+      if (slot < bs.nbound) bs.bound[slot * kBlock + threadIdx.x] = make_float4(T, K0, K1, K2);
+      K0 = K1 = K2 = 0.f;
+      nbd++;
+    }
+    const bool hit = (s0 + l < n) && ellipse_hits(r_cur, bx0, by0);
+    const uint64_t bal = __ballot(hit);
+    if (hit) {
+      const uint32_t k = nh + (uint32_t)__popcll(bal & lt);
+      B.a[k] = make_float4(r_cur.a.x, r_cur.a.y, -0.5f * kLog2e * r_cur.a.z, -kLog2e * r_cur.a.w);
+      B.b[k] = make_float2(-0.5f * kLog2e * r_cur.b.x, __log2f(r_cur.b.y));
+      B.c[k] = make_float4(r_cur.c.x, r_cur.c.y, r_cur.c.z, __uint_as_float(s0 + l + 1));
+    }
+    nh += (uint32_t)__popcll(bal);
+    wave_lds_sync();
+    if (nh >= kFwdStep) {
+      composite(nh);
+      nh = 0;
+      wave_lds_sync();
+    }
+    r_cur = r_nxt;
+    e_nxt = e_nn;
+  }
+  composite(nh);
+
+  // turn the per-chunk colours into the colour behind each boundary: sums of
+  // positive terms from the back, so no cancellation against the total
+  float S0 = K0, S1 = K1, S2 = K2;
+  for (uint32_t m = nbd; m >= 1; m--) {
+    const int64_t slot = ((int64_t)rg.x + (int64_t)m * chunk) / chunk;
+    if (slot >= bs.nbound) continue;
+    float4* q = bs.bound + slot * kBlock + threadIdx.x;
+    const float4 v = *q;
+    *q = make_float4(v.x, S0, S1, S2);
+    S0 += v.y;
+    S1 += v.z;
+    S2 += v.w;
   }
   if (inside) {
     const int64_t HW = (int64_t)vd.W * vd.H;
     const int64_t pix = (int64_t)py * vd.W + px;
+    // the running sum, whose rounding does not depend on where chunks begin
     vd.img[pix] = C0 + T * ds.bg[0];
     vd.img[HW + pix] = C1 + T * ds.bg[1];
     vd.img[2 * HW + pix] = C2 + T * ds.bg[2];
@@ -261,25 +332,10 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
     bs.last[vd.pix_base + pix] = last;
     if (bs.counts) bs.counts[vd.pix_base + pix] = cnt;
   }
-  // turn the per-chunk colours into the colour behind each boundary: sums of
-  // positive terms from the back, so no cancellation against the total
-  {
-    float S0 = K0, S1 = K1, S2 = K2;
-    for (uint32_t m = nbd; m >= 1; m--) {
-      const int64_t slot = (int64_t)(rg.x + m * bs.chunk) / bs.chunk;
-      if (slot >= bs.nbound) continue;
-      float4* q = bs.bound + slot * kBlock + threadIdx.x;
-      const float4 v = *q;
-      *q = make_float4(v.x, S0, S1, S2);
-      S0 += v.y;
-      S1 += v.z;
-      S2 += v.w;
-    }
-  }
   const uint32_t wlast = wave_max(last);
-  if ((threadIdx.x & 63) == 0) atomicMax(&s_maxlast, wlast);
+  if (l == 0) atomicMax(&s_maxlast, wlast);
   __syncthreads();
-  if (threadIdx.x == 0) bs.tile_nch[tile] = (s_maxlast + bs.chunk - 1) / bs.chunk;
+  if (threadIdx.x == 0) bs.tile_nch[tile] = (s_maxlast + chunk - 1) / chunk;
 }
 
 // ------------------------------------------------------------- reductions
@@ -417,7 +473,9 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
   // behind it (background included), carried as D = dL/dC . S
   float T = Tf;
   float S0 = Tf * ds.bg[0], S1 = Tf * ds.bg[1], S2 = Tf * ds.bg[2];
-  if (cstart + chunk < maxlast) {
+  if (cstart + chunk < last) {
+    // the pixel takes Gaussians past this chunk: resume from the state saved
+    // where the next chunk begins (otherwise its final state is that state)
     const int64_t slot = (int64_t)(rg.x + cstart + chunk) / chunk;
     const float4 st = slot < bs.nbound ? bs.bound[slot * kBlock + threadIdx.x] : make_float4(1.f, 0.f, 0.f, 0.f);
     T = st.x;
@@ -538,9 +596,9 @@ void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec,
   if (vt.total_tiles <= 0) return;
   const dim3 grid(vt.total_tiles);
   switch (vt.tile_w) {
-    case 8: hipLaunchKernelGGL(k_blend_fwd<8>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs, batch); break;
-    case 32: hipLaunchKernelGGL(k_blend_fwd<32>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs, batch); break;
-    default: hipLaunchKernelGGL(k_blend_fwd<16>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs, batch); break;
+    case 8: hipLaunchKernelGGL(k_blend_fwd<8>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
+    case 32: hipLaunchKernelGGL(k_blend_fwd<32>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
+    default: hipLaunchKernelGGL(k_blend_fwd<16>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
   }
 }
 
