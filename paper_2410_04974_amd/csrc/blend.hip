@@ -367,32 +367,11 @@ __device__ __forceinline__ float swap16_add(float a, float b) {
   return __int_as_float(r[0]) + __int_as_float(r[1]);
 }
 
-// Sums nine per-lane values over the wavefront by halving exchanges -- each
-// exchange step halves two values at once -- then adds the totals into LDS
-// column j of s_g ([9][kBlock]): after the two swap stages and the row sums,
-// lanes 0/16/32/48 hold (g0, g2, g1, g3) in k0 and (g4, g6, g5, g7) in k1, and
-// lane 0 holds g8 in k2.
-__device__ __forceinline__ void wave_sum9_to_lds(const float (&g)[kG2D], float (*s_g)[kBlock], int j, int lane) {
-  const float h0 = swap32_add(g[0], g[1]);
-  const float h1 = swap32_add(g[2], g[3]);
-  const float h2 = swap32_add(g[4], g[5]);
-  const float h3 = swap32_add(g[6], g[7]);
-  const float h4 = swap32_add(g[8], g[8]);
-  const float k0 = row_sum(swap16_add(h0, h1));
-  const float k1 = row_sum(swap16_add(h2, h3));
-  const float k2 = row_sum(swap16_add(h4, h4));
-  if ((lane & 15) == 0) {
-    const int row = lane >> 4;
-    const int f0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-    atomicAdd(&s_g[f0][j], k0);
-    atomicAdd(&s_g[f0 + 4][j], k1);
-    if (row == 0) atomicAdd(&s_g[8][j], k2);
-  }
-}
-
-// The same for two Gaussians at once (18 values, slots ja and jb): after the
-// swap stages the rows of k0..k4 hold (a0 a2 a1 a3), (a4 a6 a5 a7),
-// (a8 b0 b8 b1), (b2 b4 b3 b5) and (b6 b6 b7 b7).
+// Sums the nine per-lane values of two Gaussians (slots ja and jb) over the
+// wavefront by halving exchanges -- each exchange step halves two values at
+// once -- then adds the totals into LDS columns ja and jb of s_g ([9][kBlock]).
+// After the two swap stages and the row sums, the rows of k0..k4 hold
+// (a0 a2 a1 a3), (a4 a6 a5 a7), (a8 b0 b8 b1), (b2 b4 b3 b5) and (b6 b6 b7 b7).
 __device__ __forceinline__ void wave_sum18_to_lds(const float (&a)[kG2D], const float (&b)[kG2D],
                                                   float (*s_g)[kBlock], int ja, int jb, int lane) {
   const float h0 = swap32_add(a[0], a[1]);
@@ -533,19 +512,20 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
       gv[8] = dC2 * wgt;
       return true;
     };
-    // back to front in pairs, reduced together when both contributed
+    // back to front in pairs, always reduced together (a Gaussian no lane took
+    // adds zeros): one straight-line reduction needs no register copies for
+    // the in-place lane swaps, which the three-way choice between a joint and
+    // two single reductions did
     auto grad = [&](const Group4& G, int g) {
 #pragma unroll
       for (int h = 1; h >= 0; h--) {
         float ga[kG2D], gb[kG2D];
+#pragma unroll
+        for (int k = 0; k < kG2D; k++) ga[k] = gb[k] = 0.f;
         const bool aa = eval(G, g, 2 * h + 1, ga);
         const bool ab = eval(G, g, 2 * h, gb);
-        if (aa && ab)
+        if (aa || ab)
           wave_sum18_to_lds(ga, gb, s_g, (int)G.j[2 * h + 1], (int)G.j[2 * h], l);
-        else if (aa)
-          wave_sum9_to_lds(ga, s_g, (int)G.j[2 * h + 1], l);
-        else if (ab)
-          wave_sum9_to_lds(gb, s_g, (int)G.j[2 * h], l);
       }
     };
     for (int g = ng - 1; g >= 0; g--) {
