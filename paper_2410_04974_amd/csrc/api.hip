@@ -569,7 +569,7 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, cons
   const AdamArgs a = make_adam_args(lr, beta1, beta2, eps, step);
   {
     Timer t(c, SIXDGS_K_PREPROCESS_BWD, st);
-    launch_preprocess_bwd_adam(params, n, vt, ds, c->tiles.p, c->g2d.p, m, v, a, densify, st);
+    launch_preprocess_bwd_adam(params, n, vt, ds, c->tiles.p, c->g2d.p, m, v, a, nullptr, densify, st);
   }
   c->have_fwd = false;  // the parameters moved
   return check_launch(c, "preprocess backward + Adam");

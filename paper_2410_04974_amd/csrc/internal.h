@@ -114,7 +114,7 @@ void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, 
 // The same chain rule with an Adam step applied to params/m/v in place of writing the gradient.
 void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                                 const uint32_t* tiles, const float* g2d, float* m, float* v, const AdamArgs& a,
-                                float* densify, hipStream_t st);
+                                const int32_t* step_dev, float* densify, hipStream_t st);
 
 // sort.hip -- the integer stage
 constexpr int kMaxPasses = 4;  // radix passes of at most 8 bits over a 32-bit key

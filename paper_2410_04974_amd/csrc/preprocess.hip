@@ -196,29 +196,22 @@ struct GradToBuffer {
   float* grad;
   __device__ void put(int row, int64_t n, int64_t g, float v) const { grad[row * n + g] = v; }
 };
-struct GradToAdam {
-  float* p;
-  float* m;
-  float* v;
-  AdamArgs a;
-  __device__ void put(int row, int64_t n, int64_t g, float gv) const {
-    const int64_t k = row * n + g;
-    float pp = p[k], mm = m[k], vv = v[k];
-    adam_update(pp, gv, mm, vv, a.lr[adam_row_group(row)], a);
-    p[k] = pp;
-    m[k] = mm;
-    v[k] = vv;
-  }
+// ... or to this wavefront's rows in LDS ([kRows][64]), for an Adam step
+// that streams the parameter and moment rows afterwards.
+struct GradToLDS {
+  float* rows;
+  __device__ void put(int row, int64_t, int64_t, float v) const { rows[row * 64 + (threadIdx.x & 63)] = v; }
 };
 
-// params is read before the sink writes (the Adam sink writes the same rows),
-// so it is not declared __restrict__.
+// The chain rule from the screen-space gradients of Gaussian g back to its 76
+// parameters, summed over the views, handed to the sink row by row.  params
+// may be updated in place after this returns (by the fused Adam step), so it
+// is not declared __restrict__.
 template <class Sink>
-__global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, int64_t n, ViewTable vt,
-                                                           DevSettings ds, const uint32_t* __restrict__ tiles,
-                                                           const float* __restrict__ g2d, Sink sink,
-                                                           float* __restrict__ densify) {
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int64_t g, const ViewTable& vt,
+                                             const DevSettings& ds, const uint32_t* __restrict__ tiles,
+                                             const float* __restrict__ g2d, const Sink& sink,
+                                             float* __restrict__ densify) {
   if (g >= n) return;
   bool any = false;
   for (int vi = 0; vi < vt.nview; vi++) any |= tiles[(int64_t)vi * n + g] > 0;
@@ -435,6 +428,65 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
   if (ds.lambda_raw && ds.grad_lambda) ds.grad_lambda[g] = any ? g_lam * lam * (1.f - lam) : 0.f;
 }
 
+template <class Sink>
+__global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, int64_t n, ViewTable vt,
+                                                           DevSettings ds, const uint32_t* __restrict__ tiles,
+                                                           const float* __restrict__ g2d, Sink sink,
+                                                           float* __restrict__ densify) {
+  bwd_gaussian(params, n, (int64_t)blockIdx.x * kBlock + threadIdx.x, vt, ds, tiles, g2d, sink, densify);
+}
+
+// The chain rule with the gradient rows kept in LDS, then one Adam step over
+// this wavefront's 64 Gaussians: rows are streamed in groups of 19 (the
+// chain rule's registers are free by then), so each lane has 57 loads in
+// flight instead of the three of a per-row update.
+constexpr int kAdamGroup = 19;  // kRows = 4 groups
+__global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, int64_t n, ViewTable vt,
+                                                                DevSettings ds, const uint32_t* __restrict__ tiles,
+                                                                const float* __restrict__ g2d,
+                                                                float* __restrict__ m, float* __restrict__ v,
+                                                                AdamArgs a, const int32_t* step_dev,
+                                                                float* __restrict__ densify) {
+  __shared__ float s_g[kBlock / 64][kRows * 64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bwd_gaussian(params, n, g, vt, ds, tiles, g2d, GradToLDS{s_g[wv]}, densify);
+  if (step_dev) {
+    const float t = (float)(*step_dev + 1);
+    a.bc1 = 1.0f - powf(a.b1, t);
+    a.bc2 = 1.0f - powf(a.b2, t);
+  }
+  // each lane reads back only what it wrote: ordering the wavefront's own LDS
+  // accesses is enough
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (g >= n) return;
+  static_assert(kRows % kAdamGroup == 0, "row groups");
+  for (int r0 = 0; r0 < kRows; r0 += kAdamGroup) {
+    float pp[kAdamGroup], mm[kAdamGroup], vv[kAdamGroup];
+#pragma unroll
+    for (int j = 0; j < kAdamGroup; j++) {
+      const int64_t k = (int64_t)(r0 + j) * n + g;
+      pp[j] = params[k];
+      mm[j] = m[k];
+      vv[j] = v[k];
+    }
+#pragma unroll
+    for (int j = 0; j < kAdamGroup; j++) {
+      const int r = r0 + j;
+      const int64_t k = (int64_t)r * n + g;
+      const int grp = adam_row_group(r);  // selected, not indexed: keeps a.lr out of scratch memory
+      const float lr = grp == 0 ? a.lr[0] : grp == 1 ? a.lr[1] : grp == 2 ? a.lr[2] : grp == 3 ? a.lr[3]
+                     : grp == 4 ? a.lr[4] : a.lr[5];
+      adam_update(pp[j], s_g[wv][r * 64 + lane], mm[j], vv[j], lr, a);
+      params[k] = pp[j];
+      m[k] = mm[j];
+      v[k] = vv[j];
+    }
+  }
+}
+
 }  // namespace
 
 void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
@@ -454,11 +506,11 @@ void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, 
 
 void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                                 const uint32_t* tiles, const float* g2d, float* m, float* v, const AdamArgs& a,
-                                float* densify, hipStream_t st) {
+                                const int32_t* step_dev, float* densify, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess_bwd<GradToAdam>, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d,
-                     GradToAdam{params, m, v, a}, densify);
+  hipLaunchKernelGGL(k_preprocess_bwd_adam, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, m, v, a,
+                     step_dev, densify);
 }
 
 }  // namespace sixdgs

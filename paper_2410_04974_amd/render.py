@@ -116,11 +116,12 @@ class Trainer:
                           step_counter=self.step_counter, beta1=self.betas[0], beta2=self.betas[1], eps=self.eps)
 
     def step(self, cams, targets, densify=None, fused=False):
-        """Render, L1 loss, backward, Adam.  fused=True applies Adam inside the
-        preprocess backward (the gradient never reaches memory, but the in-place
-        per-row updates serialise on load latency: slower on MI355X today);
-        fused=False writes the gradient to self.grad and runs the streaming Adam
-        kernel."""
+        """Render, L1 loss, backward, Adam.  fused=True applies Adam at the end
+        of the preprocess backward (the gradient rows stay in LDS and never
+        reach memory; the host passes the step count); fused=False writes the
+        gradient to self.grad and runs the streaming Adam kernel on the
+        device step counter, so the step can be captured in a graph.  The two
+        take about the same time on MI355X."""
         if self._imgs is None or [tuple(i.shape) for i in self._imgs] != [(3, c.height, c.width) for c in cams]:
             self._imgs = [torch.empty((3, c.height, c.width), device=self.params.device) for c in cams]
             self._dl = [torch.empty_like(i) for i in self._imgs]
