@@ -229,6 +229,10 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
   bool done = !inside;
 
   auto composite = [&](uint32_t nh) {
+    // the group that ends past nh reads stale slots: give them a zero colour
+    // so that their (never used) weight of zero multiplies finite values
+    if ((uint32_t)l < ((4u - (nh & 3u)) & 3u)) B.c[nh + l] = make_float4(0.f, 0.f, 0.f, 0.f);
+    wave_lds_sync();
     for (uint32_t g = 0; 4 * g < nh; g++) {
       if (__ballot(!done) == 0) break;
       const uint32_t nu = min(4u, nh - 4 * g);
@@ -240,14 +244,14 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
         Bq[u] = B.b[4 * g + u];
         Cc[u] = B.c[4 * g + u];
       }
-      // predicated rather than branched: the lanes of a wavefront rarely agree
+      // predicated rather than branched, also past the last slot, so the four
+      // records are read at once: the lanes of a wavefront rarely agree
 #pragma unroll
       for (int u = 0; u < 4; u++) {
-        if ((uint32_t)u >= nu) break;
         const float p = log2_alpha(A[u], make_float4(Bq[u].x, Bq[u].y, 0.f, 0.f), fx - A[u].x, fy - A[u].y);
         const float a = fminf(kAlphaMax, exp2_fast(p));
         const float Tn = T * (1.0f - a);
-        const bool take = !done && p >= kLog2AlphaMin;
+        const bool take = (uint32_t)u < nu && !done && p >= kLog2AlphaMin;
         const bool stop = take && Tn < kTMin;
         done = done || stop;
         const bool use = take && !stop;
