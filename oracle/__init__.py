@@ -65,7 +65,8 @@ class _Set(ctypes.Structure):
                 ("jac_guard", ctypes.c_double), ("dilation", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("t_min", ctypes.c_double), ("amb_alpha_min", ctypes.c_double),
                 ("amb_alpha_max", ctypes.c_double), ("amb_t_min", ctypes.c_double), ("amb_depth", ctypes.c_double),
-                ("amb_impact", ctypes.c_double), ("lambda_raw", ctypes.c_void_p), ("grad_lambda", ctypes.c_void_p)]
+                ("amb_impact", ctypes.c_double), ("lambda_raw", ctypes.c_void_p), ("grad_lambda", ctypes.c_void_p),
+                ("color_rgb", ctypes.c_int64)]
 
 
 @dataclass
@@ -89,6 +90,9 @@ class Settings:
     amb_t_min: float = 1e-7
     amb_depth: float = 5e-7
     amb_impact: float = 2.5e-5
+    # False: colour from the degree-3 SH expansion (Sec. 4.2).  True: the No-SH
+    # ablation (Sec. 5), rgb = sigmoid(c) with c in the SH degree-0 rows.
+    rgb_color: bool = False
 
     def _c(self, lambda_raw=None, grad_lambda=None) -> _Set:
         """C settings; lambda_raw / grad_lambda are float64 arrays the caller keeps alive."""
@@ -96,7 +100,7 @@ class Settings:
                     self.dilation, self.alpha_max, self.alpha_min, self.t_min, self.amb_alpha_min,
                     self.amb_alpha_max, self.amb_t_min, self.amb_depth, self.amb_impact,
                     None if lambda_raw is None else _ptr(lambda_raw),
-                    None if grad_lambda is None else _ptr(grad_lambda))
+                    None if grad_lambda is None else _ptr(grad_lambda), int(bool(self.rgb_color)))
 
 
 _lib = None

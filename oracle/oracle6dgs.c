@@ -20,7 +20,9 @@
  *     camera centre to mu_p.
  *   - colour = sigmoid of a degree-3 real SH expansion with 48 coefficients
  *     (Sec. 4.2), evaluated at the unit vector from the camera centre to
- *     mu_cond; textbook real SH without the Condon-Shortley phase.
+ *     mu_cond; textbook real SH without the Condon-Shortley phase.  The
+ *     No-SH ablation of Sec. 5 (a learnable RGB per Gaussian) is the
+ *     color_rgb setting: rgb = sigmoid(c), c in the SH degree-0 rows.
  *   - after the slice the renderer is the 3D Gaussian splatting rasteriser
  *     (Sec. 4.4): EWA projection with the 1.3 Jacobian guard and 0.3 screen
  *     dilation, per-pixel front-to-back compositing with alpha clamped at 0.99,
@@ -99,6 +101,11 @@ typedef struct {
    * adds dL/dlambda_raw into grad_lambda (when that is not NULL either) */
   const double *lambda_raw;
   double *grad_lambda;
+  /* colour model: 0 = sigmoid of the degree-3 SH expansion (Sec. 4.2); 1 = the
+   * No-SH ablation of Sec. 5 (a learnable RGB per Gaussian, as in N-DG), read
+   * here as rgb = sigmoid(c) with c held in the three rows of the SH degree-0
+   * coefficients; the other 45 SH rows are unused and get zero gradient */
+  int64_t color_rgb;
 } orc_settings;
 
 static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
@@ -327,12 +334,16 @@ static void record_one(const double *params, int64_t n, int64_t i, const orc_cam
   for (int k = 0; k < 3; k++) { sdir[k] = mu_c[k] - C[k]; ns += sdir[k] * sdir[k]; }
   ns = sqrt(ns);
   for (int k = 0; k < 3; k++) { sdir[k] /= ns; rec[F_SHDIR + k] = sdir[k]; }
-  double Y[16];
-  sh_eval(sdir, Y, NULL);
-  for (int c = 0; c < 3; c++) {
-    double acc = 0;
-    for (int k = 0; k < 16; k++) acc += P(params, n, ROW_SH + 3 * k + c, i) * Y[k];
-    rec[F_RGB + c] = sigm(acc);
+  if (s->color_rgb) {
+    for (int c = 0; c < 3; c++) rec[F_RGB + c] = sigm(P(params, n, ROW_SH + c, i));
+  } else {
+    double Y[16];
+    sh_eval(sdir, Y, NULL);
+    for (int c = 0; c < 3; c++) {
+      double acc = 0;
+      for (int k = 0; k < 16; k++) acc += P(params, n, ROW_SH + 3 * k + c, i) * Y[k];
+      rec[F_RGB + c] = sigm(acc);
+    }
   }
   /* camera transform and projection */
   double p[3];
@@ -658,16 +669,24 @@ static void record_vjp(const double *params, int64_t n, int64_t i, const orc_cam
   for (int k = 0; k < 3; k++) { sv[k] = rec[F_MUC + k] - C[k]; ns += sv[k] * sv[k]; }
   ns = sqrt(ns);
   double sh[3] = {sv[0] / ns, sv[1] / ns, sv[2] / ns};
-  double Y[16], dY[16][3];
-  sh_eval(sh, Y, dY);
   double gs[3] = {0, 0, 0};
-  for (int c = 0; c < 3; c++) {
-    double rgb = rec[F_RGB + c];
-    double dsc = g2[G_R + c] * rgb * (1.0 - rgb);
-    for (int k = 0; k < 16; k++) {
-      grad[(int64_t)(ROW_SH + 3 * k + c) * n + i] += dsc * Y[k];
-      double beta = P(params, n, ROW_SH + 3 * k + c, i);
-      for (int m = 0; m < 3; m++) gs[m] += dsc * beta * dY[k][m];
+  if (s->color_rgb) {
+    /* rgb = sigmoid(c): no dependence on the viewing direction */
+    for (int c = 0; c < 3; c++) {
+      double rgb = rec[F_RGB + c];
+      grad[(int64_t)(ROW_SH + c) * n + i] += g2[G_R + c] * rgb * (1.0 - rgb);
+    }
+  } else {
+    double Y[16], dY[16][3];
+    sh_eval(sh, Y, dY);
+    for (int c = 0; c < 3; c++) {
+      double rgb = rec[F_RGB + c];
+      double dsc = g2[G_R + c] * rgb * (1.0 - rgb);
+      for (int k = 0; k < 16; k++) {
+        grad[(int64_t)(ROW_SH + 3 * k + c) * n + i] += dsc * Y[k];
+        double beta = P(params, n, ROW_SH + 3 * k + c, i);
+        for (int m = 0; m < 3; m++) gs[m] += dsc * beta * dY[k][m];
+      }
     }
   }
   double sdot = sh[0] * gs[0] + sh[1] * gs[1] + sh[2] * gs[2];

@@ -590,3 +590,69 @@ def test_densify_stats_by_hand():
     acc, cnt = oracle.densify_stats([g1, g2], [np.array([True, True]), np.array([True, False])], cams)
     assert np.allclose(acc, [math.hypot(0.3 * 50, 0.4 * 25) + 0.5 * 20, 50.0])
     assert np.allclose(cnt, [2, 1])
+
+
+# ------------------------------------------------- No-SH colour (Sec. 5 ablation)
+Y00 = 0.5 / math.sqrt(math.pi)  # the degree-0 real spherical harmonic, 1 / (2 sqrt(pi))
+
+
+def test_rgb_color_equals_dc_only_sh():
+    """The per-Gaussian RGB colour rgb = sigmoid(c) renders exactly like the SH
+    colour with only degree-0 coefficients beta0 = c / Y00 (the degree-0
+    harmonic is the constant 1 / (2 sqrt(pi))), which the quadrature and scipy
+    pins fix; the RGB path itself evaluates no harmonic at all."""
+    p, cam = tiny_scene(6, 61)
+    c = np.random.default_rng(8).normal(0.0, 1.0, (3, p.shape[1]))
+    p_rgb = p.copy()
+    p_rgb[27:30] = c
+    p_rgb[30:75] = np.random.default_rng(9).normal(0.0, 5.0, (45, p.shape[1]))  # unused in RGB mode
+    p_sh = p.copy()
+    p_sh[27:30] = c / Y00
+    p_sh[30:75] = 0.0
+    img_rgb, T_rgb, *_ = oracle.render(p_rgb, cam, oracle.Settings(rgb_color=True), nthreads=1)
+    img_sh, T_sh, *_ = oracle.render(p_sh, cam, oracle.Settings(), nthreads=1)
+    assert np.abs(img_rgb - img_sh).max() < 1e-12 and np.abs(T_rgb - T_sh).max() < 1e-13
+    assert img_rgb.max() > 0.05
+
+
+def test_rgb_color_gradient_is_chain_rule_of_dc_sh():
+    """Gradients in RGB mode: dL/dc = dL/dbeta0 / Y00 of the matching DC-only SH
+    scene, every other parameter's gradient as in that scene (the colour has no
+    view dependence in either), and exactly zero on the 45 unused SH rows."""
+    p, cam = tiny_scene(6, 67)
+    c = np.random.default_rng(10).normal(0.0, 1.0, (3, p.shape[1]))
+    p_rgb = p.copy()
+    p_rgb[27:30] = c
+    p_rgb[30:75] = np.random.default_rng(11).normal(0.0, 5.0, (45, p.shape[1]))
+    p_sh = p.copy()
+    p_sh[27:30] = c / Y00
+    p_sh[30:75] = 0.0
+    w = np.random.default_rng(12).normal(size=(3, cam.height, cam.width))
+    g_rgb, _ = oracle.backward(p_rgb, cam, w, oracle.Settings(rgb_color=True), nthreads=1)
+    g_sh, _ = oracle.backward(p_sh, cam, w, oracle.Settings(), nthreads=1)
+    scale = np.abs(g_sh).max()
+    assert np.all(g_rgb[30:75] == 0.0)
+    assert np.abs(g_rgb[27:30] - g_sh[27:30] / Y00).max() <= 1e-10 * scale
+    for r0, r1 in ((0, 27), (75, 76)):
+        assert np.abs(g_rgb[r0:r1] - g_sh[r0:r1]).max() <= 1e-10 * scale
+
+
+def test_rgb_color_gradient_matches_finite_differences():
+    """dL/dc in RGB mode against FP64 central differences of the render."""
+    n = 5
+    p, cam = tiny_scene(n, 71)
+    st = oracle.Settings(rgb_color=True, bg=(0.2, 0.1, 0.3))
+    w = np.random.default_rng(13).normal(size=(3, cam.height, cam.width))
+
+    def loss(pp):
+        img, *_ = oracle.render(pp, cam, st, nthreads=1)
+        return float((img * w).sum())
+
+    g, _ = oracle.backward(p, cam, w, st, nthreads=1)
+    for row in (27, 28, 29):
+        for i in range(n):
+            h = 1e-6
+            pp = p.copy(); pp[row, i] += h
+            pm = p.copy(); pm[row, i] -= h
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            assert abs(g[row, i] - fd) <= 1e-6 * max(abs(fd), 1e-3)
