@@ -90,6 +90,11 @@ typedef struct {
 } sixdgs_settings;
 
 #define SIXDGS_FLAG_COUNTS 1 /* forward also stores per-pixel contributor counts (debug export) */
+/* No-SH colour (the Sec. 5 ablation): each Gaussian's colour is sigmoid(c) of
+ * its own RGB triple c, held in the three SH degree-0 rows (27-29); the 45
+ * higher SH rows are ignored and receive zero gradient.  Without the flag the
+ * colour is the sigmoid of the degree-3 SH expansion (Sec. 4.2). */
+#define SIXDGS_FLAG_RGB_COLOR 2
 
 /* Fills `s` with the defaults: lambda 0.35, z_near 0.2, bg 0, 16x16 tiles,
  * batch 256, pair_capacity 0, flags 0, chunk 256. */
@@ -121,6 +126,30 @@ const char* sixdgs_last_error(const sixdgs_ctx* ctx);
  * sixdgs_bin on this context. */
 sixdgs_status sixdgs_forward(sixdgs_ctx* ctx, const float* params, int64_t n, const sixdgs_camera* cams,
                              int32_t ncam, float* const* images, void* stream);
+
+/* Inference cache (Algorithm 1's caption notes that the slice's
+ * direction-independent part can be computed once per Gaussian): writes, for
+ * each of the n Gaussians in params (device [76][n]), the rows of
+ * cache (device [SIXDGS_CACHE_ROWS][n], caller-owned, overwritten):
+ *   0-5   Sigma_cond = Sigma_p - Sigma_pd Sigma_d^-1 Sigma_pd^T (xx xy xz yy yz zz)
+ *   6-14  K = Sigma_pd Sigma_d^-1, row-major
+ *   15-20 Sigma_d^-1 (xx xy xz yy yz zz)
+ *   21    alpha = sigmoid(opacity logit)
+ * Asynchronous on `stream`; INVALID_ARG for n < 0 or NULL pointers with n > 0.
+ * The cache is a function of the Cholesky and opacity rows only: rebuild it
+ * after they change. */
+#define SIXDGS_CACHE_ROWS 22
+sixdgs_status sixdgs_build_cache(const float* params, int64_t n, float* cache, void* stream);
+
+/* Render-only forward from the inference cache: the images of sixdgs_forward
+ * (bit-identical for a cache built from the same params), with the per-view
+ * work reduced to the conditional mean, the directional opacity, the colour
+ * and the projection, and none of the state a backward needs kept (the next
+ * sixdgs_backward on this context returns STATE).  params supplies the mean
+ * and colour rows.  Takes the scalar lambda_opa: STATE while a per-Gaussian
+ * lambda array is attached. */
+sixdgs_status sixdgs_forward_cached(sixdgs_ctx* ctx, const float* params, const float* cache, int64_t n,
+                                    const sixdgs_camera* cams, int32_t ncam, float* const* images, void* stream);
 
 /* Backward of the last forward on this context: given dL/dI for each of its
  * cameras (host array of ncam device pointers, each [3][H][W]), writes dL/d

@@ -113,6 +113,7 @@ def lib():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         _lib.orc_preprocess.argtypes = [I64, P, P, P, P]
+        _lib.orc_static.argtypes = [I64, P, P]
         _lib.orc_render.argtypes = [I64, P, P, P, I64, P, P, P, P, P, ctypes.c_int]
         _lib.orc_backward.argtypes = [I64, P, P, P, I64, P, P, P, P, ctypes.c_int]
         _lib.orc_slice.argtypes = [I64, P, P, ctypes.c_double, P]
@@ -225,6 +226,17 @@ def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=Non
     if rc != 0:
         raise MemoryError("oracle backward failed")
     return (grad, g2d) if lam is None else (grad, g2d, glam)
+
+
+def static_part(params) -> np.ndarray:
+    """The slice's direction-independent part per Gaussian, [22, N]: Sigma_cond
+    (xx xy xz yy yz zz), K = Sigma_pd Sigma_d^-1 (row-major), Sigma_d^-1
+    (xx xy xz yy yz zz), alpha (Alg. 1 steps 1-3 up to the direction)."""
+    p = _params64(params)
+    n = p.shape[1]
+    out = np.zeros((n, 22), np.float64)
+    lib().orc_static(n, _ptr(p), _ptr(out))
+    return np.ascontiguousarray(out.T)
 
 
 def slice_gaussians(params, dirs, lambda_opa: float):

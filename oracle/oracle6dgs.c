@@ -307,6 +307,24 @@ void orc_slice(int64_t n, const double *params, const double *dirs, double lambd
   }
 }
 
+/* The direction-independent part of the slice per Gaussian (what an
+ * inference cache holds): out[22 i + k] = Sigma_cond (xx xy xz yy yz zz),
+ * K = Sigma_pd Sigma_d^-1 (row-major), Sigma_d^-1 (xx xy xz yy yz zz), alpha. */
+void orc_static(int64_t n, const double *params, double *out) {
+  for (int64_t i = 0; i < n; i++) {
+    g6 g;
+    load_g6(params, n, i, &g);
+    double *o = out + 22 * i;
+    o[0] = g.Sc[0][0]; o[1] = g.Sc[0][1]; o[2] = g.Sc[0][2];
+    o[3] = g.Sc[1][1]; o[4] = g.Sc[1][2]; o[5] = g.Sc[2][2];
+    for (int r = 0; r < 3; r++)
+      for (int c = 0; c < 3; c++) o[6 + 3 * r + c] = g.K[r][c];
+    o[15] = g.A[0][0]; o[16] = g.A[0][1]; o[17] = g.A[0][2];
+    o[18] = g.A[1][1]; o[19] = g.A[1][2]; o[20] = g.A[2][2];
+    o[21] = g.alpha;
+  }
+}
+
 static void cam_center(const orc_camera *c, double C[3]) {
   for (int k = 0; k < 3; k++) C[k] = -(c->R[0 + k] * c->t[0] + c->R[3 + k] * c->t[1] + c->R[6 + k] * c->t[2]);
 }

@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("SIXDGS_LIB", os.path.join(_HERE, "lib6dgs.so"))
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_STATE = range(6)
 MAX_VIEWS = 16
 FLAG_COUNTS = 1
+FLAG_RGB_COLOR = 2
+CACHE_ROWS = 22  # rows of the inference cache (SIXDGS_CACHE_ROWS)
 EXPORT_RECORDS, EXPORT_TILES, EXPORT_KEYS, EXPORT_VALUES, EXPORT_RANGES, EXPORT_T_FINAL, EXPORT_LAST, \
     EXPORT_COUNTS, EXPORT_SIZES = range(9)
 K_PREPROCESS, K_BLEND_FWD, K_BLEND_BWD, K_PREPROCESS_BWD, K_SORT = range(5)
@@ -69,6 +71,8 @@ def lib():
         L.sixdgs_last_error.argtypes = [P]
         L.sixdgs_last_error.restype = ctypes.c_char_p
         L.sixdgs_forward.argtypes = [P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
+        L.sixdgs_build_cache.argtypes = [P, I64, P, P]
+        L.sixdgs_forward_cached.argtypes = [P, P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
         L.sixdgs_backward.argtypes = [P, P, I64, PP, P, P, P]
         L.sixdgs_backward_adam.argtypes = [P, P, I64, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
@@ -86,6 +90,7 @@ def lib():
         L.sixdgs_set_timing.argtypes = [P, I32]
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
+                     "sixdgs_build_cache", "sixdgs_forward_cached",
                      "sixdgs_backward_adam", "sixdgs_l1_loss",
                      "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check",
                      "sixdgs_set_timing",
@@ -96,7 +101,8 @@ def lib():
 
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
-            "sixdgs_last_error", "sixdgs_forward", "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
+            "sixdgs_last_error", "sixdgs_forward", "sixdgs_build_cache", "sixdgs_forward_cached",
+            "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
             "sixdgs_l1_dssim_loss",
             "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_decompose",
             "sixdgs_densify_plan", "sixdgs_densify_apply", "sixdgs_bin",
@@ -224,6 +230,26 @@ class Context:
         ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
         self._rc(lib().sixdgs_forward(self._h, ctypes.c_void_p(params.data_ptr()), n, ccams, len(cams),
                                       _ptrs(images), ctypes.c_void_p(_stream(stream))))
+
+    def forward_cached(self, params, cache, cams, images, stream=None):
+        """Render-only forward from an inference cache (see build_cache)."""
+        n = params.shape[1]
+        _check_f32_cuda(params, "params")
+        _check_f32_cuda(cache, "cache")
+        if params.dim() != 2 or params.shape[0] != 76:
+            raise ValueError("params must have shape [76, N]")
+        if tuple(cache.shape) != (CACHE_ROWS, n):
+            raise ValueError(f"cache must have shape [{CACHE_ROWS}, N]")
+        if len(images) != len(cams):
+            raise ValueError("one image per camera")
+        for im, c in zip(images, cams):
+            _check_f32_cuda(im, "image")
+            if im.numel() != 3 * int(c.width) * int(c.height):
+                raise ValueError("each image must hold 3*H*W floats")
+        ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
+        self._rc(lib().sixdgs_forward_cached(self._h, ctypes.c_void_p(params.data_ptr()),
+                                             ctypes.c_void_p(cache.data_ptr()), n, ccams, len(cams), _ptrs(images),
+                                             ctypes.c_void_p(_stream(stream))))
 
     def backward(self, params, dl_dimages, grad, densify=None, stream=None):
         n = params.shape[1]
@@ -369,6 +395,23 @@ def adam_vec(p, grad, m, v, lr, step=1, step_counter=None, beta1=0.9, beta2=0.99
                                ctypes.c_void_p(_stream(stream)))
     if rc != OK:
         raise SixDGSError(rc, "adam_vec failed (bad arguments)")
+
+
+def build_cache(params, out=None, stream=None):
+    """Inference cache of params [76, N]: a [22, N] float32 CUDA tensor holding
+    Sigma_cond, K = Sigma_pd Sigma_d^-1, Sigma_d^-1 and alpha per Gaussian."""
+    import torch
+    _check_f32_cuda(params, "params")
+    n = params.shape[1]
+    cache = out if out is not None else torch.empty((CACHE_ROWS, n), device=params.device, dtype=torch.float32)
+    _check_f32_cuda(cache, "cache")
+    if tuple(cache.shape) != (CACHE_ROWS, n):
+        raise ValueError(f"cache must have shape [{CACHE_ROWS}, N]")
+    rc = lib().sixdgs_build_cache(ctypes.c_void_p(params.data_ptr()), n, ctypes.c_void_p(cache.data_ptr()),
+                                  ctypes.c_void_p(_stream(stream)))
+    if rc != OK:
+        raise SixDGSError(rc, "build_cache failed (bad arguments)")
+    return cache
 
 
 def adam_devstep(params, grad, m, v, lr, step_counter, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -78,7 +78,7 @@ struct sixdgs_ctx {
   // backward and loss
   DevBuf<float> g2d, l1_partial, ssim_maps, ssim_partial;
   // scratch
-  DevBuf<uint32_t> rstate, blk_start, counters;
+  DevBuf<uint32_t> rstate, blk_start, counters, tile_order;
   uint32_t* host_counters = nullptr;  // pinned
   // state of the last forward
   bool have_fwd = false;
@@ -127,6 +127,7 @@ bool valid_settings(const sixdgs_settings* s, std::string& why) {
     return false;
   }
   if (s->pair_capacity < 0 || s->pair_capacity > kMaxItems) { why = "pair_capacity out of range"; return false; }
+  if (s->flags & ~(SIXDGS_FLAG_COUNTS | SIXDGS_FLAG_RGB_COLOR)) { why = "unknown flag bits"; return false; }
   if (s->chunk < s->batch || s->chunk > 16384 || (s->chunk & (s->chunk - 1)) != 0) {
     why = "chunk must be a power of two between batch and 16384";
     return false;
@@ -196,6 +197,7 @@ DevSettings dev_settings(const sixdgs_settings& s) {
   d.lambda_opa = s.lambda_opa;
   d.z_near = s.z_near;
   for (int k = 0; k < 3; k++) d.bg[k] = s.bg[k];
+  d.rgb_color = (s.flags & SIXDGS_FLAG_RGB_COLOR) != 0;
   d.lambda_raw = nullptr;
   d.grad_lambda = nullptr;
   return d;
@@ -223,6 +225,7 @@ BlendState blend_state(sixdgs_ctx* c) {
   bs.bound = c->bound.p;
   bs.nbound = c->bound.cap / kBlock;
   bs.tile_nch = c->tile_nch.p;
+  bs.order = c->tile_order.p;
   bs.items = c->items.p;
   bs.items_cap = c->items.cap;
   bs.n_items = c->counters.p + 4;
@@ -255,6 +258,7 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.rstate_depth = c->rstate.p;
   b.rstate_pairs = c->rstate.p + sort_state_words(std::max<int64_t>(E, 1), false);
   b.blk_start = c->blk_start.p;
+  b.tile_order = c->tile_order.p;
   b.chunk_state = c->chunk_state.p;
   b.counters = c->counters.p;
 }
@@ -321,6 +325,7 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
     return fail(c, SIXDGS_ERR_OOM, "sort scratch");
   if (!c->ranges.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile ranges");
   if (!c->chunk_state.ensure(chunk_scan_words(c->vt.total_tiles))) return fail(c, SIXDGS_ERR_OOM, "tile scan");
+  if (!c->tile_order.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile order");
   fill_sort_buffers(c, E);
   Timer t(c, SIXDGS_K_SORT, st);
   launch_bin_count(c->sb, st);
@@ -420,6 +425,7 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   c->dens_off.release();
   c->dens_state.release();
   c->blk_start.release();
+  c->tile_order.release();
   c->counters.release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   delete c;
@@ -438,9 +444,15 @@ const char* sixdgs_last_error(const sixdgs_ctx* c) {
   return c->err.c_str();
 }
 
-sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, const sixdgs_camera* cams, int32_t ncam,
-                             float* const* images, void* stream) {
-  if (!c) return SIXDGS_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+// The forward; with a cache the slice's direction-independent part is read
+// from it, and inference = true renders the images only (no state for a
+// backward is kept).
+sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cache, int64_t n,
+                           const sixdgs_camera* cams, int32_t ncam, float* const* images, bool inference,
+                           void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (n < 0) return fail(c, SIXDGS_ERR_INVALID_ARG, "n must be >= 0");
   if (n > 0 && !params) return fail(c, SIXDGS_ERR_INVALID_ARG, "params is NULL");
@@ -466,7 +478,7 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
   c->fwd_lambda = c->lambda_raw;
   {
     Timer t(c, SIXDGS_K_PREPROCESS, st);
-    launch_preprocess(params, n, vt, ds, c->rec.p, c->tiles.p, c->depth.p, st);
+    launch_preprocess(params, cache, n, vt, ds, c->rec.p, c->tiles.p, c->depth.p, st);
   }
   sixdgs_status rc = check_launch(c, "preprocess");
   if (rc != SIXDGS_OK) return rc;
@@ -484,9 +496,11 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
   bs.counts = want_counts ? c->counts.p : nullptr;
   {
     Timer t(c, SIXDGS_K_BLEND_FWD, st);
-    launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->s.batch, st);
+    launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->s.batch, !inference, st);
   }
-  launch_chunk_items(c->tile_nch.p, vt.total_tiles, c->items.p, grid, c->chunk_state.p, c->counters.p + 4,
+  if (inference) return check_launch(c, "blend forward");
+  launch_chunk_items(c->tile_nch.p, c->tile_order.p, vt.total_tiles, c->items.p, grid, c->chunk_state.p,
+                     c->counters.p + 4,
                      c->counters.p + 3, st);
   rc = check_launch(c, "blend forward");
   if (rc != SIXDGS_OK) return rc;
@@ -498,6 +512,29 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
   c->fwd_px = total_px;
   c->stream = st;
   return SIXDGS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, const sixdgs_camera* cams, int32_t ncam,
+                             float* const* images, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return forward_impl(c, params, nullptr, n, cams, ncam, images, false, stream);
+}
+
+sixdgs_status sixdgs_build_cache(const float* params, int64_t n, float* cache, void* stream) {
+  if (n < 0 || (n > 0 && (!params || !cache))) return SIXDGS_ERR_INVALID_ARG;
+  launch_build_cache(params, n, cache, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
+}
+
+sixdgs_status sixdgs_forward_cached(sixdgs_ctx* c, const float* params, const float* cache, int64_t n,
+                                    const sixdgs_camera* cams, int32_t ncam, float* const* images, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (n > 0 && !cache) return fail(c, SIXDGS_ERR_INVALID_ARG, "cache is NULL");
+  if (c->lambda_raw) return fail(c, SIXDGS_ERR_STATE, "a cached forward takes the scalar lambda: detach the array");
+  return forward_impl(c, params, cache, n, cams, ncam, images, true, stream);
 }
 
 sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, const float* const* dl_dimages,

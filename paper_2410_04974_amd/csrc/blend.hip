@@ -196,13 +196,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int TW>
+// SAVE = false renders the image only (inference): no chunk boundaries, no
+// final transmittance, last contributor or chunk counts for a backward.
+template <int TW, bool SAVE>
 __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings ds, const Rec* __restrict__ rec,
                                                       const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ pval, BlendState bs) {
   __shared__ FwdWaveLDS W[kWaves];
   __shared__ uint32_t s_maxlast;
-  const int tile = blockIdx.x;
+  const int tile = (int)bs.order[blockIdx.x];
   const int vi = find_view(vt, tile);
   const ViewDesc& vd = vt.v[vi];
   const int local = tile - vd.tile_base;
@@ -217,8 +219,10 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
   FwdWaveLDS& B = W[wv];
   const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
 
-  if (threadIdx.x == 0) s_maxlast = 0;
-  __syncthreads();
+  if constexpr (SAVE) {
+    if (threadIdx.x == 0) s_maxlast = 0;
+    __syncthreads();
+  }
   const uint2 rg = ranges[tile];
   const uint32_t n = rg.y - rg.x;
   const uint32_t* pv = pval + rg.x;
@@ -259,12 +263,14 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
         C0 += Cc[u].x * wgt;
         C1 += Cc[u].y * wgt;
         C2 += Cc[u].z * wgt;
-        K0 += Cc[u].x * wgt;
-        K1 += Cc[u].y * wgt;
-        K2 += Cc[u].z * wgt;
         T = use ? Tn : T;
-        last = use ? __float_as_uint(Cc[u].w) : last;
-        cnt += use ? 1u : 0u;
+        if constexpr (SAVE) {
+          K0 += Cc[u].x * wgt;
+          K1 += Cc[u].y * wgt;
+          K2 += Cc[u].z * wgt;
+          last = use ? __float_as_uint(Cc[u].w) : last;
+          cnt += use ? 1u : 0u;
+        }
       }
     }
   };
@@ -282,7 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
     uint32_t e_nn = 0;
     if (s0 + kFwdStep + l < n) r_nxt = rec[e_nxt];
     if (s0 + 2 * kFwdStep + l < n) e_nn = pv[s0 + 2 * kFwdStep + l];
-    if (s0 != 0 && (s0 & (chunk - 1)) == 0) {
+    if (SAVE && s0 != 0 && (s0 & (chunk - 1)) == 0) {
       // a backward work item starts here: finish the chunk, then keep this
       // pixel's transmittance and the colour of the chunk that ends here
       composite(nh);
@@ -311,6 +317,16 @@ __global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings 
     e_nxt = e_nn;
   }
   composite(nh);
+  if constexpr (!SAVE) {
+    if (inside) {
+      const int64_t HW = (int64_t)vd.W * vd.H;
+      const int64_t pix = (int64_t)py * vd.W + px;
+      vd.img[pix] = C0 + T * ds.bg[0];
+      vd.img[HW + pix] = C1 + T * ds.bg[1];
+      vd.img[2 * HW + pix] = C2 + T * ds.bg[2];
+    }
+    return;
+  }
 
   // turn the per-chunk colours into the colour behind each boundary: sums of
   // positive terms from the back, so no cancellation against the total
@@ -478,58 +494,62 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
     // groups of four list slots, from the back
     const uint32_t lw = list4[l];
     const int ng = (int)((wn + 3) >> 2);
-    // one Gaussian of the reverse walk: updates T and D, fills the per-lane
-    // values to sum, and says (uniformly) whether any lane contributed
-    auto eval = [&](const Group4& G, int g, int u, float (&gv)[kG2D]) -> bool {
-      if ((uint32_t)(4 * g + u) >= wn) return false;
-      const uint32_t pos = pos0 + G.j[u];
-      if (pos >= wlast) return false;  // no pixel of this wavefront reached it
-      // predicated rather than branched: the lanes of a wavefront rarely agree
-      const float4 A = G.a[u];
-      const float4 B = make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f);
-      const float dx = fx - A.x, dy = fy - A.y;
-      const float p = log2_alpha(A, B, dx, dy);
-      const bool contrib = pos < last && p >= kLog2AlphaMin;
-      if (__ballot(contrib) == 0) return false;
-      const float araw = exp2_fast(p);
-      const float a = fminf(kAlphaMax, araw);
-      const float ro = rcp_fast(1.0f - a);
-      const float Tb = T * ro;  // transmittance in front of this Gaussian
-      const float wgt = contrib ? a * Tb : 0.f;
-      const float dc = dC0 * G.c[u].x + dC1 * G.c[u].y + dC2 * G.c[u].z;
-      const float dl_da = Tb * dc - ro * D;  // dL/dC . (c T_front - S_behind / (1 - alpha))
-      D += dc * wgt;
-      T = contrib ? Tb : T;
-      // d alpha / d(exponent) = alpha while alpha is below its clamp, zero above
-      const float dl_dp = (contrib && araw <= kAlphaMax) ? dl_da * araw : 0.f;
-      const float e0 = dl_dp * dx, e1 = dl_dp * dy;
-      // moments of dL/d(exponent) over the lanes; the mean and opacity gradients
-      // are formed from them once per Gaussian after the reduction
-      gv[0] = e0;
-      gv[1] = e1;
-      gv[2] = e0 * dx;
-      gv[3] = e0 * dy;
-      gv[4] = e1 * dy;
-      gv[5] = dl_dp;
-      gv[6] = dC0 * wgt;
-      gv[7] = dC1 * wgt;
-      gv[8] = dC2 * wgt;
-      return true;
-    };
-    // back to front in pairs, always reduced together (a Gaussian no lane took
-    // adds zeros): one straight-line reduction needs no register copies for
-    // the in-place lane swaps, which the three-way choice between a joint and
-    // two single reductions did
+    // A group of four list slots, back to front.  What does not depend on the
+    // walk's state -- offsets, exponent, take flag, alpha and 1 / (1 - alpha)
+    // -- is formed for all four first, branch-free, so the exponentials and
+    // reciprocals overlap; then the reverse steps run in pairs, each pair's
+    // 18 per-lane values summed in one straight-line reduction (a Gaussian no
+    // lane took adds zeros; a pair no lane took is skipped).  The one
+    // reduction for both needs no register copies for the in-place lane
+    // swaps, which a choice between a joint and two single reductions did.
     auto grad = [&](const Group4& G, int g) {
+      float dxs[4], dys[4], ars[4], as[4], ros[4];
+      bool cs[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t pos = pos0 + G.j[u];
+        // slots past the list and Gaussians no pixel of this wavefront reached are out
+        const bool in = (uint32_t)(4 * g + u) < wn && pos < wlast;
+        dxs[u] = fx - G.a[u].x;
+        dys[u] = fy - G.a[u].y;
+        const float p = log2_alpha(G.a[u], make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f), dxs[u], dys[u]);
+        cs[u] = in && pos < last && p >= kLog2AlphaMin;
+        ars[u] = exp2_fast(p);
+        as[u] = fminf(kAlphaMax, ars[u]);
+        ros[u] = rcp_fast(1.0f - as[u]);
+      }
+      // one reverse step: updates T and D and fills the per-lane values to sum
+      auto step = [&](int u, float (&gv)[kG2D]) {
+        const bool contrib = cs[u];
+        const float a = as[u], ro = ros[u], dx = dxs[u], dy = dys[u];
+        const float Tb = T * ro;  // transmittance in front of this Gaussian
+        const float wgt = contrib ? a * Tb : 0.f;
+        const float dc = dC0 * G.c[u].x + dC1 * G.c[u].y + dC2 * G.c[u].z;
+        const float dl_da = Tb * dc - ro * D;  // dL/dC . (c T_front - S_behind / (1 - alpha))
+        D += dc * wgt;
+        T = contrib ? Tb : T;
+        // d alpha / d(exponent) = alpha while alpha is below its clamp, zero above
+        const float dl_dp = (contrib && ars[u] <= kAlphaMax) ? dl_da * ars[u] : 0.f;
+        const float e0 = dl_dp * dx, e1 = dl_dp * dy;
+        // moments of dL/d(exponent) over the lanes; the mean and opacity gradients
+        // are formed from them once per Gaussian after the reduction
+        gv[0] = e0;
+        gv[1] = e1;
+        gv[2] = e0 * dx;
+        gv[3] = e0 * dy;
+        gv[4] = e1 * dy;
+        gv[5] = dl_dp;
+        gv[6] = dC0 * wgt;
+        gv[7] = dC1 * wgt;
+        gv[8] = dC2 * wgt;
+      };
 #pragma unroll
       for (int h = 1; h >= 0; h--) {
+        if (__ballot(cs[2 * h + 1] || cs[2 * h]) == 0) continue;
         float ga[kG2D], gb[kG2D];
-#pragma unroll
-        for (int k = 0; k < kG2D; k++) ga[k] = gb[k] = 0.f;
-        const bool aa = eval(G, g, 2 * h + 1, ga);
-        const bool ab = eval(G, g, 2 * h, gb);
-        if (aa || ab)
-          wave_sum18_to_lds(ga, gb, s_g, (int)G.j[2 * h + 1], (int)G.j[2 * h], l);
+        step(2 * h + 1, ga);
+        step(2 * h, gb);
+        wave_sum18_to_lds(ga, gb, s_g, (int)G.j[2 * h + 1], (int)G.j[2 * h], l);
       }
     };
     for (int g = ng - 1; g >= 0; g--) {
@@ -575,15 +595,28 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
 
 }  // namespace
 
-void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
-                      const uint32_t* pval, BlendState bs, int batch, hipStream_t st) {
-  if (vt.total_tiles <= 0) return;
+template <bool SAVE>
+void launch_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
+                const uint32_t* pval, const BlendState& bs, hipStream_t st) {
   const dim3 grid(vt.total_tiles);
   switch (vt.tile_w) {
-    case 8: hipLaunchKernelGGL(k_blend_fwd<8>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
-    case 32: hipLaunchKernelGGL(k_blend_fwd<32>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
-    default: hipLaunchKernelGGL(k_blend_fwd<16>, grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
+    case 8: hipLaunchKernelGGL((k_blend_fwd<8, SAVE>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
+    case 32:
+      hipLaunchKernelGGL((k_blend_fwd<32, SAVE>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_blend_fwd<16, SAVE>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
+      break;
   }
+}
+
+void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
+                      const uint32_t* pval, BlendState bs, int batch, bool save, hipStream_t st) {
+  if (vt.total_tiles <= 0) return;
+  if (save)
+    launch_fwd<true>(vt, s, rec, ranges, pval, bs, st);
+  else
+    launch_fwd<false>(vt, s, rec, ranges, pval, bs, st);
 }
 
 void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,

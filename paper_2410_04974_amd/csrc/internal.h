@@ -11,6 +11,10 @@
 namespace sixdgs {
 
 constexpr int kRows = 76;
+// Inference cache rows per Gaussian (the direction-independent part of the
+// slice): Sigma_cond (00 01 02 11 12 22), K = Sigma_pd Sigma_d^-1 (row-major),
+// Sigma_d^-1 (00 01 02 11 12 22), alpha.
+constexpr int kCacheRows = 22;
 constexpr int kRowMuP = 0;
 constexpr int kRowMuD = 3;
 constexpr int kRowL = 6;
@@ -49,6 +53,7 @@ struct DevSettings {
   float lambda_opa;
   float z_near;
   float bg[3];
+  int32_t rgb_color;        // colour = sigmoid of the SH degree-0 rows (no SH), else the SH expansion
   const float* lambda_raw;  // [n] learnable per-Gaussian lambda = sigmoid(raw), or nullptr: lambda_opa
   float* grad_lambda;       // [n] backward output dL/dlambda_raw, or nullptr
 };
@@ -107,8 +112,11 @@ __device__ __forceinline__ void adam_update(float& p, float g, float& m, float& 
 
 // ----------------------------------------------------------- host launchers
 // preprocess.hip
-void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
-                       uint32_t* tiles, float* depth, hipStream_t st);
+// cache: nullptr, or the inference cache of params (then the slice's
+// direction-independent part is read instead of computed)
+void launch_preprocess(const float* params, const float* cache, int64_t n, const ViewTable& vt,
+                       const DevSettings& s, Rec* rec, uint32_t* tiles, float* depth, hipStream_t st);
+void launch_build_cache(const float* params, int64_t n, float* cache, hipStream_t st);
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st);
 // The same chain rule with an Adam step applied to params/m/v in place of writing the gradient.
@@ -137,6 +145,7 @@ struct SortBuffers {
   uint32_t* rstate_depth;  // [sort_state_words(E, false)] state of the scans and the depth sort
   uint32_t* rstate_pairs;  // [sort_state_words(pcap, true)] radix state of the tile sort
   uint32_t* blk_start;     // [sort_block_starts(pcap)] first sorted entry of each emission block
+  uint32_t* tile_order;    // [total_tiles] tiles, longest lists first (the compositing order)
   uint32_t* chunk_state;   // [chunk_scan_words(total_tiles)] state of the backward work-item scan
   uint32_t* counters;      // [0] binned entries, [1] pairs, [2] overflow flag, [3] sort look-back timeout
   // where the sorted results ended up (index into the ping-pong pairs)
@@ -173,20 +182,22 @@ struct BlendState {
                        // excluded); slot = absolute pair position / chunk (unique per boundary)
   int64_t nbound;
   uint32_t* tile_nch;  // [total_tiles] backward work items per tile
+  const uint32_t* order;  // [total_tiles] forward workgroup -> tile (longest lists first)
   uint2* items;        // [items_cap] (tile, chunk) backward work items
   int64_t items_cap;
   uint32_t* n_items;   // device count of items
 };
+// save = false: the image only, none of the state a backward needs
 void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
-                      const uint32_t* pval, BlendState bs, int batch, hipStream_t st);
+                      const uint32_t* pval, BlendState bs, int batch, bool save, hipStream_t st);
 // `grid` bounds the number of backward work items (pairs / chunk + tiles).
 void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
                       const uint32_t* pval, BlendState bs, float* g2d, int batch, int64_t grid, hipStream_t st);
 // sort.hip: the backward work items (tile, chunk) of every tile, from the
 // forward's per-tile chunk counts.  `state` holds chunk_scan_words(tiles)
 // words zeroed by the stage's preparation.
-void launch_chunk_items(const uint32_t* tile_nch, int64_t total_tiles, uint2* items, int64_t items_cap,
-                        uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st);
+void launch_chunk_items(const uint32_t* tile_nch, const uint32_t* order, int64_t total_tiles, uint2* items,
+                        int64_t items_cap, uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st);
 int64_t chunk_scan_words(int64_t total_tiles);
 // sort.hip: exclusive scan of n counts into off, the sum into *total (device);
 // `state` holds chunk_scan_words(n) words (zeroed here).

@@ -144,13 +144,25 @@ __device__ __forceinline__ bool view_state(const Static& s, const ViewDesc& vd, 
   return true;
 }
 
-__global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__ params, int64_t n, ViewTable vt,
+template <bool CACHED>
+__global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__ params,
+                                                       const float* __restrict__ cache, int64_t n, ViewTable vt,
                                                        DevSettings ds, Rec* __restrict__ rec,
                                                        uint32_t* __restrict__ tiles, float* __restrict__ depth) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= n) return;
   Static s;
-  load_static(params, n, g, s);
+  if constexpr (CACHED)
+    load_cached(params, cache, n, g, s);
+  else
+    load_static(params, n, g, s);
+  // the colour coefficients, issued with the rest of the parameter loads so
+  // their latency overlaps the slice (the RGB colour uses the first three)
+  float beta[16][3];
+#pragma unroll
+  for (int k = 0; k < 16; k++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) beta[k][c] = params[(kRowSH + 3 * k + c) * n + g];
   const float lam = gaussian_lambda(ds, g);
   for (int vi = 0; vi < vt.nview; vi++) {
     const ViewDesc& vd = vt.v[vi];
@@ -167,15 +179,21 @@ __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__
       tile_rect(u, v, ex, ey, vt.tile_shift_x, vt.tile_shift_y, vd.ntx, vd.nty, x0, y0, x1, y1);
       count = (uint32_t)((x1 - x0) * (y1 - y0));
       if (count > 0) {
-        float Y[16];
-        sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
         float col[3];
+        if (ds.rgb_color) {
+          // No-SH colour: sigmoid of the per-Gaussian RGB held in the degree-0 rows
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-          float acc = 0.f;
+          for (int c = 0; c < 3; c++) col[c] = sigmoidf(beta[0][c]);
+        } else {
+          float Y[16];
+          sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
 #pragma unroll
-          for (int k = 0; k < 16; k++) acc += params[(kRowSH + 3 * k + c) * n + g] * Y[k];
-          col[c] = sigmoidf(acc);
+          for (int c = 0; c < 3; c++) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
+            col[c] = sigmoidf(acc);
+          }
         }
         Rec r;
         r.a = make_float4(u, v, w.Q[0], w.Q[1]);
@@ -187,6 +205,22 @@ __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__
     }
     tiles[e] = count;
   }
+}
+
+// The inference cache: the direction-independent part of the slice (Alg. 1
+// caption), computed once so that render-only calls skip it.
+__global__ void __launch_bounds__(kBlock) k_build_cache(const float* __restrict__ params, int64_t n,
+                                                        float* __restrict__ cache) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= n) return;
+  Static s;
+  load_static(params, n, g, s);
+  const float v[kCacheRows] = {s.Sc[0][0], s.Sc[0][1], s.Sc[0][2], s.Sc[1][1], s.Sc[1][2], s.Sc[2][2],
+                               s.K[0][0],  s.K[0][1],  s.K[0][2],  s.K[1][0],  s.K[1][1],  s.K[1][2],
+                               s.K[2][0],  s.K[2][1],  s.K[2][2],  s.A[0][0],  s.A[0][1],  s.A[0][2],
+                               s.A[1][1],  s.A[1][2],  s.A[2][2],  s.alpha};
+#pragma unroll
+  for (int k = 0; k < kCacheRows; k++) cache[k * n + g] = v[k];
 }
 
 // ------------------------------------------------------------------ backward
@@ -310,30 +344,39 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     float gmu[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) gmu[k] = vd.R[k] * dp0 + vd.R[3 + k] * dp1 + vd.R[6 + k] * dp2;
-    // SH colour (Sec. 4.2): rgb = sigmoid(sum beta Y(s)), s = (mu_c - C)/|mu_c - C|
-    float Y[16];
-    sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
-    float wsum[16];
+    if (ds.rgb_color) {
+      // No-SH colour: rgb = sigmoid(c), no dependence on the viewing direction
 #pragma unroll
-    for (int k = 0; k < 16; k++) wsum[k] = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      float acc = 0.f;
-#pragma unroll
-      for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
-      const float col = sigmoidf(acc);
-      const float dsc = gp[6 + c] * col * (1.f - col);
-#pragma unroll
-      for (int k = 0; k < 16; k++) {
-        g_beta[k][c] += dsc * Y[k];
-        wsum[k] += dsc * beta[k][c];
+      for (int c = 0; c < 3; c++) {
+        const float col = sigmoidf(beta[0][c]);
+        g_beta[0][c] += gp[6 + c] * col * (1.f - col);
       }
-    }
-    float gs[3];
-    sh_basis_vjp(w.sdir[0], w.sdir[1], w.sdir[2], wsum, gs);
-    const float sdot = w.sdir[0] * gs[0] + w.sdir[1] * gs[1] + w.sdir[2] * gs[2];
+    } else {
+      // SH colour (Sec. 4.2): rgb = sigmoid(sum beta Y(s)), s = (mu_c - C)/|mu_c - C|
+      float Y[16];
+      sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
+      float wsum[16];
 #pragma unroll
-    for (int k = 0; k < 3; k++) gmu[k] += (gs[k] - w.sdir[k] * sdot) / w.ns;
+      for (int k = 0; k < 16; k++) wsum[k] = 0.f;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
+        const float col = sigmoidf(acc);
+        const float dsc = gp[6 + c] * col * (1.f - col);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+          g_beta[k][c] += dsc * Y[k];
+          wsum[k] += dsc * beta[k][c];
+        }
+      }
+      float gs[3];
+      sh_basis_vjp(w.sdir[0], w.sdir[1], w.sdir[2], wsum, gs);
+      const float sdot = w.sdir[0] * gs[0] + w.sdir[1] * gs[1] + w.sdir[2] * gs[2];
+#pragma unroll
+      for (int k = 0; k < 3; k++) gmu[k] += (gs[k] - w.sdir[k] * sdot) / w.ns;
+    }
     // slice (Sec. 3.2): mu_c = mu_p + K x, D = x^T A x, alpha_c = alpha exp(-lambda D)
     const float dD = -lam * w.ac * gac;
     g_lam -= w.D * w.ac * gac;  // d alpha_c / d lambda = -D alpha_c
@@ -489,11 +532,22 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
 
 }  // namespace
 
-void launch_preprocess(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s, Rec* rec,
-                       uint32_t* tiles, float* depth, hipStream_t st) {
+void launch_preprocess(const float* params, const float* cache, int64_t n, const ViewTable& vt,
+                       const DevSettings& s, Rec* rec, uint32_t* tiles, float* depth, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, rec, tiles, depth);
+  if (cache)
+    hipLaunchKernelGGL(k_preprocess<true>, dim3(grid), dim3(kBlock), 0, st, params, cache, n, vt, s, rec, tiles,
+                       depth);
+  else
+    hipLaunchKernelGGL(k_preprocess<false>, dim3(grid), dim3(kBlock), 0, st, params, cache, n, vt, s, rec, tiles,
+                       depth);
+}
+
+void launch_build_cache(const float* params, int64_t n, float* cache, hipStream_t st) {
+  if (n <= 0) return;
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_build_cache, dim3(grid), dim3(kBlock), 0, st, params, n, cache);
 }
 
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,

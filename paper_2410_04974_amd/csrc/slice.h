@@ -82,4 +82,30 @@ __device__ __forceinline__ void load_static(const float* __restrict__ params, in
   s.Sc[2][1] = s.Sc[1][2];
 }
 
+// The same from the inference cache (see kCacheRows): only what the forward
+// slice uses (mu_p, mu_d, K, Sigma_d^-1, Sigma_cond, alpha).
+__device__ __forceinline__ void load_cached(const float* __restrict__ params, const float* __restrict__ cache,
+                                            int64_t n, int64_t g, Static& s) {
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    s.mu_p[k] = params[(kRowMuP + k) * n + g];
+    s.mu_d[k] = params[(kRowMuD + k) * n + g];
+  }
+  const float c00 = cache[0 * n + g], c01 = cache[1 * n + g], c02 = cache[2 * n + g];
+  const float c11 = cache[3 * n + g], c12 = cache[4 * n + g], c22 = cache[5 * n + g];
+  s.Sc[0][0] = c00; s.Sc[0][1] = c01; s.Sc[0][2] = c02;
+  s.Sc[1][0] = c01; s.Sc[1][1] = c11; s.Sc[1][2] = c12;
+  s.Sc[2][0] = c02; s.Sc[2][1] = c12; s.Sc[2][2] = c22;
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) s.K[a][b] = cache[(6 + 3 * a + b) * n + g];
+  const float a00 = cache[15 * n + g], a01 = cache[16 * n + g], a02 = cache[17 * n + g];
+  const float a11 = cache[18 * n + g], a12 = cache[19 * n + g], a22 = cache[20 * n + g];
+  s.A[0][0] = a00; s.A[0][1] = a01; s.A[0][2] = a02;
+  s.A[1][0] = a01; s.A[1][1] = a11; s.A[1][2] = a12;
+  s.A[2][0] = a02; s.A[2][1] = a12; s.A[2][2] = a22;
+  s.alpha = cache[21 * n + g];
+}
+
 }  // namespace sixdgs

@@ -299,14 +299,28 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
   if (t == 0) s_blk = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kWaves; w++) s_wc[w][t] = 0;
-  __syncthreads();
-  const int64_t blk = s_blk;
   const uint32_t count = load_count(count_ptr, cap, cap);
-  const int64_t base = blk * kChunkI;
-  if (base >= count) return;  // uniform; no later workgroup has items, so none waits on this one
   const uint32_t mask = (1u << dbits) - 1u;
   const bool own = (uint32_t)t <= mask;
-  const uint32_t gh = own ? ghist[t] : 0u;  // issued early: used after the look-back
+  const uint32_t gh = own ? ghist[t] : 0u;
+  // every key has the same digit in this pass (e.g. the exponent byte of
+  // depths within one octave): the stable order is the input order, so the
+  // pass is a copy
+  const bool one = __syncthreads_or(own && count > 0 && gh == count);
+  const int64_t blk = s_blk;
+  const int64_t base = blk * kChunkI;
+  if (base >= count) return;  // uniform; no later workgroup has items, so none waits on this one
+  if (one) {
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+      const int64_t i = base + (int64_t)r * kBlock + t;
+      if (i < count) {
+        kout[i] = kin[i];
+        vout[i] = vin[i];
+      }
+    }
+    return;
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t wbase = base + (int64_t)wv * kWaveItems;  // each wavefront ranks consecutive items
   uint32_t key[ITEMS], val[ITEMS], loc[ITEMS];
@@ -526,6 +540,41 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const uint32_t* __restrict__ 
   }
 }
 
+// Order in which the compositing kernels take the tiles: longest lists first
+// (buckets of log2 of the pair count, heaviest bucket first), so the tiles
+// whose per-pixel walks are longest start before the light ones and the
+// kernels' tails shrink.  One workgroup of 1024 threads: a bucket histogram,
+// its scan and a scatter; the order inside a bucket is arbitrary.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 33;
+__global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __restrict__ ranges, uint32_t total_tiles,
+                                                              uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_h[kOrderBuckets];
+  const int t = threadIdx.x;
+  if (t < kOrderBuckets) s_h[t] = 0;
+  __syncthreads();
+  auto bucket = [&](uint32_t k) {
+    const uint2 r = ranges[k];
+    const uint32_t c = r.y - r.x;
+    return c ? 32 - __clz(c) : 0;  // 0 for an empty tile, else 1 + floor(log2 c)
+  };
+  for (uint32_t k = t; k < total_tiles; k += kOrderThreads) atomicAdd(&s_h[kOrderBuckets - 1 - bucket(k)], 1u);
+  __syncthreads();
+  if (t == 0) {
+    uint32_t acc = 0;
+    for (int b = 0; b < kOrderBuckets; b++) {
+      const uint32_t c = s_h[b];
+      s_h[b] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = t; k < total_tiles; k += kOrderThreads) {
+    const uint32_t pos = atomicAdd(&s_h[kOrderBuckets - 1 - bucket(k)], 1u);
+    if (pos < total_tiles) order[pos] = k;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_zero_g2d(const uint32_t* __restrict__ dval, const uint32_t* counters,
                                                      float* __restrict__ g2d) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -604,19 +653,27 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
   if (gp)
     hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
                        (uint32_t)vt.total_tiles, b.ranges);
+  if (vt.total_tiles > 0)
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges,
+                       (uint32_t)vt.total_tiles, b.tile_order);
 }
 
 namespace {
+// Work items in the tiles' compositing order: the chunks of the heaviest
+// tiles come first.
 struct TileChunks {
   const uint32_t* nch;
-  __device__ uint32_t operator()(int64_t i) const { return nch[i]; }
+  const uint32_t* order;
+  __device__ uint32_t operator()(int64_t i) const { return nch[order[i]]; }
 };
 struct ExpandItems {
   uint2* items;
+  const uint32_t* order;
   uint32_t cap;
   __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const {
+    const uint32_t tile = order[i];
     for (uint32_t k = 0; k < v; k++)
-      if (pre + k < cap) items[pre + k] = make_uint2((uint32_t)i, k);
+      if (pre + k < cap) items[pre + k] = make_uint2(tile, k);
   }
 };
 }  // namespace
@@ -647,11 +704,11 @@ void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* 
                (uint32_t*)nullptr, err, st);
 }
 
-void launch_chunk_items(const uint32_t* tile_nch, int64_t total_tiles, uint2* items, int64_t items_cap,
-                        uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st) {
+void launch_chunk_items(const uint32_t* tile_nch, const uint32_t* order, int64_t total_tiles, uint2* items,
+                        int64_t items_cap, uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st) {
   const uint32_t T = (uint32_t)total_tiles;
-  scan1<false>(TileChunks{tile_nch}, ExpandItems{items, (uint32_t)items_cap}, nullptr, T, T, total_tiles, state,
-               reinterpret_cast<uint64_t*>(state + 2), n_items, (uint32_t*)nullptr, err, st);
+  scan1<false>(TileChunks{tile_nch, order}, ExpandItems{items, order, (uint32_t)items_cap}, nullptr, T, T,
+               total_tiles, state, reinterpret_cast<uint64_t*>(state + 2), n_items, (uint32_t*)nullptr, err, st);
 }
 
 int64_t sort_state_words(int64_t bound, bool pairs) {

@@ -20,7 +20,11 @@ class Renderer:
     of the last forward)."""
 
     def __init__(self, lambda_opa=0.35, z_near=0.2, bg=(0.0, 0.0, 0.0), tile=(16, 16), batch=256,
-                 pair_capacity=0, flags=0, chunk=256):
+                 pair_capacity=0, flags=0, chunk=256, rgb_color=False):
+        """rgb_color=True selects the No-SH colour: sigmoid of a per-Gaussian RGB
+        held in the SH degree-0 rows (the other SH rows are ignored)."""
+        if rgb_color:
+            flags |= _lib.FLAG_RGB_COLOR
         self.ctx = _lib.Context(lambda_opa=lambda_opa, z_near=z_near, bg=bg, tile_w=tile[0], tile_h=tile[1],
                                 batch=batch, pair_capacity=pair_capacity, flags=flags, chunk=chunk)
 
@@ -33,6 +37,14 @@ class Renderer:
         imgs = out if out is not None else [
             torch.empty((3, c.height, c.width), device=params.device, dtype=torch.float32) for c in cams]
         self.ctx.forward(params, cams, imgs)
+        return imgs
+
+    def forward_cached(self, params, cache, cams, out=None):
+        """Render-only forward from an inference cache (``_lib.build_cache``);
+        no backward may follow it."""
+        imgs = out if out is not None else [
+            torch.empty((3, c.height, c.width), device=params.device, dtype=torch.float32) for c in cams]
+        self.ctx.forward_cached(params, cache, cams, imgs)
         return imgs
 
     def backward(self, params, dl_dimages, grad=None, densify=None):

@@ -97,11 +97,17 @@ def _random_records(n, cams, seed, ext=10.0):
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32)])
-@pytest.mark.parametrize("case", ["one_view", "three_views", "empty"])
+@pytest.mark.parametrize("case", ["one_view", "three_views", "empty", "one_octave", "one_tile"])
 def test_binning_bit_exact(tile, case):
-    if case == "one_view":
+    """one_octave: every depth in [2, 4), so the depth keys' top byte is the
+    same for all (that radix pass keeps the order and copies); one_tile: an
+    image of one tile, every pair with the same key."""
+    if case in ("one_view", "one_octave"):
         cams = [synth.default_camera(203, 157)]
         n = 5000
+    elif case == "one_tile":
+        cams = [synth.default_camera(tile[0], tile[1])]
+        n = 3000
     elif case == "three_views":
         cams = [synth.default_camera(64, 64), synth.default_camera(400, 130), synth.default_camera(33, 517)]
         n = 3000
@@ -111,6 +117,9 @@ def test_binning_bit_exact(tile, case):
     u, v, ex, ey, depth, alive = _random_records(n, cams, seed=11)
     if case == "empty":
         alive[:] = 0
+    if case == "one_octave":
+        depth = (2.0 + (depth - 0.5) / 7.5 * 1.999).astype(np.float32)
+        depth[::7] = np.float32(3.0)  # equal depths still fall back to entry order
     r = G.renderer(tile=tile)
     dev = [torch.from_numpy(a).to(G.DEV) for a in (u, v, ex, ey, depth, alive)]
     r.ctx.bin(n, cams, *dev)

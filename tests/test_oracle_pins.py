@@ -656,3 +656,30 @@ def test_rgb_color_gradient_matches_finite_differences():
             pm = p.copy(); pm[row, i] -= h
             fd = (loss(pp) - loss(pm)) / (2 * h)
             assert abs(g[row, i] - fd) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+# --------------------------------------------- the slice's direction-independent part
+def test_static_part_reproduces_the_slice():
+    """The cached quantities rebuild the slice: mu_cond = mu_p + K (d - mu_d),
+    D = (d - mu_d)^T Sigma_d^-1 (d - mu_d), alpha_cond = alpha exp(-lambda D)
+    and Sigma_cond equal the oracle's slice (pinned above against the precision
+    form and the Woodbury identity) for arbitrary unit directions."""
+    n = 200
+    p = synth.make_scene(synth.workload("c2", n).scene)
+    st = oracle.static_part(p)
+    rng = np.random.default_rng(17)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    mu_c, sig, D, f, ac = oracle.slice_gaussians(p, d, 0.35)
+    K = st[6:15].T.reshape(n, 3, 3)
+    a = st[15:21].T
+    A = np.stack([a[:, [0, 1, 2]], a[:, [1, 3, 4]], a[:, [2, 4, 5]]], axis=1)
+    sc = st[0:6].T
+    Sc = np.stack([sc[:, [0, 1, 2]], sc[:, [1, 3, 4]], sc[:, [2, 4, 5]]], axis=1)
+    x = d - p[3:6].T
+    assert np.abs(p[0:3].T + np.einsum("nij,nj->ni", K, x) - mu_c).max() < 1e-12
+    Dc = np.einsum("ni,nij,nj->n", x, A, x)
+    assert np.abs(Dc - D).max() <= 1e-12 * max(1.0, np.abs(D).max())
+    assert np.abs(st[21] * np.exp(-0.35 * Dc) - ac).max() < 1e-12
+    assert np.abs(Sc - sig).max() <= 1e-12 * np.abs(sig).max()
+    assert np.all(np.linalg.eigvalsh(A) > 0)  # an inverse covariance
