@@ -189,7 +189,7 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic(name),
                 "avg_ms": round(avg_ms, 4), "contributions_per_launch": counts, "flops_per_contribution": per}
     if dom == _lib.K_PREPROCESS:
-        bytes_ = 304 * n + 4 * n + 48 * nb
+        bytes_ = 304 * n + 4 * n + 52 * nb
     elif dom == _lib.K_PREPROCESS_BWD:
         bytes_ = 608 * n + 4 * n + 36 * nb
     else:  # integer stage: depth keys and pair lists (sort passes read and write 8 B per item)
