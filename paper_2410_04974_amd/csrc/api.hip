@@ -82,6 +82,8 @@ struct sixdgs_ctx {
   uint32_t* host_counters = nullptr;  // pinned
   // state of the last forward
   bool have_fwd = false;
+  float* bin_g2d = nullptr;  // the gradient accumulators the binning clears (training forwards)
+  bool g2d_clean = false;    // g2d is zero for the binned entries of the last forward
   bool counts_valid = false;
   const float* fwd_params = nullptr;
   int64_t fwd_n = 0;
@@ -259,6 +261,7 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.rstate_pairs = c->rstate.p + sort_state_words(std::max<int64_t>(E, 1), false);
   b.blk_start = c->blk_start.p;
   b.tile_order = c->tile_order.p;
+  b.g2d = c->bin_g2d;
   b.chunk_state = c->chunk_state.p;
   b.counters = c->counters.p;
 }
@@ -482,8 +485,13 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
   }
   sixdgs_status rc = check_launch(c, "preprocess");
   if (rc != SIXDGS_OK) return rc;
+  c->g2d_clean = false;
+  if (!inference && !c->g2d.ensure(E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
+  c->bin_g2d = inference ? nullptr : c->g2d.p;  // cleared by the binning for the backward
   rc = run_binning(c, E, st);
+  c->bin_g2d = nullptr;
   if (rc != SIXDGS_OK) return rc;
+  c->g2d_clean = !inference;
   // the backward's work items: at most one per `chunk` pairs plus one per tile
   const int64_t nbound = c->sb.pcap / c->s.chunk + 1;
   const int64_t grid = nbound + vt.total_tiles;
@@ -556,7 +564,8 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, con
   DevSettings ds = dev_settings(c->s);
   ds.lambda_raw = c->fwd_lambda;
   ds.grad_lambda = c->fwd_lambda ? c->grad_lambda : nullptr;
-  launch_zero_g2d(c->sb, c->g2d.p, st);
+  if (!c->g2d_clean) launch_zero_g2d(c->sb, c->g2d.p, st);  // a second backward of one forward
+  c->g2d_clean = false;
   const BlendState bs = blend_state(c);
   {
     Timer t(c, SIXDGS_K_BLEND_BWD, st);
@@ -594,7 +603,8 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, cons
   DevSettings ds = dev_settings(c->s);
   ds.lambda_raw = c->fwd_lambda;
   ds.grad_lambda = c->fwd_lambda ? c->grad_lambda : nullptr;
-  launch_zero_g2d(c->sb, c->g2d.p, st);
+  if (!c->g2d_clean) launch_zero_g2d(c->sb, c->g2d.p, st);  // a second backward of one forward
+  c->g2d_clean = false;
   const BlendState bs = blend_state(c);
   {
     Timer t(c, SIXDGS_K_BLEND_BWD, st);

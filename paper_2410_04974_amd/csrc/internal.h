@@ -146,6 +146,7 @@ struct SortBuffers {
   uint32_t* rstate_pairs;  // [sort_state_words(pcap, true)] radix state of the tile sort
   uint32_t* blk_start;     // [sort_block_starts(pcap)] first sorted entry of each emission block
   uint32_t* tile_order;    // [total_tiles] tiles, longest lists first (the compositing order)
+  float* g2d;              // [E][kG2D] screen-space gradient accumulators to clear, or nullptr
   uint32_t* chunk_state;   // [chunk_scan_words(total_tiles)] state of the backward work-item scan
   uint32_t* counters;      // [0] binned entries, [1] pairs, [2] overflow flag, [3] sort look-back timeout
   // where the sorted results ended up (index into the ping-pong pairs)

@@ -545,12 +545,26 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const uint32_t* __restrict__ 
 // whose per-pixel walks are longest start before the light ones and the
 // kernels' tails shrink.  One workgroup of 1024 threads: a bucket histogram,
 // its scan and a scatter; the order inside a bucket is arbitrary.
+// Workgroups past the first zero the screen-space gradient accumulators of
+// the binned entries (when g2d is given) for the backward that may follow.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 33;
 __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __restrict__ ranges, uint32_t total_tiles,
-                                                              uint32_t* __restrict__ order) {
+                                                              uint32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ dval,
+                                                              const uint32_t* __restrict__ counters,
+                                                              float* __restrict__ g2d) {
   __shared__ uint32_t s_h[kOrderBuckets];
   const int t = threadIdx.x;
+  if (blockIdx.x > 0) {
+    const int64_t i = (int64_t)(blockIdx.x - 1) * kOrderThreads + t;
+    if (i < counters[0]) {
+      float* p = g2d + (int64_t)dval[i] * kG2D;
+#pragma unroll
+      for (int k = 0; k < kG2D; k++) p[k] = 0.f;
+    }
+    return;
+  }
   if (t < kOrderBuckets) s_h[t] = 0;
   __syncthreads();
   auto bucket = [&](uint32_t k) {
@@ -653,9 +667,12 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
   if (gp)
     hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
                        (uint32_t)vt.total_tiles, b.ranges);
-  if (vt.total_tiles > 0)
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges,
-                       (uint32_t)vt.total_tiles, b.tile_order);
+  // the tile order, and the gradient accumulators cleared for a backward
+  const unsigned gz = b.g2d ? (unsigned)((b.E + kOrderThreads - 1) / kOrderThreads) : 0u;
+  if (vt.total_tiles > 0 || gz)
+    hipLaunchKernelGGL(k_tile_order, dim3(1 + gz), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges,
+                       (uint32_t)vt.total_tiles, b.tile_order, (const uint32_t*)b.dval[b.dsorted],
+                       (const uint32_t*)b.counters, b.g2d);
 }
 
 namespace {
@@ -704,9 +721,51 @@ void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* 
                (uint32_t*)nullptr, err, st);
 }
 
+namespace {
+// The work items of up to kOneGroupTiles tiles in one workgroup of 1024
+// threads: each thread takes a run of consecutive positions of the order,
+// a block scan gives the runs' item offsets, and each thread writes its items.
+// (A single launch with no look-back: the scan sits between the two
+// compositing kernels, so its latency is on the step's critical path.)
+constexpr int kOneGroupThreads = 1024;
+constexpr int64_t kOneGroupTiles = 1 << 17;
+__global__ void __launch_bounds__(kOneGroupThreads) k_chunk_items(const uint32_t* __restrict__ nch,
+                                                                  const uint32_t* __restrict__ order, uint32_t T,
+                                                                  uint2* __restrict__ items, uint32_t cap,
+                                                                  uint32_t* __restrict__ n_items) {
+  __shared__ uint32_t s_w[kOneGroupThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t per = (T + kOneGroupThreads - 1) / kOneGroupThreads;
+  const uint32_t i0 = min((uint32_t)t * per, T), i1 = min(i0 + per, T);
+  uint32_t sum = 0;
+  for (uint32_t i = i0; i < i1; i++) sum += nch[order[i]];
+  const uint32_t inc = wave_scan_incl(sum);
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint32_t pre = inc - sum, total = 0;
+  for (int w = 0; w < kOneGroupThreads / 64; w++) {
+    pre += (w < wv) ? s_w[w] : 0u;
+    total += s_w[w];
+  }
+  for (uint32_t i = i0; i < i1; i++) {
+    const uint32_t tile = order[i];
+    const uint32_t v = nch[tile];
+    for (uint32_t k = 0; k < v; k++)
+      if (pre + k < cap) items[pre + k] = make_uint2(tile, k);
+    pre += v;
+  }
+  if (t == 0) *n_items = total;
+}
+}  // namespace
+
 void launch_chunk_items(const uint32_t* tile_nch, const uint32_t* order, int64_t total_tiles, uint2* items,
                         int64_t items_cap, uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st) {
   const uint32_t T = (uint32_t)total_tiles;
+  if (total_tiles <= kOneGroupTiles) {
+    hipLaunchKernelGGL(k_chunk_items, dim3(1), dim3(kOneGroupThreads), 0, st, tile_nch, order, T, items,
+                       (uint32_t)items_cap, n_items);
+    return;
+  }
   scan1<false>(TileChunks{tile_nch, order}, ExpandItems{items, order, (uint32_t)items_cap}, nullptr, T, T,
                total_tiles, state, reinterpret_cast<uint64_t*>(state + 2), n_items, (uint32_t*)nullptr, err, st);
 }

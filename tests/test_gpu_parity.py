@@ -272,3 +272,18 @@ def test_backward_chunk_lengths_agree(batch):
         errs = _group_errors(grads[chunk], ref)
         _say("batch", batch, "chunk", chunk, "vs one chunk per tile", {k: f"{v:.1e}" for k, v in errs.items()})
         assert all(v < 2e-5 for v in errs.values())
+
+
+def test_second_backward_of_one_forward_repeats_the_gradient():
+    """The forward clears the screen-space gradient accumulators for the
+    backward that follows; a second backward of the same forward clears them
+    itself, so it returns the same gradient (up to the order of float atomics)."""
+    w, pn = G.scene("c1", 20000)
+    cam = synth.default_camera(160, 128)
+    r, p, _ = G.render(pn, [cam])
+    dl = torch.from_numpy(synth.upstream_gradient([cam])[0]).to(G.DEV)
+    g1 = r.backward(p, [dl]).cpu().numpy().astype(np.float64)
+    g2 = r.backward(p, [dl]).cpu().numpy().astype(np.float64)
+    scale = np.abs(g1).max()
+    assert scale > 0
+    assert np.abs(g1 - g2).max() <= 1e-5 * scale
