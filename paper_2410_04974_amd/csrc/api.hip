@@ -78,7 +78,7 @@ struct sixdgs_ctx {
   // backward and loss
   DevBuf<float> g2d, l1_partial, ssim_maps, ssim_partial;
   // scratch
-  DevBuf<uint32_t> rstate, blk_start, counters, tile_order;
+  DevBuf<uint32_t> rstate, blk_start, counters, tile_order, order_state;
   uint32_t* host_counters = nullptr;  // pinned
   // state of the last forward
   bool have_fwd = false;
@@ -261,6 +261,7 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.rstate_pairs = c->rstate.p + sort_state_words(std::max<int64_t>(E, 1), false);
   b.blk_start = c->blk_start.p;
   b.tile_order = c->tile_order.p;
+  b.order_state = c->order_state.p;
   b.g2d = c->bin_g2d;
   b.chunk_state = c->chunk_state.p;
   b.counters = c->counters.p;
@@ -328,7 +329,8 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
     return fail(c, SIXDGS_ERR_OOM, "sort scratch");
   if (!c->ranges.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile ranges");
   if (!c->chunk_state.ensure(chunk_scan_words(c->vt.total_tiles))) return fail(c, SIXDGS_ERR_OOM, "tile scan");
-  if (!c->tile_order.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile order");
+  if (!c->tile_order.ensure(std::max<int64_t>(c->vt.total_tiles, 1)) || !c->order_state.ensure(order_state_words()))
+    return fail(c, SIXDGS_ERR_OOM, "tile order");
   fill_sort_buffers(c, E);
   Timer t(c, SIXDGS_K_SORT, st);
   launch_bin_count(c->sb, st);
@@ -429,6 +431,7 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   c->dens_state.release();
   c->blk_start.release();
   c->tile_order.release();
+  c->order_state.release();
   c->counters.release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   delete c;

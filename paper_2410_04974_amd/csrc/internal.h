@@ -147,6 +147,7 @@ struct SortBuffers {
   uint32_t* blk_start;     // [sort_block_starts(pcap)] first sorted entry of each emission block
   uint32_t* tile_order;    // [total_tiles] tiles, longest lists first (the compositing order)
   float* g2d;              // [E][kG2D] screen-space gradient accumulators to clear, or nullptr
+  uint32_t* order_state;   // [order_state_words()] bucket counts and cursors of the tile order
   uint32_t* chunk_state;   // [chunk_scan_words(total_tiles)] state of the backward work-item scan
   uint32_t* counters;      // [0] binned entries, [1] pairs, [2] overflow flag, [3] sort look-back timeout
   // where the sorted results ended up (index into the ping-pong pairs)
@@ -155,6 +156,7 @@ struct SortBuffers {
 // Scratch sizes (32-bit words) of the integer stage for a bound on the items.
 int64_t sort_state_words(int64_t bound, bool pairs);
 int64_t sort_block_starts(int64_t pcap);
+int64_t order_state_words();
 // Stage 1: compaction of binned entries and their depth sort, then the pair
 // offsets; leaves counters[0] = binned entries, counters[1] = pairs.
 void launch_bin_count(SortBuffers& b, hipStream_t st);

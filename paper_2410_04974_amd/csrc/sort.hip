@@ -299,28 +299,14 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
   if (t == 0) s_blk = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kWaves; w++) s_wc[w][t] = 0;
-  const uint32_t count = load_count(count_ptr, cap, cap);
-  const uint32_t mask = (1u << dbits) - 1u;
-  const bool own = (uint32_t)t <= mask;
-  const uint32_t gh = own ? ghist[t] : 0u;
-  // every key has the same digit in this pass (e.g. the exponent byte of
-  // depths within one octave): the stable order is the input order, so the
-  // pass is a copy
-  const bool one = __syncthreads_or(own && count > 0 && gh == count);
+  __syncthreads();
   const int64_t blk = s_blk;
+  const uint32_t count = load_count(count_ptr, cap, cap);
   const int64_t base = blk * kChunkI;
   if (base >= count) return;  // uniform; no later workgroup has items, so none waits on this one
-  if (one) {
-#pragma unroll
-    for (int r = 0; r < ITEMS; r++) {
-      const int64_t i = base + (int64_t)r * kBlock + t;
-      if (i < count) {
-        kout[i] = kin[i];
-        vout[i] = vin[i];
-      }
-    }
-    return;
-  }
+  const uint32_t mask = (1u << dbits) - 1u;
+  const bool own = (uint32_t)t <= mask;
+  const uint32_t gh = own ? ghist[t] : 0u;  // issued early: used after the look-back
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t wbase = base + (int64_t)wv * kWaveItems;  // each wavefront ranks consecutive items
   uint32_t key[ITEMS], val[ITEMS], loc[ITEMS];
@@ -329,6 +315,20 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
     const int64_t i = wbase + r * 64 + lane;
     key[r] = i < count ? kin[i] : 0u;
     val[r] = i < count ? vin[i] : 0u;
+  }
+  // every key has the same digit in this pass (e.g. the exponent byte of
+  // depths within one octave): the stable order is the input order, so the
+  // pass is a copy (decided while the loads are in flight)
+  if (__syncthreads_or(own && gh == count)) {
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+      const int64_t i = wbase + r * 64 + lane;
+      if (i < count) {
+        kout[i] = key[r];
+        vout[i] = val[r];
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int r = 0; r < ITEMS; r++) {
@@ -543,12 +543,72 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const uint32_t* __restrict__ 
 // Order in which the compositing kernels take the tiles: longest lists first
 // (buckets of log2 of the pair count, heaviest bucket first), so the tiles
 // whose per-pixel walks are longest start before the light ones and the
-// kernels' tails shrink.  One workgroup of 1024 threads: a bucket histogram,
-// its scan and a scatter; the order inside a bucket is arbitrary.
-// Workgroups past the first zero the screen-space gradient accumulators of
-// the binned entries (when g2d is given) for the backward that may follow.
+// kernels' tails shrink (LPT scheduling); the order inside a bucket is
+// arbitrary.  Up to kOrderOneGroup tiles one workgroup of 1024 threads takes
+// the bucket histogram, its scan and the scatter; beyond, k_order_count and
+// k_order_place split the same over many workgroups, which reserve their
+// places inside each bucket with one device atomic per bucket.  Workgroups
+// past the ordering ones zero the screen-space gradient accumulators of the
+// binned entries (when g2d is given) for the backward that may follow.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 33;
+constexpr int kOrderU = 8;                                   // tiles per thread and round
+constexpr uint32_t kOrderGroupTiles = kOrderThreads * kOrderU;
+constexpr uint32_t kOrderOneGroup = 2 * kOrderGroupTiles;    // one workgroup orders up to this many tiles
+constexpr int kOrderStateWords = 2 * kOrderBuckets;          // bucket counts, then bucket cursors
+
+// the bucket of tile k (heaviest first: slot 0 holds 2^31 pairs and more, the
+// last slot the empty tiles), -1 past the last tile
+__device__ __forceinline__ int order_slot(const uint2* __restrict__ ranges, uint32_t total_tiles, uint32_t k) {
+  if (k >= total_tiles) return -1;
+  const uint2 r = ranges[k];
+  const uint32_t c = r.y - r.x;
+  return kOrderBuckets - 1 - (c ? 32 - __clz(c) : 0);
+}
+
+// Adds the lanes of each distinct slot b (>= 0) of the wavefront to h[b] with
+// one LDS atomic per slot (the lanes mostly agree, and same-address atomics
+// from the lanes of a wavefront would serialise); returns what the atomic
+// returned for this lane's slot plus the lane's rank among that slot's lanes.
+__device__ __forceinline__ uint32_t wave_add(int b, uint32_t* h) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t todo = __ballot(b >= 0);
+  uint32_t mine = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int v = __shfl(b, leader, 64);
+    const uint64_t m = __ballot(b == v);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&h[v], (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    if (b == v) mine = base + (uint32_t)__popcll(m & lt);
+    todo &= ~m;
+  }
+  return mine;
+}
+
+__device__ __forceinline__ void zero_g2d_rows(int64_t i, const uint32_t* __restrict__ dval,
+                                              const uint32_t* __restrict__ counters, float* __restrict__ g2d) {
+  if (i < counters[0]) {
+    float* p = g2d + (int64_t)dval[i] * kG2D;
+#pragma unroll
+    for (int k = 0; k < kG2D; k++) p[k] = 0.f;
+  }
+}
+
+// exclusive scan of the kOrderBuckets counts in s (one thread; tiny)
+__device__ __forceinline__ void scan_buckets(uint32_t* s) {
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 0; b < kOrderBuckets; b++) {
+      const uint32_t c = s[b];
+      s[b] = acc;
+      acc += c;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __restrict__ ranges, uint32_t total_tiles,
                                                               uint32_t* __restrict__ order,
                                                               const uint32_t* __restrict__ dval,
@@ -557,35 +617,89 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __res
   __shared__ uint32_t s_h[kOrderBuckets];
   const int t = threadIdx.x;
   if (blockIdx.x > 0) {
-    const int64_t i = (int64_t)(blockIdx.x - 1) * kOrderThreads + t;
-    if (i < counters[0]) {
-      float* p = g2d + (int64_t)dval[i] * kG2D;
-#pragma unroll
-      for (int k = 0; k < kG2D; k++) p[k] = 0.f;
-    }
+    zero_g2d_rows((int64_t)(blockIdx.x - 1) * kOrderThreads + t, dval, counters, g2d);
     return;
   }
   if (t < kOrderBuckets) s_h[t] = 0;
   __syncthreads();
-  auto bucket = [&](uint32_t k) {
-    const uint2 r = ranges[k];
-    const uint32_t c = r.y - r.x;
-    return c ? 32 - __clz(c) : 0;  // 0 for an empty tile, else 1 + floor(log2 c)
-  };
-  for (uint32_t k = t; k < total_tiles; k += kOrderThreads) atomicAdd(&s_h[kOrderBuckets - 1 - bucket(k)], 1u);
-  __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int b = 0; b < kOrderBuckets; b++) {
-      const uint32_t c = s_h[b];
-      s_h[b] = acc;
-      acc += c;
-    }
+  const uint32_t span = (total_tiles + kOrderGroupTiles - 1) / kOrderGroupTiles * kOrderGroupTiles;
+  for (uint32_t k0 = t; k0 < span; k0 += kOrderGroupTiles) {
+    int b[kOrderU];
+#pragma unroll
+    for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+#pragma unroll
+    for (int u = 0; u < kOrderU; u++) wave_add(b[u], s_h);
   }
   __syncthreads();
-  for (uint32_t k = t; k < total_tiles; k += kOrderThreads) {
-    const uint32_t pos = atomicAdd(&s_h[kOrderBuckets - 1 - bucket(k)], 1u);
-    if (pos < total_tiles) order[pos] = k;
+  scan_buckets(s_h);
+  __syncthreads();
+  for (uint32_t k0 = t; k0 < span; k0 += kOrderGroupTiles) {
+    int b[kOrderU];
+#pragma unroll
+    for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+#pragma unroll
+    for (int u = 0; u < kOrderU; u++) {
+      const uint32_t pos = wave_add(b[u], s_h);
+      if (b[u] >= 0 && pos < total_tiles) order[pos] = k0 + u * kOrderThreads;
+    }
+  }
+}
+
+// Many tiles, first half: bucket counts of kOrderGroupTiles tiles per
+// workgroup, added into state[0, kOrderBuckets) (zeroed beforehand).
+__global__ void __launch_bounds__(kOrderThreads) k_order_count(const uint2* __restrict__ ranges, uint32_t total_tiles,
+                                                               uint32_t ngroups, uint32_t* __restrict__ state,
+                                                               const uint32_t* __restrict__ dval,
+                                                               const uint32_t* __restrict__ counters,
+                                                               float* __restrict__ g2d) {
+  __shared__ uint32_t s_h[kOrderBuckets];
+  const int t = threadIdx.x;
+  if (blockIdx.x >= ngroups) {
+    zero_g2d_rows((int64_t)(blockIdx.x - ngroups) * kOrderThreads + t, dval, counters, g2d);
+    return;
+  }
+  if (t < kOrderBuckets) s_h[t] = 0;
+  __syncthreads();
+  const uint32_t k0 = blockIdx.x * kOrderGroupTiles + t;
+  int b[kOrderU];
+#pragma unroll
+  for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+#pragma unroll
+  for (int u = 0; u < kOrderU; u++) wave_add(b[u], s_h);
+  __syncthreads();
+  if (t < kOrderBuckets && s_h[t]) atomicAdd(&state[t], s_h[t]);
+}
+
+// Second half: each workgroup ranks its tiles inside their buckets, reserves
+// a run of places per bucket (device atomics on state[kOrderBuckets + b]) and
+// writes the tiles there.
+__global__ void __launch_bounds__(kOrderThreads) k_order_place(const uint2* __restrict__ ranges, uint32_t total_tiles,
+                                                               uint32_t* __restrict__ state,
+                                                               uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_off[kOrderBuckets];   // first place of each bucket
+  __shared__ uint32_t s_loc[kOrderBuckets];   // this workgroup's count per bucket, then its reserved base
+  const int t = threadIdx.x;
+  if (t < kOrderBuckets) {
+    s_off[t] = state[t];
+    s_loc[t] = 0;
+  }
+  __syncthreads();
+  scan_buckets(s_off);
+  const uint32_t k0 = blockIdx.x * kOrderGroupTiles + t;
+  int b[kOrderU];
+  uint32_t rank[kOrderU];
+#pragma unroll
+  for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+#pragma unroll
+  for (int u = 0; u < kOrderU; u++) rank[u] = wave_add(b[u], s_loc);
+  __syncthreads();
+  if (t < kOrderBuckets && s_loc[t]) s_loc[t] = atomicAdd(&state[kOrderBuckets + t], s_loc[t]);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kOrderU; u++) {
+    if (b[u] < 0) continue;
+    const uint32_t pos = s_off[b[u]] + s_loc[b[u]] + rank[u];
+    if (pos < total_tiles) order[pos] = k0 + u * kOrderThreads;
   }
 }
 
@@ -631,7 +745,8 @@ void launch_bin_count(SortBuffers& b, hipStream_t st) {
   const unsigned gprep = (unsigned)((rs.words() / 4 + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_stage_prep, dim3(gprep), dim3(kBlock), 0, st, rs, (uint2*)nullptr, (int64_t)0,
                      (const uint32_t*)b.counters, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
-                     (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0, (uint32_t*)nullptr, (int64_t)0);
+                     (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0, b.order_state,
+                     (int64_t)kOrderStateWords);
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
   scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.depth, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
               rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
@@ -669,10 +784,18 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
                        (uint32_t)vt.total_tiles, b.ranges);
   // the tile order, and the gradient accumulators cleared for a backward
   const unsigned gz = b.g2d ? (unsigned)((b.E + kOrderThreads - 1) / kOrderThreads) : 0u;
-  if (vt.total_tiles > 0 || gz)
-    hipLaunchKernelGGL(k_tile_order, dim3(1 + gz), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges,
-                       (uint32_t)vt.total_tiles, b.tile_order, (const uint32_t*)b.dval[b.dsorted],
-                       (const uint32_t*)b.counters, b.g2d);
+  const uint32_t T = (uint32_t)vt.total_tiles;
+  if (T <= kOrderOneGroup) {
+    if (T > 0 || gz)
+      hipLaunchKernelGGL(k_tile_order, dim3(1 + gz), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges, T,
+                         b.tile_order, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.counters, b.g2d);
+  } else {
+    const uint32_t ng = (T + kOrderGroupTiles - 1) / kOrderGroupTiles;
+    hipLaunchKernelGGL(k_order_count, dim3(ng + gz), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges, T, ng,
+                       b.order_state, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.counters, b.g2d);
+    hipLaunchKernelGGL(k_order_place, dim3(ng), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges, T,
+                       b.order_state, b.tile_order);
+  }
 }
 
 namespace {
@@ -774,6 +897,7 @@ int64_t sort_state_words(int64_t bound, bool pairs) {
   return radix_state(nullptr, bound, pairs ? kRItems : kRItemsSmall, !pairs).words();
 }
 int64_t sort_block_starts(int64_t pcap) { return radix_blocks(pcap, kRItems) + 1; }
+int64_t order_state_words() { return kOrderStateWords; }
 
 void launch_zero_g2d(const SortBuffers& b, float* g2d, hipStream_t st) {
   const unsigned g = (unsigned)((b.E + kBlock - 1) / kBlock);
