@@ -558,34 +558,42 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
       grad(X, g);
     }
     __syncthreads();
-    // one set of global atomics per (tile, Gaussian); the conic gradient goes
-    // from the pre-scaled coefficients back to the conic's full-matrix gradient
-    if ((uint32_t)threadIdx.x < nb) {
-      const int t = threadIdx.x;
+    // one set of global atomics per (chunk, Gaussian).  Each staged
+    // Gaussian's thread turns its column of sums into the nine components in
+    // place (the conic gradient goes from the pre-scaled coefficients back to
+    // the conic's full-matrix gradient); the adds then go Gaussian-major, so
+    // that consecutive lanes add to consecutive words of one Gaussian's row (a
+    // memory request per row instead of one per component), zero components
+    // skipped.
+    const int t = threadIdx.x;
+    static_assert(sizeof(L.list) >= sizeof(uint32_t) * kBlock, "entry ids fit the slot lists");
+    uint32_t* s_ent = reinterpret_cast<uint32_t*>(L.list);  // the slot lists are no longer read
+    if ((uint32_t)t < nb) {
       float v[kG2D];
-      bool any = false;
 #pragma unroll
-      for (int k = 0; k < kG2D; k++) {
-        v[k] = s_g[k][t];
-        s_g[k][t] = 0.f;
-        any |= v[k] != 0.f;
-      }
-      if (any) {
-        // exponent p2 = log2(alpha) = cA dx^2 + cB dx dy + cC dy^2 + log2(alpha_cond), with
-        // dx = x - u: dp2/du = -(2 cA dx + cB dy), dp2/dv = -(cB dx + 2 cC dy); and
-        // dp2/dcA = dx^2 etc., cA = kq Qxx, cB = 2 kq Qxy, cC = kq Qyy
-        const Staged& sr = L.rec[t];
-        const float m0 = v[0] * kLn2, m1 = v[1] * kLn2;  // moments of dL/dp2 = dL/dp ln 2
-        float* dst = g2d + (int64_t)__float_as_uint(sr.b.w) * kG2D;
-        unsafeAtomicAdd(dst + 0, -(2.f * sr.a.z * m0 + sr.a.w * m1));
-        unsafeAtomicAdd(dst + 1, -(sr.a.w * m0 + 2.f * sr.b.x * m1));
-        unsafeAtomicAdd(dst + 2, v[2] * (kLn2 * kq));
-        unsafeAtomicAdd(dst + 3, v[3] * (kLn2 * kq));
-        unsafeAtomicAdd(dst + 4, v[4] * (kLn2 * kq));
-        unsafeAtomicAdd(dst + 5, v[5] * sr.b.z);  // d alpha / d alpha_cond = alpha / alpha_cond
-        unsafeAtomicAdd(dst + 6, v[6]);
-        unsafeAtomicAdd(dst + 7, v[7]);
-        unsafeAtomicAdd(dst + 8, v[8]);
+      for (int k = 0; k < kG2D; k++) v[k] = s_g[k][t];
+      // exponent p2 = log2(alpha) = cA dx^2 + cB dx dy + cC dy^2 + log2(alpha_cond), with
+      // dx = x - u: dp2/du = -(2 cA dx + cB dy), dp2/dv = -(cB dx + 2 cC dy); and
+      // dp2/dcA = dx^2 etc., cA = kq Qxx, cB = 2 kq Qxy, cC = kq Qyy
+      const Staged& sr = L.rec[t];
+      const float m0 = v[0] * kLn2, m1 = v[1] * kLn2;  // moments of dL/dp2 = dL/dp ln 2
+      s_g[0][t] = -(2.f * sr.a.z * m0 + sr.a.w * m1);
+      s_g[1][t] = -(sr.a.w * m0 + 2.f * sr.b.x * m1);
+      s_g[2][t] = v[2] * (kLn2 * kq);
+      s_g[3][t] = v[3] * (kLn2 * kq);
+      s_g[4][t] = v[4] * (kLn2 * kq);
+      s_g[5][t] = v[5] * sr.b.z;  // d alpha / d alpha_cond = alpha / alpha_cond
+      s_ent[t] = __float_as_uint(sr.b.w);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int r = 0; r < kG2D; r++) {
+      const uint32_t idx = (uint32_t)(r * kBlock + t);
+      if (idx < nb * kG2D) {
+        const uint32_t jg = idx / kG2D, k = idx - jg * kG2D;
+        const float val = s_g[k][jg];
+        s_g[k][jg] = 0.f;
+        if (val != 0.f) unsafeAtomicAdd(g2d + (int64_t)s_ent[jg] * kG2D + k, val);
       }
     }
     __syncthreads();
