@@ -164,11 +164,14 @@ struct Group4 {
   float3 c[4];    // r, g, b
 };
 
-__device__ __forceinline__ void fetch_group(const BatchLDS& L, uint32_t lw, uint32_t g, Group4& G) {
+// Slots past the list's length wn take the group's first slot instead: the
+// bytes there are left over from earlier use of the LDS, and a record never
+// staged may hold infinities or NaNs, which a zero weight does not cancel.
+__device__ __forceinline__ void fetch_group(const BatchLDS& L, uint32_t lw, uint32_t g, uint32_t wn, Group4& G) {
   const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)lw, (int)g);
 #pragma unroll
   for (int u = 0; u < 4; u++) {
-    const uint32_t j = (w >> (8 * u)) & 255u;
+    const uint32_t j = (4 * g + u < wn ? w >> (8 * u) : w) & 255u;
     G.j[u] = j;
     G.a[u] = L.rec[j].a;
     G.b[u] = make_float2(L.rec[j].b.x, L.rec[j].b.y);
@@ -554,7 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_blend_bwd(ViewTable vt, DevSettings 
     };
     for (int g = ng - 1; g >= 0; g--) {
       Group4 X;
-      fetch_group(L, lw, (uint32_t)g, X);
+      fetch_group(L, lw, (uint32_t)g, wn, X);
       grad(X, g);
     }
     __syncthreads();

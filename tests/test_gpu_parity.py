@@ -287,3 +287,28 @@ def test_second_backward_of_one_forward_repeats_the_gradient():
     scale = np.abs(g1).max()
     assert scale > 0
     assert np.abs(g1 - g2).max() <= 1e-5 * scale
+
+
+def test_backward_ignores_lds_left_by_earlier_kernels():
+    """The backward reads its staged records through per-wavefront slot lists;
+    the slots past a list's end hold whatever an earlier kernel left in LDS.
+    With reductions over NaN run between the forward and the backward (their
+    partial sums pass through LDS), the gradient stays finite and equal to the
+    one computed without them (up to the order of float atomics)."""
+    w, pn = G.scene("c1")
+    cam = w.cameras[0]
+    p = G.to_dev(pn)
+    dl = torch.from_numpy(synth.upstream_gradient([cam])[0]).to(G.DEV)
+    r = G.renderer(chunk=16384)
+    r.forward(p, [cam])
+    g1 = r.backward(p, [dl]).cpu().numpy().astype(np.float64)
+    poison = torch.full((1 << 24,), float("nan"), device=G.DEV)
+    r.forward(p, [cam])
+    for _ in range(4):
+        poison.sum()
+        torch.softmax(poison.view(-1, 4096), dim=1)
+        torch.cumsum(poison.view(-1, 4096), dim=1)
+    g2 = r.backward(p, [dl]).cpu().numpy().astype(np.float64)
+    assert np.isfinite(g2).all()
+    scale = np.abs(g1).max()
+    assert np.abs(g1 - g2).max() <= 1e-5 * scale
