@@ -55,7 +55,8 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t& total)
 }
 
 // ------------------------------------------------------------ radix sort
-// One kernel per pass: each workgroup takes the next 4096 items in ticket
+// The depth order's passes (the pair sort's are further below): one kernel
+// per pass, where each workgroup takes the next 4096 items in ticket
 // order, ranks them stably by digit in LDS, and finds where its items of each
 // digit go by looking back over the per-digit counts that earlier workgroups
 // publish (a status word per digit: aggregate of that workgroup alone, or
@@ -78,7 +79,7 @@ constexpr int kMaxSpin = 1 << 20;
 struct RadixState {
   uint32_t* ghist;        // [kMaxPasses][256]
   uint32_t* tickets;      // [kMaxPasses] passes, then [2] scans (padded to 256 words)
-  uint32_t* status;       // [kMaxPasses][nblk][256]
+  uint32_t* status;       // [kMaxPasses][nblk][256]: look-back words (depth sort), chunk tables (pair sort)
   uint64_t* scan_status;  // [2][nscan] look-back words of the two scans over entries
   int64_t nblk, nscan;
   int items;              // items per thread of the passes
@@ -256,7 +257,8 @@ void scan1(F f, G g, const uint32_t* count_ptr, uint32_t fixed, uint32_t cap, in
                      ticket, status, total_out, ghist, err);
 }
 
-// Zeroes a radix state (and optionally the tile ranges), and when given the
+// Zeroes the first zero_words words of a radix state (and optionally the tile
+// ranges), and when given the
 // depth-sorted entries, records for every 4096-pair block the sorted entry
 // whose pairs contain the block's first pair.
 __global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, uint2* __restrict__ ranges, int64_t nranges,
@@ -265,9 +267,10 @@ __global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, uint2* __r
                                                        const uint32_t* __restrict__ dval,
                                                        const uint32_t* __restrict__ poff, uint32_t pcap,
                                                        uint32_t* __restrict__ blk_start, int64_t nblk_start,
-                                                       uint32_t* __restrict__ extra, int64_t extra_words) {
+                                                       uint32_t* __restrict__ extra, int64_t extra_words,
+                                                       int64_t zero_words) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t w4 = rs.words() / 4;
+  const int64_t w4 = zero_words / 4;
   if (i < w4) reinterpret_cast<uint4*>(rs.ghist)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (extra && i < extra_words) extra[i] = 0u;
   if (ranges && i < nranges) ranges[i] = make_uint2(0u, 0u);
@@ -396,6 +399,170 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
   }
 }
 
+// ---------------------------------------------------- reduce-then-scan passes
+// The pair sort's passes in three launches with no chain between workgroups
+// (the wait on earlier workgroups' counts dominated the one-kernel passes at
+// a few thousand workgroups, and the emission counts the first pass's chunks
+// for free):
+// each 4,096-item chunk's digit counts (k_digit_count; for the first pass the
+// emission writes them), one scan per digit over the chunks, offset by the
+// counts of the smaller digits (k_digit_scan), and the stable scatter
+// (k_digit_scatter), where chunk b's items of digit d start at the scanned
+// table entry (d, b).  The tables are [digit][chunk]; chunks past the item
+// count are read as zero.
+
+// Stable ranks of the workgroup's items by digit, each wavefront over its
+// consecutive items (ballot matching): loc[r] = (rank in the wavefront << 8) |
+// digit, or ~0 past the count; on return wc[w][d] holds the count of digit d in
+// the wavefronts before w, and the return value is the workgroup's count of
+// digit threadIdx.x.
+template <int ITEMS>
+__device__ __forceinline__ uint32_t rank_chunk(uint32_t (*wc)[256], const uint32_t (&key)[ITEMS], int64_t wbase,
+                                               uint32_t count, int shift, int dbits, uint32_t (&loc)[ITEMS]) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t mask = (1u << dbits) - 1u;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const bool valid = wbase + r * 64 + lane < count;
+    const uint32_t d = (key[r] >> shift) & mask;
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < dbits; b++) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(m & lt);
+    // every lane of a digit group reads the running count before its first lane moves it on
+    const uint32_t pre = wc[wv][d];
+    if (valid && rank == 0) wc[wv][d] = pre + (uint32_t)__popcll(m);
+    loc[r] = valid ? ((pre + rank) << 8 | d) : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; w++) {
+    const uint32_t c = wc[w][t];
+    wc[w][t] = tot;
+    tot += c;
+  }
+  return tot;
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_digit_count(const uint32_t* __restrict__ kin, const uint32_t* count_ptr,
+                                                        uint32_t cap, int shift, int dbits,
+                                                        uint32_t* __restrict__ table, int64_t nblk) {
+  constexpr int kChunkI = kBlock * ITEMS;
+  __shared__ uint32_t s_wc[kWaves][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t blk = blockIdx.x;
+  const uint32_t count = load_count(count_ptr, cap, cap);
+  const int64_t base = blk * kChunkI;
+  if (base >= count) return;  // uniform
+#pragma unroll
+  for (int w = 0; w < kWaves; w++) s_wc[w][t] = 0;
+  __syncthreads();
+  const int64_t wbase = base + (int64_t)wv * (kChunkI / kWaves);
+  uint32_t key[ITEMS], loc[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const int64_t i = wbase + r * 64 + lane;
+    key[r] = i < count ? kin[i] : 0u;
+  }
+  const uint32_t tot = rank_chunk<ITEMS>(s_wc, key, wbase, count, shift, dbits, loc);
+  if ((uint32_t)t < (1u << dbits)) table[(int64_t)t * nblk + blk] = tot;
+}
+
+// One workgroup per digit d: table[d][b] <- (items of digits < d) + (items of
+// digit d in chunks < b), over the chunks that hold items.
+__global__ void __launch_bounds__(kBlock) k_digit_scan(uint32_t* __restrict__ table, int64_t nblk,
+                                                       const uint32_t* count_ptr, uint32_t cap, int chunk_items,
+                                                       const uint32_t* __restrict__ ghist) {
+  const int d = blockIdx.x, t = threadIdx.x;
+  const uint32_t count = load_count(count_ptr, cap, cap);
+  const int64_t used = ((int64_t)count + chunk_items - 1) / chunk_items;
+  uint32_t dbase;  // items of the digits below d: the total of this scan
+  block_scan_excl((uint32_t)t < (uint32_t)d ? ghist[t] : 0u, dbase);
+  uint32_t* row = table + (int64_t)d * nblk;
+  const int64_t per = (used + kBlock - 1) / kBlock;
+  const int64_t b0 = min<int64_t>((int64_t)t * per, used), b1 = min<int64_t>(b0 + per, used);
+  uint32_t sum = 0;
+  for (int64_t b = b0; b < b1; b++) sum += row[b];
+  uint32_t all;
+  uint32_t pre = dbase + block_scan_excl(sum, all);
+  for (int64_t b = b0; b < b1; b++) {
+    const uint32_t c = row[b];
+    row[b] = pre;
+    pre += c;
+  }
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_digit_scatter(const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                          uint32_t* __restrict__ vout, const uint32_t* count_ptr,
+                                                          uint32_t cap, int shift, int dbits,
+                                                          const uint32_t* __restrict__ table, int64_t nblk) {
+  constexpr int kChunkI = kBlock * ITEMS;
+  __shared__ uint32_t s_key[kChunkI];
+  __shared__ uint32_t s_val[kChunkI];
+  __shared__ uint32_t s_wc[kWaves][256];
+  __shared__ uint32_t s_lex[256];
+  __shared__ uint32_t s_gb[256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t blk = blockIdx.x;
+  const uint32_t count = load_count(count_ptr, cap, cap);
+  const int64_t base = blk * kChunkI;
+  if (base >= count) return;  // uniform
+  const uint32_t mask = (1u << dbits) - 1u;
+  const bool own = (uint32_t)t <= mask;
+  const uint32_t gstart = own ? table[(int64_t)t * nblk + blk] : 0u;  // issued early
+#pragma unroll
+  for (int w = 0; w < kWaves; w++) s_wc[w][t] = 0;
+  __syncthreads();
+  const int64_t wbase = base + (int64_t)wv * (kChunkI / kWaves);
+  uint32_t key[ITEMS], val[ITEMS], loc[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const int64_t i = wbase + r * 64 + lane;
+    key[r] = i < count ? kin[i] : 0u;
+    val[r] = i < count ? vin[i] : 0u;
+  }
+  const uint32_t tot = rank_chunk<ITEMS>(s_wc, key, wbase, count, shift, dbits, loc);
+  uint32_t total;
+  const uint32_t lex = block_scan_excl(tot, total);
+  s_lex[t] = lex;
+  s_gb[t] = gstart - lex;  // modular: adding an LDS slot of this digit lands in range
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    if (loc[r] != 0xFFFFFFFFu) {
+      const uint32_t d = loc[r] & 255u;
+      const uint32_t pos = s_lex[d] + s_wc[wv][d] + (loc[r] >> 8);
+      if (pos < (uint32_t)kChunkI) {  // always true; guards LDS against inconsistent counts
+        s_key[pos] = key[r];
+        s_val[pos] = val[r];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t left = (int64_t)count - base;
+  const int nvalid = left < kChunkI ? (int)left : kChunkI;
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const int k = r * kBlock + t;
+    if (k < nvalid) {
+      const uint32_t kk = s_key[k];
+      const uint32_t o = s_gb[(kk >> shift) & mask] + (uint32_t)k;
+      if (o < count) {  // always true for consistent tables; guards the buffers
+        kout[o] = kk;
+        vout[o] = s_val[k];
+      }
+    }
+  }
+}
+
 // Sorts (keys, vals) of length *count_ptr (<= bound) over plan.npass digits
 // whose histograms are already in rs.ghist; returns which buffer of the
 // ping-pong pair holds the result.
@@ -455,7 +622,7 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
                                                  const uint32_t* __restrict__ blk_start,
                                                  uint32_t* __restrict__ counters, uint32_t pcap, int npass, int dbits,
                                                  uint32_t* __restrict__ ghist, uint32_t* __restrict__ pkey,
-                                                 uint32_t* __restrict__ pval) {
+                                                 uint32_t* __restrict__ pval, uint32_t* __restrict__ table0) {
   __shared__ uint32_t s_o[kBlock + 1];  // pair offset of each entry of the step; [kBlock]: the next step's
   __shared__ uint32_t s_e[kBlock];      // entry id
   __shared__ uint32_t s_base[kBlock];   // global id of the rectangle's first tile
@@ -516,6 +683,8 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
   }
   for (int p = 0; p < npass; p++)
     if (s_h[p][t]) atomicAdd(&ghist[p * 256 + t], s_h[p][t]);
+  // this chunk's counts of the first pass's digits (the chunk is the pass's)
+  if ((uint32_t)t <= mask) table0[(int64_t)t * gridDim.x + blockIdx.x] = s_h[0][t];
 }
 
 constexpr int kRangeItems = 8;  // consecutive pairs per thread
@@ -746,7 +915,7 @@ void launch_bin_count(SortBuffers& b, hipStream_t st) {
   hipLaunchKernelGGL(k_stage_prep, dim3(gprep), dim3(kBlock), 0, st, rs, (uint2*)nullptr, (int64_t)0,
                      (const uint32_t*)b.counters, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
                      (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0, b.order_state,
-                     (int64_t)kOrderStateWords);
+                     (int64_t)kOrderStateWords, rs.words());
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
   scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.depth, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
               rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
@@ -765,19 +934,42 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
   const int64_t bound = pairs_hint < b.pcap ? pairs_hint : b.pcap;
   const RadixState rs = radix_state(b.rstate_pairs, bound, kRItems, false);
   const int64_t cwords = chunk_scan_words(vt.total_tiles);
-  int64_t prep = rs.words() / 4;
+  // the passes write every table entry they read: only the histograms (and
+  // the unused tickets) start from zero
+  const int64_t zero_words = 2 * kMaxPasses * 256;
+  int64_t prep = zero_words / 4;
   if (prep < vt.total_tiles) prep = vt.total_tiles;
   if (prep < b.E) prep = b.E;
   if (prep < cwords) prep = cwords;
   hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs, b.ranges,
                      (int64_t)vt.total_tiles, (const uint32_t*)b.counters, (const uint32_t*)b.tiles,
                      (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.poff, (uint32_t)b.pcap, b.blk_start,
-                     rs.nblk, b.chunk_state, cwords);
-  if (rs.nblk)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)rs.nblk), dim3(kBlock), 0, st, vt, b.rec, b.dval[b.dsorted], b.poff,
+                     rs.nblk, b.chunk_state, cwords, zero_words);
+  // the pairs, with every pass's digit histogram and the first pass's per-chunk
+  // counts; then the passes, each a scan of the chunk counts and a scatter
+  // (the chunk counts of later passes taken from their input)
+  int cur = 0;
+  if (rs.nblk) {
+    const int64_t nb = rs.nblk;
+    const uint32_t cap = (uint32_t)bound;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kBlock), 0, st, vt, b.rec, b.dval[b.dsorted], b.poff,
                        b.blk_start, b.counters, (uint32_t)b.pcap, plan.npass, plan.dbits, rs.ghist, b.pkey[0],
-                       b.pval[0]);
-  b.psorted = radix_sort(b.pkey, b.pval, &b.counters[1], bound, plan, rs, &b.counters[3], st);
+                       b.pval[0], rs.status);
+    for (int p = 0; p < plan.npass; p++) {
+      uint32_t* table = rs.status + (int64_t)p * nb * 256;
+      const int shift = p * plan.dbits;
+      if (p > 0)
+        hipLaunchKernelGGL(k_digit_count<kRItems>, dim3((unsigned)nb), dim3(kBlock), 0, st, b.pkey[cur],
+                           (const uint32_t*)&b.counters[1], cap, shift, plan.dbits, table, nb);
+      hipLaunchKernelGGL(k_digit_scan, dim3(1u << plan.dbits), dim3(kBlock), 0, st, table, nb,
+                         (const uint32_t*)&b.counters[1], cap, kRChunk, (const uint32_t*)(rs.ghist + p * 256));
+      hipLaunchKernelGGL(k_digit_scatter<kRItems>, dim3((unsigned)nb), dim3(kBlock), 0, st, b.pkey[cur],
+                         b.pval[cur], b.pkey[cur ^ 1], b.pval[cur ^ 1], (const uint32_t*)&b.counters[1], cap, shift,
+                         plan.dbits, (const uint32_t*)table, nb);
+      cur ^= 1;
+    }
+  }
+  b.psorted = cur;
   const unsigned gp = (unsigned)((bound + (int64_t)kBlock * kRangeItems - 1) / ((int64_t)kBlock * kRangeItems));
   if (gp)
     hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
