@@ -260,6 +260,8 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.rstate_depth = c->rstate.p;
   b.rstate_pairs = c->rstate.p + sort_state_words(std::max<int64_t>(E, 1), false);
   b.blk_start = c->blk_start.p;
+  b.nblk_start = c->blk_start.cap;
+  b.total_tiles = c->vt.total_tiles;
   b.tile_order = c->tile_order.p;
   b.order_state = c->order_state.p;
   b.g2d = c->bin_g2d;
@@ -335,6 +337,7 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
   Timer t(c, SIXDGS_K_SORT, st);
   launch_bin_count(c->sb, st);
   int64_t hint = c->sb.pcap;
+  bool regrown = false;
   if (!fixed) {
     // read the pair count back, then size the pair buffers exactly (with slack for the next call)
     if (hipMemcpyAsync(c->host_counters, c->counters.p, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st) !=
@@ -347,10 +350,11 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
       if (!ensure_pairs(c, P, 1.25)) return fail(c, SIXDGS_ERR_OOM, "pair buffers");
       if (!ensure_scratch(c, E, c->pkey0.cap)) return fail(c, SIXDGS_ERR_OOM, "sort scratch");
       fill_sort_buffers(c, E);  // keeps dsorted: the depth-sorted entries are untouched
+      regrown = true;
     }
     hint = P;
   }
-  launch_bin_emit(c->sb, c->vt, hint, st);
+  launch_bin_emit(c->sb, c->vt, hint, regrown, st);
   return check_launch(c, "binning");
 }
 

@@ -144,7 +144,9 @@ struct SortBuffers {
   // scratch
   uint32_t* rstate_depth;  // [sort_state_words(E, false)] state of the scans and the depth sort
   uint32_t* rstate_pairs;  // [sort_state_words(pcap, true)] radix state of the tile sort
-  uint32_t* blk_start;     // [sort_block_starts(pcap)] first sorted entry of each emission block
+  uint32_t* blk_start;     // [nblk_start] first sorted entry of each emission block
+  int64_t nblk_start;      // sort_block_starts(pcap) when the pair buffers were sized
+  int64_t total_tiles;     // tiles of the views being binned
   uint32_t* tile_order;    // [total_tiles] tiles, longest lists first (the compositing order)
   float* g2d;              // [E][kG2D] screen-space gradient accumulators to clear, or nullptr
   uint32_t* order_state;   // [order_state_words()] bucket counts and cursors of the tile order
@@ -162,8 +164,10 @@ int64_t order_state_words();
 void launch_bin_count(SortBuffers& b, hipStream_t st);
 // Stage 2: emission of (tile, entry) pairs, their stable tile sort and the
 // per-tile ranges; `pairs_hint` bounds the launch sizes (the capacity in
-// fixed mode, the exact count otherwise).
-void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hipStream_t st);
+// fixed mode, the exact count otherwise).  `regrown`: the pair buffers and
+// the scratch were reallocated after stage 1, so the pair sort's histograms
+// and the emission blocks' first entries are set up again.
+void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bool regrown, hipStream_t st);
 // Zero the screen-space gradient accumulators of the binned entries.
 void launch_zero_g2d(const SortBuffers& b, float* g2d, hipStream_t st);
 // sixdgs_bin's record import: (u, v, ex, ey, depth, alive) -> Rec + tiles.

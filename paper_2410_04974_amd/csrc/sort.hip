@@ -257,23 +257,30 @@ void scan1(F f, G g, const uint32_t* count_ptr, uint32_t fixed, uint32_t cap, in
                      ticket, status, total_out, ghist, err);
 }
 
-// Zeroes the first zero_words words of a radix state (and optionally the tile
-// ranges), and when given the
-// depth-sorted entries, records for every 4096-pair block the sorted entry
-// whose pairs contain the block's first pair.
-__global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, uint2* __restrict__ ranges, int64_t nranges,
+// Up to four word ranges a preparation kernel zeroes.
+struct ZeroList {
+  uint32_t* p[4];
+  int64_t n[4];
+};
+
+// Zeroes the first zero_words words of a radix state, the regions of z and
+// the tile ranges; when given the depth-sorted entries, records for every
+// 4096-pair block the sorted entry whose pairs contain the block's first pair
+// (normally the pair-offset scan records them; this is for pair buffers that
+// were regrown after it).
+__global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, int64_t zero_words, ZeroList z,
+                                                       uint2* __restrict__ ranges, int64_t nranges,
                                                        const uint32_t* __restrict__ counters,
                                                        const uint32_t* __restrict__ tiles,
                                                        const uint32_t* __restrict__ dval,
                                                        const uint32_t* __restrict__ poff, uint32_t pcap,
-                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start,
-                                                       uint32_t* __restrict__ extra, int64_t extra_words,
-                                                       int64_t zero_words) {
+                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t w4 = zero_words / 4;
-  if (i < w4) reinterpret_cast<uint4*>(rs.ghist)[i] = make_uint4(0u, 0u, 0u, 0u);
-  if (extra && i < extra_words) extra[i] = 0u;
-  if (ranges && i < nranges) ranges[i] = make_uint2(0u, 0u);
+  if (i < zero_words / 4) reinterpret_cast<uint4*>(rs.ghist)[i] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    if (z.p[k] && i < z.n[k]) z.p[k][i] = 0u;
+  if (ranges && i < nranges) ranges[i] = make_uint2(0xFFFFFFFFu, 0u);  // merged by min / max
   if (blk_start && i < (int64_t)counters[0] && counters[1] <= pcap) {
     const uint32_t o = poff[i];
     const uint32_t end = o + tiles[dval[i]];
@@ -503,7 +510,9 @@ __global__ void __launch_bounds__(kBlock) k_digit_scatter(const uint32_t* __rest
                                                           const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout, const uint32_t* count_ptr,
                                                           uint32_t cap, int shift, int dbits,
-                                                          const uint32_t* __restrict__ table, int64_t nblk) {
+                                                          const uint32_t* __restrict__ table, int64_t nblk,
+                                                          uint2* __restrict__ ranges, uint32_t total_tiles,
+                                                          const uint32_t* __restrict__ counters, uint32_t pcap) {
   constexpr int kChunkI = kBlock * ITEMS;
   __shared__ uint32_t s_key[kChunkI];
   __shared__ uint32_t s_val[kChunkI];
@@ -549,6 +558,13 @@ __global__ void __launch_bounds__(kBlock) k_digit_scatter(const uint32_t* __rest
   __syncthreads();
   const int64_t left = (int64_t)count - base;
   const int nvalid = left < kChunkI ? (int)left : kChunkI;
+  // the last pass also finds the tiles' ranges: the workgroup's digit runs
+  // are sorted by the whole key, so where the key changes inside a run is
+  // where the output changes key; a run's ends meet other workgroups' items,
+  // so every end is merged with a device min / max (ranges start at
+  // (UINT_MAX, 0); the tile order turns the untouched ones into (0, 0)).
+  // Skipped when the pairs overflowed: every range then stays empty.
+  const bool with_ranges = ranges && counters[1] <= pcap;
 #pragma unroll
   for (int r = 0; r < ITEMS; r++) {
     const int k = r * kBlock + t;
@@ -558,6 +574,10 @@ __global__ void __launch_bounds__(kBlock) k_digit_scatter(const uint32_t* __rest
       if (o < count) {  // always true for consistent tables; guards the buffers
         kout[o] = kk;
         vout[o] = s_val[k];
+        if (with_ranges && kk < total_tiles) {
+          if (k == 0 || s_key[k - 1] != kk) atomicMin(&ranges[kk].x, o);
+          if (k == nvalid - 1 || s_key[k + 1] != kk) atomicMax(&ranges[kk].y, o + 1u);
+        }
       }
     }
   }
@@ -604,9 +624,17 @@ struct SortedTiles {
   const uint32_t* dval;
   __device__ uint32_t operator()(int64_t i) const { return tiles[dval[i]]; }
 };
+// The pair offset of each depth-sorted entry, and for every 4096-pair
+// emission block that starts inside the entry's pairs, the entry.
 struct StoreOffset {
   uint32_t* poff;
-  __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { poff[i] = pre; }
+  uint32_t* blk_start;
+  int64_t nblk_start;
+  __device__ void operator()(int64_t i, uint32_t pre, uint32_t n) const {
+    poff[i] = pre;
+    for (int64_t b = ((int64_t)pre + kRChunk - 1) / kRChunk; b * kRChunk < (int64_t)pre + n && b < nblk_start; b++)
+      blk_start[b] = (uint32_t)i;
+  }
 };
 
 // Load-balanced pair emission: workgroup b writes pairs [4096 b, 4096 (b + 1))
@@ -687,28 +715,6 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
   if ((uint32_t)t <= mask) table0[(int64_t)t * gridDim.x + blockIdx.x] = s_h[0][t];
 }
 
-constexpr int kRangeItems = 8;  // consecutive pairs per thread
-
-__global__ void __launch_bounds__(kBlock) k_ranges(const uint32_t* __restrict__ pkey, const uint32_t* counters,
-                                                   uint32_t pcap, uint32_t total_tiles, uint2* __restrict__ ranges) {
-  const uint32_t P = counters[1];
-  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kRangeItems;
-  if (P > pcap || i0 >= P) return;  // on overflow the pair lists were not written: leave every range empty
-  uint32_t k[kRangeItems + 2];  // pairs i0 - 1 .. i0 + kRangeItems; past either end: no tile
-#pragma unroll
-  for (int j = 0; j < kRangeItems + 2; j++) {
-    const int64_t i = i0 - 1 + j;
-    k[j] = (i >= 0 && i < (int64_t)P) ? pkey[i] : 0xFFFFFFFFu;
-  }
-#pragma unroll
-  for (int j = 1; j <= kRangeItems; j++) {
-    const uint32_t key = k[j];
-    if (key >= total_tiles) continue;  // also the slots past P
-    if (k[j - 1] != key) ranges[key].x = (uint32_t)(i0 + j - 1);
-    if (k[j + 1] != key) ranges[key].y = (uint32_t)(i0 + j);
-  }
-}
-
 // Order in which the compositing kernels take the tiles: longest lists first
 // (buckets of log2 of the pair count, heaviest bucket first), so the tiles
 // whose per-pixel walks are longest start before the light ones and the
@@ -728,10 +734,17 @@ constexpr int kOrderStateWords = 2 * kOrderBuckets;          // bucket counts, t
 
 // the bucket of tile k (heaviest first: slot 0 holds 2^31 pairs and more, the
 // last slot the empty tiles), -1 past the last tile
-__device__ __forceinline__ int order_slot(const uint2* __restrict__ ranges, uint32_t total_tiles, uint32_t k) {
+// FIX: also turn a range the sort left untouched ((UINT_MAX, 0): a tile
+// without pairs) into (0, 0), the form every later reader expects.
+template <bool FIX>
+__device__ __forceinline__ int order_slot(uint2* __restrict__ ranges, uint32_t total_tiles, uint32_t k) {
   if (k >= total_tiles) return -1;
   const uint2 r = ranges[k];
-  const uint32_t c = r.y - r.x;
+  uint32_t c = r.y - r.x;
+  if (r.x >= r.y) {
+    c = 0;
+    if (FIX && (r.x | r.y)) ranges[k] = make_uint2(0u, 0u);
+  }
   return kOrderBuckets - 1 - (c ? 32 - __clz(c) : 0);
 }
 
@@ -778,7 +791,7 @@ __device__ __forceinline__ void scan_buckets(uint32_t* s) {
   }
 }
 
-__global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __restrict__ ranges, uint32_t total_tiles,
+__global__ void __launch_bounds__(kOrderThreads) k_tile_order(uint2* __restrict__ ranges, uint32_t total_tiles,
                                                               uint32_t* __restrict__ order,
                                                               const uint32_t* __restrict__ dval,
                                                               const uint32_t* __restrict__ counters,
@@ -795,7 +808,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __res
   for (uint32_t k0 = t; k0 < span; k0 += kOrderGroupTiles) {
     int b[kOrderU];
 #pragma unroll
-    for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+    for (int u = 0; u < kOrderU; u++) b[u] = order_slot<true>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
     for (int u = 0; u < kOrderU; u++) wave_add(b[u], s_h);
   }
@@ -805,7 +818,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __res
   for (uint32_t k0 = t; k0 < span; k0 += kOrderGroupTiles) {
     int b[kOrderU];
 #pragma unroll
-    for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+    for (int u = 0; u < kOrderU; u++) b[u] = order_slot<false>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
     for (int u = 0; u < kOrderU; u++) {
       const uint32_t pos = wave_add(b[u], s_h);
@@ -816,7 +829,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* __res
 
 // Many tiles, first half: bucket counts of kOrderGroupTiles tiles per
 // workgroup, added into state[0, kOrderBuckets) (zeroed beforehand).
-__global__ void __launch_bounds__(kOrderThreads) k_order_count(const uint2* __restrict__ ranges, uint32_t total_tiles,
+__global__ void __launch_bounds__(kOrderThreads) k_order_count(uint2* __restrict__ ranges, uint32_t total_tiles,
                                                                uint32_t ngroups, uint32_t* __restrict__ state,
                                                                const uint32_t* __restrict__ dval,
                                                                const uint32_t* __restrict__ counters,
@@ -832,7 +845,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_count(const uint2* __re
   const uint32_t k0 = blockIdx.x * kOrderGroupTiles + t;
   int b[kOrderU];
 #pragma unroll
-  for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+  for (int u = 0; u < kOrderU; u++) b[u] = order_slot<true>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
   for (int u = 0; u < kOrderU; u++) wave_add(b[u], s_h);
   __syncthreads();
@@ -842,7 +855,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_count(const uint2* __re
 // Second half: each workgroup ranks its tiles inside their buckets, reserves
 // a run of places per bucket (device atomics on state[kOrderBuckets + b]) and
 // writes the tiles there.
-__global__ void __launch_bounds__(kOrderThreads) k_order_place(const uint2* __restrict__ ranges, uint32_t total_tiles,
+__global__ void __launch_bounds__(kOrderThreads) k_order_place(uint2* __restrict__ ranges, uint32_t total_tiles,
                                                                uint32_t* __restrict__ state,
                                                                uint32_t* __restrict__ order) {
   __shared__ uint32_t s_off[kOrderBuckets];   // first place of each bucket
@@ -858,7 +871,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_place(const uint2* __re
   int b[kOrderU];
   uint32_t rank[kOrderU];
 #pragma unroll
-  for (int u = 0; u < kOrderU; u++) b[u] = order_slot(ranges, total_tiles, k0 + u * kOrderThreads);
+  for (int u = 0; u < kOrderU; u++) b[u] = order_slot<false>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
   for (int u = 0; u < kOrderU; u++) rank[u] = wave_add(b[u], s_loc);
   __syncthreads();
@@ -911,40 +924,46 @@ void launch_bin_count(SortBuffers& b, hipStream_t st) {
   // short sorts take small workgroups (more of them in flight); long ones the pairs' size
   const RadixState rs = radix_state(b.rstate_depth, b.E, b.E >= kLargeSort ? kRItems : kRItemsSmall, true);
   const RadixPlan plan{4, 8};
-  const unsigned gprep = (unsigned)((rs.words() / 4 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_stage_prep, dim3(gprep), dim3(kBlock), 0, st, rs, (uint2*)nullptr, (int64_t)0,
-                     (const uint32_t*)b.counters, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
-                     (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0, b.order_state,
-                     (int64_t)kOrderStateWords, rs.words());
+  // one preparation for the whole stage: the depth sort's state, the pair
+  // sort's histograms, the tile ranges, the tile order's counts and the
+  // backward work-item scan's state
+  const ZeroList z{{b.order_state, b.chunk_state, b.rstate_pairs, nullptr},
+                   {(int64_t)kOrderStateWords, chunk_scan_words(b.total_tiles), 2 * kMaxPasses * 256, 0}};
+  int64_t prep = rs.words() / 4;
+  for (int k = 0; k < 3; k++) prep = std::max(prep, z.n[k]);
+  prep = std::max(prep, b.total_tiles);
+  hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
+                     rs.words(), z, b.ranges, b.total_tiles, (const uint32_t*)b.counters, (const uint32_t*)nullptr,
+                     (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0);
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
   scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.depth, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
               rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
   // depth order (stable: equal depths keep entry order)
   b.dsorted = radix_sort(b.dkey, b.dval, &b.counters[0], b.E, plan, rs, &b.counters[3], st);
   // pair offsets in depth order
-  scan1<false>(SortedTiles{b.tiles, b.dval[b.dsorted]}, StoreOffset{b.poff}, &b.counters[0], 0u, E, b.E,
+  scan1<false>(SortedTiles{b.tiles, b.dval[b.dsorted]}, StoreOffset{b.poff, b.blk_start, b.nblk_start},
+               &b.counters[0], 0u, E, b.E,
                rs.tickets + kMaxPasses + 1, rs.scan_status + rs.nscan, &b.counters[1], (uint32_t*)nullptr,
                &b.counters[3], st);
 }
 
-void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hipStream_t st) {
+void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bool regrown, hipStream_t st) {
   int bits = 1;
   while ((1ll << bits) < (int64_t)vt.total_tiles) bits++;
   const RadixPlan plan = radix_plan(bits);
   const int64_t bound = pairs_hint < b.pcap ? pairs_hint : b.pcap;
   const RadixState rs = radix_state(b.rstate_pairs, bound, kRItems, false);
-  const int64_t cwords = chunk_scan_words(vt.total_tiles);
-  // the passes write every table entry they read: only the histograms (and
-  // the unused tickets) start from zero
-  const int64_t zero_words = 2 * kMaxPasses * 256;
-  int64_t prep = zero_words / 4;
-  if (prep < vt.total_tiles) prep = vt.total_tiles;
-  if (prep < b.E) prep = b.E;
-  if (prep < cwords) prep = cwords;
-  hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs, b.ranges,
-                     (int64_t)vt.total_tiles, (const uint32_t*)b.counters, (const uint32_t*)b.tiles,
-                     (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.poff, (uint32_t)b.pcap, b.blk_start,
-                     rs.nblk, b.chunk_state, cwords, zero_words);
+  if (regrown) {
+    // the passes write every table entry they read: only the histograms (and
+    // the unused tickets) start from zero
+    const int64_t zero_words = 2 * kMaxPasses * 256;
+    const ZeroList z{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}};
+    const int64_t prep = std::max<int64_t>(zero_words / 4, b.E);
+    hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
+                       zero_words, z, (uint2*)nullptr, (int64_t)0, (const uint32_t*)b.counters,
+                       (const uint32_t*)b.tiles, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.poff,
+                       (uint32_t)b.pcap, b.blk_start, rs.nblk);
+  }
   // the pairs, with every pass's digit histogram and the first pass's per-chunk
   // counts; then the passes, each a scan of the chunk counts and a scatter
   // (the chunk counts of later passes taken from their input)
@@ -963,29 +982,27 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, hi
                            (const uint32_t*)&b.counters[1], cap, shift, plan.dbits, table, nb);
       hipLaunchKernelGGL(k_digit_scan, dim3(1u << plan.dbits), dim3(kBlock), 0, st, table, nb,
                          (const uint32_t*)&b.counters[1], cap, kRChunk, (const uint32_t*)(rs.ghist + p * 256));
+      const bool last = p == plan.npass - 1;
       hipLaunchKernelGGL(k_digit_scatter<kRItems>, dim3((unsigned)nb), dim3(kBlock), 0, st, b.pkey[cur],
                          b.pval[cur], b.pkey[cur ^ 1], b.pval[cur ^ 1], (const uint32_t*)&b.counters[1], cap, shift,
-                         plan.dbits, (const uint32_t*)table, nb);
+                         plan.dbits, (const uint32_t*)table, nb, last ? b.ranges : nullptr,
+                         (uint32_t)vt.total_tiles, (const uint32_t*)b.counters, (uint32_t)b.pcap);
       cur ^= 1;
     }
   }
   b.psorted = cur;
-  const unsigned gp = (unsigned)((bound + (int64_t)kBlock * kRangeItems - 1) / ((int64_t)kBlock * kRangeItems));
-  if (gp)
-    hipLaunchKernelGGL(k_ranges, dim3(gp), dim3(kBlock), 0, st, b.pkey[b.psorted], b.counters, (uint32_t)b.pcap,
-                       (uint32_t)vt.total_tiles, b.ranges);
   // the tile order, and the gradient accumulators cleared for a backward
   const unsigned gz = b.g2d ? (unsigned)((b.E + kOrderThreads - 1) / kOrderThreads) : 0u;
   const uint32_t T = (uint32_t)vt.total_tiles;
   if (T <= kOrderOneGroup) {
     if (T > 0 || gz)
-      hipLaunchKernelGGL(k_tile_order, dim3(1 + gz), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges, T,
+      hipLaunchKernelGGL(k_tile_order, dim3(1 + gz), dim3(kOrderThreads), 0, st, b.ranges, T,
                          b.tile_order, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.counters, b.g2d);
   } else {
     const uint32_t ng = (T + kOrderGroupTiles - 1) / kOrderGroupTiles;
-    hipLaunchKernelGGL(k_order_count, dim3(ng + gz), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges, T, ng,
+    hipLaunchKernelGGL(k_order_count, dim3(ng + gz), dim3(kOrderThreads), 0, st, b.ranges, T, ng,
                        b.order_state, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.counters, b.g2d);
-    hipLaunchKernelGGL(k_order_place, dim3(ng), dim3(kOrderThreads), 0, st, (const uint2*)b.ranges, T,
+    hipLaunchKernelGGL(k_order_place, dim3(ng), dim3(kOrderThreads), 0, st, b.ranges, T,
                        b.order_state, b.tile_order);
   }
 }

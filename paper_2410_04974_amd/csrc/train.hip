@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_ssim_final(const float* __restrict__
   if (threadIdx.x == 0) *loss = (1.f - lam) * tl * inv_count + lam * (1.f - ts * inv_count);
 }
 
-// With a device step counter the bias corrections are formed on the device// With a device step counter the bias corrections are formed on the device
+// With a device step counter the bias corrections are formed on the device
 // from the step about to be taken (*step + 1), so a captured graph advances
 // the step on every replay; k_step_inc then moves the counter on.
 __device__ __forceinline__ void device_bias(AdamArgs& a, const int32_t* step_dev) {
