@@ -67,7 +67,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t& total)
 // word instead of spinning forever.
 constexpr int kRItems = 16;
 constexpr int kRChunk = kBlock * kRItems;  // items per workgroup and pass over the pairs
-constexpr int kRItemsSmall = 4;           // short depth sorts: 1024 items per workgroup, 4x the workgroups
+constexpr int kRItemsSmall = 8;           // short depth sorts: 2048 items per workgroup, 2x the workgroups
 constexpr int64_t kLargeSort = 1 << 20;    // from this many entries the depth sort uses kRItems
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStIncl = 2u << 30;
@@ -748,28 +748,6 @@ __device__ __forceinline__ int order_slot(uint2* __restrict__ ranges, uint32_t t
   return kOrderBuckets - 1 - (c ? 32 - __clz(c) : 0);
 }
 
-// Adds the lanes of each distinct slot b (>= 0) of the wavefront to h[b] with
-// one LDS atomic per slot (the lanes mostly agree, and same-address atomics
-// from the lanes of a wavefront would serialise); returns what the atomic
-// returned for this lane's slot plus the lane's rank among that slot's lanes.
-__device__ __forceinline__ uint32_t wave_add(int b, uint32_t* h) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint64_t todo = __ballot(b >= 0);
-  uint32_t mine = 0;
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int v = __shfl(b, leader, 64);
-    const uint64_t m = __ballot(b == v);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&h[v], (uint32_t)__popcll(m));
-    base = (uint32_t)__shfl((int)base, leader, 64);
-    if (b == v) mine = base + (uint32_t)__popcll(m & lt);
-    todo &= ~m;
-  }
-  return mine;
-}
-
 __device__ __forceinline__ void zero_g2d_rows(int64_t i, const uint32_t* __restrict__ dval,
                                               const uint32_t* __restrict__ counters, float* __restrict__ g2d) {
   if (i < counters[0]) {
@@ -810,7 +788,8 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(uint2* __restrict_
 #pragma unroll
     for (int u = 0; u < kOrderU; u++) b[u] = order_slot<true>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
-    for (int u = 0; u < kOrderU; u++) wave_add(b[u], s_h);
+    for (int u = 0; u < kOrderU; u++)
+      if (b[u] >= 0) atomicAdd(&s_h[b[u]], 1u);
   }
   __syncthreads();
   scan_buckets(s_h);
@@ -821,7 +800,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(uint2* __restrict_
     for (int u = 0; u < kOrderU; u++) b[u] = order_slot<false>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
     for (int u = 0; u < kOrderU; u++) {
-      const uint32_t pos = wave_add(b[u], s_h);
+      const uint32_t pos = b[u] >= 0 ? atomicAdd(&s_h[b[u]], 1u) : 0u;
       if (b[u] >= 0 && pos < total_tiles) order[pos] = k0 + u * kOrderThreads;
     }
   }
@@ -847,7 +826,8 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_count(uint2* __restrict
 #pragma unroll
   for (int u = 0; u < kOrderU; u++) b[u] = order_slot<true>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
-  for (int u = 0; u < kOrderU; u++) wave_add(b[u], s_h);
+  for (int u = 0; u < kOrderU; u++)
+    if (b[u] >= 0) atomicAdd(&s_h[b[u]], 1u);
   __syncthreads();
   if (t < kOrderBuckets && s_h[t]) atomicAdd(&state[t], s_h[t]);
 }
@@ -873,7 +853,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_place(uint2* __restrict
 #pragma unroll
   for (int u = 0; u < kOrderU; u++) b[u] = order_slot<false>(ranges, total_tiles, k0 + u * kOrderThreads);
 #pragma unroll
-  for (int u = 0; u < kOrderU; u++) rank[u] = wave_add(b[u], s_loc);
+  for (int u = 0; u < kOrderU; u++) rank[u] = b[u] >= 0 ? atomicAdd(&s_loc[b[u]], 1u) : 0u;
   __syncthreads();
   if (t < kOrderBuckets && s_loc[t]) s_loc[t] = atomicAdd(&state[kOrderBuckets + t], s_loc[t]);
   __syncthreads();
