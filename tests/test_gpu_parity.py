@@ -162,6 +162,36 @@ def test_binning_bit_exact_at_full_size(case):
         assert np.array_equal(r.ctx.export(_lib.EXPORT_RANGES), ref["ranges"].astype(np.int32))
 
 
+def test_pair_overflow_at_fixed_capacity_is_reported_and_renders_background():
+    """A fixed pair capacity below the pair count: nothing is binned, so the
+    forward renders the background alone (no pair list is read), check()
+    reports the capacity error once, and a context with room for the pairs
+    renders the image the growing mode renders."""
+    from paper_2410_04974_amd import SixDGSError, _lib
+    w, pn = G.scene("c1", 20000)
+    cam = synth.default_camera(160, 128)
+    p = G.to_dev(pn)
+    bg = (0.25, 0.5, 0.75)
+    grow = G.renderer(bg=bg)
+    ref = grow.forward(p, [cam])[0]
+    grow.ctx.check()
+    P = grow.ctx.sizes()["pairs"]
+    _say("pairs", P)
+    assert P > 1000
+    r = G.renderer(bg=bg, pair_capacity=P // 2)
+    img = r.forward(p, [cam])[0]
+    with pytest.raises(SixDGSError) as e:
+        r.ctx.check()
+    assert e.value.status == _lib.ERR_CAPACITY
+    r.ctx.check()  # reported once
+    want = torch.tensor(bg, device=G.DEV, dtype=torch.float32).view(3, 1, 1).expand_as(img)
+    assert torch.equal(img, want)
+    roomy = G.renderer(bg=bg, pair_capacity=P + 4096)
+    img2 = roomy.forward(p, [cam])[0]
+    roomy.ctx.check()
+    assert torch.equal(img2, ref)
+
+
 # ------------------------------------------------------------------ forward
 def _compare_pixels(img, T, ref_img, ref_T, amb, tag):
     ok = ~amb
