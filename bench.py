@@ -154,7 +154,7 @@ def main():
                                "800x800, L1 + Adam training step",
                    "gaussians": n, "width": cam.width, "height": cam.height, "views_per_step": 1,
                    "binned": nb, "pairs": P, "tiles": tiles, "tile": [r.ctx.settings.tile_w, r.ctx.settings.tile_h],
-                   "batch": r.ctx.settings.batch},
+                   "batch": sz["batch"], "chunk": sz["chunk"]},
         "train_steps_per_s": round(1e3 / ms_step, 2),
         "wall_s_timed": round(wall, 3),
         "kernel_ms": {_lib.KERNEL_NAMES[k]: round(v, 4) for k, v in kt.items()},
@@ -178,6 +178,8 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
     from paper_2410_04974_amd import _lib
 
     name = _lib.KERNEL_NAMES[dom]
+    sz = r.ctx.sizes()
+    settings = {"tile": [r.ctx.settings.tile_w, r.ctx.settings.tile_h], "batch": sz["batch"], "chunk": sz["chunk"]}
     if dom in (_lib.K_BLEND_FWD, _lib.K_BLEND_BWD):
         # count the contributing (pixel, Gaussian) pairs in one extra forward
         cnt_r = Renderer_with_counts(r)
@@ -186,7 +188,7 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
         per = FWD_FLOPS_PER_CONTRIB if dom == _lib.K_BLEND_FWD else BWD_FLOPS_PER_CONTRIB
         achieved = per * counts / (avg_ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic(name),
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic(name, settings),
                 "avg_ms": round(avg_ms, 4), "contributions_per_launch": counts, "flops_per_contribution": per}
     if dom == _lib.K_PREPROCESS:
         bytes_ = 304 * n + 4 * n + 52 * nb
@@ -196,7 +198,7 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
         bytes_ = 4 * n + 8 * nb * 2 * 4 + 8 * P * 2 * 2 + 8 * tiles
     achieved = bytes_ / (avg_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic(name), "avg_ms": round(avg_ms, 4)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic(name, settings), "avg_ms": round(avg_ms, 4)}
 
 
 def _timed(fn, steps):
@@ -229,7 +231,7 @@ def bench_c3(args):
     gen = torch.Generator(device="cuda:0").manual_seed(2)
     dls = [torch.randn((3, c.height, c.width), device="cuda:0", generator=gen) for c in cams]
 
-    rb = Renderer(tile=tune["tile"], batch=tune["batch"])
+    rb = Renderer(tile=tune["tile"], batch=tune["batch"], chunk=tune["chunk"])
     imgs = rb.forward(params, cams)
     torch.cuda.synchronize()
     pairs = rb.ctx.sizes()["pairs"]
@@ -251,7 +253,7 @@ def bench_c3(args):
     ms_batched = _timed(g.replay, args.steps)
     rb.ctx.check()
 
-    per = [Renderer(tile=tune["tile"], batch=tune["batch"]) for _ in cams]
+    per = [Renderer(tile=tune["tile"], batch=tune["batch"], chunk=tune["chunk"]) for _ in cams]
     gsum = torch.empty_like(params)
 
     def per_view():
@@ -270,7 +272,7 @@ def bench_c3(args):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "c3: 500k 6D Gaussians on a noisy sphere, 16 Fibonacci cameras cycling "
                                   "400x400, 800x800, 1280x720, 1600x900", "pixels": px, "pairs": pairs,
-                      "tile": list(tune["tile"]), "batch": tune["batch"]},
+                      "tile": list(tune["tile"]), "batch": tune["batch"], "chunk": tune["chunk"]},
            "per_view_launches": {"ms_per_step": round(ms_per_view, 4),
                                  "value": round(px / (ms_per_view * 1e-3) / 1e6, 3)},
            "speedup_vs_per_view": round(ms_per_view / ms_batched, 3),
@@ -382,9 +384,10 @@ def Renderer_with_counts(r):
                     batch=s.batch, flags=1)
 
 
-def traffic(kernel):
+def traffic(kernel, settings=None):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else null."""
+    taken on the current kernel sources with the same tile shape, batch depth
+    and backward chunk; else null."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -393,6 +396,8 @@ def traffic(kernel):
             t = json.load(f)
         e = t.get(kernel)
         if not e or e.get("source_digest") != source_digest(e.get("sources", [])):
+            return None
+        if settings is not None and e.get("settings") != settings:
             return None
         return e.get("bytes_per_launch")
     except Exception:

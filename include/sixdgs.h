@@ -75,7 +75,9 @@ typedef struct {
   float bg[3];         /* background colour */
   int32_t tile_w;      /* screen tile width in pixels: 8, 16 or 32 */
   int32_t tile_h;      /* screen tile height: tile_w * tile_h must be 256 */
-  int32_t batch;       /* Gaussians staged in LDS per backward batch: 64, 128 or 256 */
+  int32_t batch;       /* Gaussians staged in LDS per backward batch: 64, 128 or 256;
+                          0: automatic (128 below 16,384 tiles in the call's
+                          views, 256 from there on; never above the chunk) */
   int64_t pair_capacity; /* 0: grow the (tile, Gaussian) pair buffers on demand
                             (sixdgs_forward then waits once on the stream to
                             read the pair count); > 0: fixed capacity, no host
@@ -86,7 +88,9 @@ typedef struct {
   int32_t chunk;       /* list positions per backward work item: the backward
                           walks each tile's list in chunks of this length in
                           parallel, restarting from state the forward saves at
-                          chunk starts.  A power of two, >= batch, <= 16384. */
+                          chunk starts.  A power of two, >= batch (and 64),
+                          <= 16384; 0: automatic (128 below 16,384 tiles,
+                          512 from there on). */
 } sixdgs_settings;
 
 #define SIXDGS_FLAG_COUNTS 1 /* forward also stores per-pixel contributor counts (debug export) */
@@ -97,7 +101,7 @@ typedef struct {
 #define SIXDGS_FLAG_RGB_COLOR 2
 
 /* Fills `s` with the defaults: lambda 0.35, z_near 0.2, bg 0, 16x16 tiles,
- * batch 256, pair_capacity 0, flags 0, chunk 256. */
+ * batch 0 (automatic), pair_capacity 0, flags 0, chunk 0 (automatic). */
 void sixdgs_default_settings(sixdgs_settings* s);
 
 /* Creates a context on the current HIP device.  It owns all scratch memory
@@ -289,7 +293,8 @@ sixdgs_status sixdgs_bin(sixdgs_ctx* ctx, int64_t n, const sixdgs_camera* cams, 
  *   LAST         int32  [sum H*W]: 1 + position (within its tile's range) of the
  *                last contributor, 0 if none
  *   COUNTS       int32  [sum H*W]: contributors per pixel (SIXDGS_FLAG_COUNTS)
- *   SIZES        int64  [5]: E, P, T, number of binned entries, pixels */
+ *   SIZES        int64  [7]: E, P, T, number of binned entries, pixels, and
+ *                the backward batch depth and chunk the last forward chose */
 #define SIXDGS_EXPORT_RECORDS 0
 #define SIXDGS_EXPORT_TILES 1
 #define SIXDGS_EXPORT_KEYS 2

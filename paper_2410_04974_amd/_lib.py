@@ -329,11 +329,11 @@ class Context:
 
     # -- read-back (synchronous) ----------------------------------------------------
     def sizes(self):
-        out = np.zeros(5, np.int64)
+        out = np.zeros(7, np.int64)
         w = ctypes.c_int64()
-        self._rc(lib().sixdgs_export(self._h, EXPORT_SIZES, out.ctypes.data_as(ctypes.c_void_p), 40, ctypes.byref(w)))
+        self._rc(lib().sixdgs_export(self._h, EXPORT_SIZES, out.ctypes.data_as(ctypes.c_void_p), 56, ctypes.byref(w)))
         return {"entries": int(out[0]), "pairs": int(out[1]), "tiles": int(out[2]), "binned": int(out[3]),
-                "pixels": int(out[4])}
+                "pixels": int(out[4]), "batch": int(out[5]), "chunk": int(out[6])}
 
     def export(self, what):
         sz = self.sizes()

@@ -1,8 +1,11 @@
-"""Tile shape and LDS batch-depth autotuner.
+"""Tile shape, LDS batch-depth and backward-chunk autotuner.
 
-The image does not depend on either setting (the per-pixel arithmetic and the
-per-pixel Gaussian order are the same for every tile shape), so the tuner is
-free to pick the fastest.  It times a forward + backward of the caller's own
+The image does not depend on any of them (the per-pixel arithmetic and the
+per-pixel Gaussian order are the same for every tile shape; the backward's
+chunk only changes where its walks restart), so the tuner is free to pick the
+fastest.  Short chunks spread the heavy tiles of a small frame over more
+workgroups; with tens of thousands of tiles there is parallelism enough, and
+longer chunks save the restarts.  It times a forward + backward of the caller's own
 workload for each candidate on the current stream with HIP events, and caches
 the winner in a JSON file keyed by device and workload shape.
 """
@@ -15,7 +18,9 @@ import torch
 
 from .render import Renderer
 
-CANDIDATES = [((16, 16), 256), ((16, 16), 128), ((32, 8), 256), ((32, 8), 128), ((8, 32), 256), ((8, 32), 128)]
+# (tile, LDS batch depth, backward chunk); a batch longer than the chunk is cut to it
+CANDIDATES = [(tile, batch, chunk) for tile in ((16, 16), (32, 8), (8, 32))
+              for batch, chunk in ((256, 512), (256, 256), (128, 128), (64, 64))]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sixdgs_autotune.json")
 
 
@@ -24,8 +29,8 @@ def _key(n, cams):
     return f"{dev}|n={n}|views=" + ",".join(f"{c.width}x{c.height}" for c in cams)
 
 
-def _time_config(params, cams, dls, tile, batch, iters):
-    r = Renderer(tile=tile, batch=batch)
+def _time_config(params, cams, dls, tile, batch, chunk, iters):
+    r = Renderer(tile=tile, batch=batch, chunk=chunk)
     r.forward(params, cams)
     torch.cuda.synchronize()
     r.configure(pair_capacity=int(r.ctx.sizes()["pairs"] * 1.3) + 4096)
@@ -46,14 +51,14 @@ def _time_config(params, cams, dls, tile, batch, iters):
 
 
 def autotune(params, cams, candidates=CANDIDATES, iters=5, cache=DEFAULT_CACHE, use_cache=True):
-    """Returns {"tile": (w, h), "batch": b, "ms": t, "timings": {...}} for the
-    fastest forward + backward of ``params`` over ``cams``."""
+    """Returns {"tile": (w, h), "batch": b, "chunk": c, "ms": t, "timings": {...}}
+    for the fastest forward + backward of ``params`` over ``cams``."""
     key = _key(params.shape[1], cams)
     if use_cache and cache and os.path.exists(cache):
         try:
             with open(cache) as f:
                 hit = json.load(f).get(key)
-            if hit:
+            if hit and "chunk" in hit:
                 hit["tile"] = tuple(hit["tile"])
                 return hit
         except (OSError, ValueError):
@@ -61,12 +66,12 @@ def autotune(params, cams, candidates=CANDIDATES, iters=5, cache=DEFAULT_CACHE, 
     gen = torch.Generator(device=params.device).manual_seed(0)
     dls = [torch.randn((3, c.height, c.width), device=params.device, generator=gen) for c in cams]
     timings = {}
-    for tile, batch in candidates:
-        timings[f"{tile[0]}x{tile[1]}/{batch}"] = _time_config(params, cams, dls, tile, batch, iters)
+    for tile, batch, chunk in candidates:
+        timings[f"{tile[0]}x{tile[1]}/{batch}/{chunk}"] = _time_config(params, cams, dls, tile, batch, chunk, iters)
     best = min(timings, key=timings.get)
     tw, rest = best.split("x")
-    th, b = rest.split("/")
-    res = {"tile": (int(tw), int(th)), "batch": int(b), "ms": timings[best], "timings": timings}
+    th, b, c = rest.split("/")
+    res = {"tile": (int(tw), int(th)), "batch": int(b), "chunk": int(c), "ms": timings[best], "timings": timings}
     if cache:
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -66,6 +66,7 @@ struct sixdgs_ctx {
   DevBuf<uint2> items;
   int64_t bwd_grid = 0;
   int32_t fwd_chunk = 256;   // chunk length the last forward saved its boundary state for
+  int32_t fwd_batch = 256;   // LDS batch depth of the last forward's backward
   // learnable per-Gaussian lambda (caller-owned device arrays, sixdgs_set_lambda)
   const float* lambda_raw = nullptr;
   float* grad_lambda = nullptr;
@@ -124,14 +125,14 @@ bool valid_settings(const sixdgs_settings* s, std::string& why) {
     why = "tile shape must be 8x32, 16x16 or 32x8";
     return false;
   }
-  if (!(s->batch == 64 || s->batch == 128 || s->batch == 256)) {
-    why = "batch must be 64, 128 or 256";
+  if (!(s->batch == 0 || s->batch == 64 || s->batch == 128 || s->batch == 256)) {
+    why = "batch must be 0 (automatic), 64, 128 or 256";
     return false;
   }
   if (s->pair_capacity < 0 || s->pair_capacity > kMaxItems) { why = "pair_capacity out of range"; return false; }
   if (s->flags & ~(SIXDGS_FLAG_COUNTS | SIXDGS_FLAG_RGB_COLOR)) { why = "unknown flag bits"; return false; }
-  if (s->chunk < s->batch || s->chunk > 16384 || (s->chunk & (s->chunk - 1)) != 0) {
-    why = "chunk must be a power of two between batch and 16384";
+  if (s->chunk != 0 && (s->chunk < std::max(s->batch, 64) || s->chunk > 16384 || (s->chunk & (s->chunk - 1)) != 0)) {
+    why = "chunk must be 0 (automatic) or a power of two between batch (64 at least) and 16384";
     return false;
   }
   return true;
@@ -204,6 +205,10 @@ DevSettings dev_settings(const sixdgs_settings& s) {
   d.grad_lambda = nullptr;
   return d;
 }
+
+// from this many tiles on, the automatic backward chunk and batch depth are
+// the long ones
+constexpr int64_t kAutoTiles = 16384;
 
 bool ensure_entries(sixdgs_ctx* c, int64_t E) {
   const int64_t e1 = E > 0 ? E : 1;
@@ -369,10 +374,10 @@ void sixdgs_default_settings(sixdgs_settings* s) {
   s->z_near = 0.2f;
   s->tile_w = 16;
   s->tile_h = 16;
-  s->batch = 256;
+  s->batch = 0;  // automatic
   s->pair_capacity = 0;
   s->flags = 0;
-  s->chunk = 256;
+  s->chunk = 0;  // automatic
 }
 
 sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s) {
@@ -499,19 +504,31 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
   c->bin_g2d = nullptr;
   if (rc != SIXDGS_OK) return rc;
   c->g2d_clean = !inference;
+  // the backward's chunk and LDS batch depth: with few tiles, short chunks
+  // spread the heavy tiles' walks over many workgroups; with many tiles
+  // (several large views) there is parallelism enough and longer chunks save
+  // the restarts (measured: 128 / 128 best for one 800x800 view, 256 / 512
+  // for eight or sixteen 1080p-class views)
+  {
+    const bool few = vt.total_tiles < kAutoTiles;
+    int chunk = c->s.chunk ? c->s.chunk : (few ? 128 : 512);
+    int batch = c->s.batch ? c->s.batch : (few ? 128 : 256);
+    if (batch > chunk) batch = chunk;
+    c->fwd_chunk = chunk;
+    c->fwd_batch = batch;
+  }
   // the backward's work items: at most one per `chunk` pairs plus one per tile
-  const int64_t nbound = c->sb.pcap / c->s.chunk + 1;
+  const int64_t nbound = c->sb.pcap / c->fwd_chunk + 1;
   const int64_t grid = nbound + vt.total_tiles;
   if (!c->bound.ensure(nbound * kBlock) ||
       !c->tile_nch.ensure(std::max<int64_t>(vt.total_tiles, 1)) || !c->items.ensure(grid))
     return fail(c, SIXDGS_ERR_OOM, "backward work items");
   c->bwd_grid = grid;
-  c->fwd_chunk = c->s.chunk;
   BlendState bs = blend_state(c);
   bs.counts = want_counts ? c->counts.p : nullptr;
   {
     Timer t(c, SIXDGS_K_BLEND_FWD, st);
-    launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->s.batch, !inference, st);
+    launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->fwd_batch, !inference, st);
   }
   if (inference) return check_launch(c, "blend forward");
   launch_chunk_items(c->tile_nch.p, c->tile_order.p, vt.total_tiles, c->items.p, grid, c->chunk_state.p,
@@ -576,7 +593,7 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, con
   const BlendState bs = blend_state(c);
   {
     Timer t(c, SIXDGS_K_BLEND_BWD, st);
-    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch,
+    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->fwd_batch,
                      c->bwd_grid, st);
   }
   sixdgs_status rc = check_launch(c, "blend backward");
@@ -615,7 +632,7 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, cons
   const BlendState bs = blend_state(c);
   {
     Timer t(c, SIXDGS_K_BLEND_BWD, st);
-    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->s.batch,
+    launch_blend_bwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->g2d.p, c->fwd_batch,
                      c->bwd_grid, st);
   }
   sixdgs_status rc = check_launch(c, "blend backward");
@@ -823,14 +840,16 @@ sixdgs_status sixdgs_export(sixdgs_ctx* c, int32_t what, void* dst, int64_t cap_
       return SIXDGS_OK;
     }
     case SIXDGS_EXPORT_SIZES: {
-      if (cap_bytes < 40) return fail(c, SIXDGS_ERR_INVALID_ARG, "destination too small");
+      if (cap_bytes < 56) return fail(c, SIXDGS_ERR_INVALID_ARG, "destination too small");
       int64_t* o = (int64_t*)dst;
       o[0] = E;
       o[1] = cnt[1];
       o[2] = T;
       o[3] = cnt[0];
       o[4] = c->fwd_px;
-      *written = 40;
+      o[5] = c->fwd_batch;
+      o[6] = c->fwd_chunk;
+      *written = 56;
       return SIXDGS_OK;
     }
     default: return fail(c, SIXDGS_ERR_INVALID_ARG, "unknown export item");

@@ -19,10 +19,12 @@ class Renderer:
     """Owns a library context (workspace, autotuned settings, the saved state
     of the last forward)."""
 
-    def __init__(self, lambda_opa=0.35, z_near=0.2, bg=(0.0, 0.0, 0.0), tile=(16, 16), batch=256,
-                 pair_capacity=0, flags=0, chunk=256, rgb_color=False):
+    def __init__(self, lambda_opa=0.35, z_near=0.2, bg=(0.0, 0.0, 0.0), tile=(16, 16), batch=0,
+                 pair_capacity=0, flags=0, chunk=0, rgb_color=False):
         """rgb_color=True selects the No-SH colour: sigmoid of a per-Gaussian RGB
-        held in the SH degree-0 rows (the other SH rows are ignored)."""
+        held in the SH degree-0 rows (the other SH rows are ignored).  batch /
+        chunk 0: the library picks the backward's batch depth and chunk from
+        the tile count of each call (``ctx.sizes()`` reports the choice)."""
         if rgb_color:
             flags |= _lib.FLAG_RGB_COLOR
         self.ctx = _lib.Context(lambda_opa=lambda_opa, z_near=z_near, bg=bg, tile_w=tile[0], tile_h=tile[1],

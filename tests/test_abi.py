@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_settings_on_host():
     s = _lib.default_settings()
     assert abs(s.lambda_opa - 0.35) < 1e-7 and abs(s.z_near - 0.2) < 1e-7
-    assert (s.tile_w, s.tile_h, s.batch, s.pair_capacity, s.chunk) == (16, 16, 256, 0, 256)
+    assert (s.tile_w, s.tile_h, s.batch, s.pair_capacity, s.chunk) == (16, 16, 0, 0, 0)  # 0: automatic
 
 
 def test_adam_rejects_bad_arguments_before_any_launch():
@@ -47,8 +47,8 @@ def test_create_rejects_unsupported_settings():
     L = _lib.lib()
     h = ctypes.c_void_p()
     for kw in ({"tile_w": 16, "tile_h": 8}, {"batch": 100}, {"batch": 32}, {"lambda_opa": 1.5}, {"z_near": 0.0},
-               {"pair_capacity": -1}, {"tile_w": 32, "tile_h": 16}, {"pair_capacity": 1 << 30}, {"chunk": 128},
-               {"chunk": 1536}, {"chunk": 32768}):
+               {"pair_capacity": -1}, {"tile_w": 32, "tile_h": 16}, {"pair_capacity": 1 << 30},
+               {"batch": 256, "chunk": 128}, {"chunk": 32}, {"chunk": 1536}, {"chunk": 32768}, {"batch": -1}):
         s = _lib.default_settings(**kw)
         assert L.sixdgs_create(ctypes.byref(h), ctypes.byref(s)) == _lib.ERR_INVALID_ARG
         assert not h.value

@@ -286,8 +286,8 @@ def test_backward_chunk_lengths_agree(batch):
     """The backward walks each tile's list in work items of `chunk` positions,
     restarted from state the forward saved; any chunk length gives the same
     gradient up to float32 rounding (c1 at full size: heavy tiles span many
-    chunks).  The default chunk is also the one the oracle comparisons and
-    the finite-difference check use."""
+    chunks).  The oracle comparisons and the finite-difference check use the
+    automatic chunk (128 at their sizes)."""
     w, pn = G.scene("c1")
     cam = w.cameras[0]
     dl = torch.from_numpy(synth.upstream_gradient([cam])[0]).to(G.DEV)
