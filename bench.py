@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=8192)
+    ap.add_argument("--cpu-pixels", type=int, default=32768)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a kernel of known traffic that "
                          "scales the HBM byte counters of a profiler run)")
