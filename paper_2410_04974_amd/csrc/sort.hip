@@ -1038,9 +1038,12 @@ namespace {
 // threads: each thread takes a run of consecutive positions of the order,
 // a block scan gives the runs' item offsets, and each thread writes its items.
 // (A single launch with no look-back: the scan sits between the two
-// compositing kernels, so its latency is on the step's critical path.)
+// compositing kernels, so its latency is on the step's critical path.  Past
+// a few thousand tiles the serial runs per thread cost more than the
+// look-back of the many-workgroup scan: 213 us for 65k tiles in one
+// workgroup.)
 constexpr int kOneGroupThreads = 1024;
-constexpr int64_t kOneGroupTiles = 1 << 17;
+constexpr int64_t kOneGroupTiles = 1 << 13;
 __global__ void __launch_bounds__(kOneGroupThreads) k_chunk_items(const uint32_t* __restrict__ nch,
                                                                   const uint32_t* __restrict__ order, uint32_t T,
                                                                   uint2* __restrict__ items, uint32_t cap,
