@@ -22,18 +22,32 @@ __device__ __forceinline__ float block_sum(float v) {
   return t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_l1(const float* __restrict__ img, const float* __restrict__ tgt,
-                                               float* __restrict__ dimg, int64_t numel, float inv_count,
-                                               float* __restrict__ partial) {
+// The images of one call, one grid row (blockIdx.y) each.
+struct L1Images {
+  const float* img[kMaxViews];
+  const float* tgt[kMaxViews];
+  float* dimg[kMaxViews];
+  int64_t numel[kMaxViews];
+  int64_t off[kMaxViews];  // first partial sum of each image
+  int32_t nb[kMaxViews];   // blocks of each image
+};
+
+__global__ void __launch_bounds__(kBlock) k_l1(L1Images im, float inv_count, float* __restrict__ partial) {
+  const int k = blockIdx.y;
+  if ((int)blockIdx.x >= im.nb[k]) return;  // uniform: a smaller image needs fewer blocks
+  const float* __restrict__ img = im.img[k];
+  const float* __restrict__ tgt = im.tgt[k];
+  float* __restrict__ dimg = im.dimg[k];
+  const int64_t numel = im.numel[k];
   float acc = 0.f;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t stride = (int64_t)im.nb[k] * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < numel; i += stride) {
     const float d = img[i] - tgt[i];
     acc += fabsf(d);
     dimg[i] = (d > 0.f) ? inv_count : ((d < 0.f) ? -inv_count : 0.f);
   }
   const float t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[im.off[k] + blockIdx.x] = t;
 }
 
 __global__ void __launch_bounds__(kBlock) k_l1_final(const float* __restrict__ partial, int64_t count,
@@ -266,13 +280,24 @@ void launch_l1(int nimg, const float* const* img, const float* const* tgt, const
   int64_t total = 0;
   for (int k = 0; k < nimg; k++) total += numel[k];
   const float inv = 1.0f / (float)total;
+  // all images in one launch (one grid row each), then the sum of the partials
+  L1Images im{};
   int64_t off = 0;
-  for (int k = 0; k < nimg; k++) {
+  int nbmax = 1, n = 0;
+  for (int k = 0; k < nimg && k < kMaxViews; k++) {
     const int nb = l1_blocks(numel[k]);
     if (off + nb > partial_cap) break;
-    hipLaunchKernelGGL(k_l1, dim3(nb), dim3(kBlock), 0, st, img[k], tgt[k], dimg[k], numel[k], inv, partial + off);
+    im.img[k] = img[k];
+    im.tgt[k] = tgt[k];
+    im.dimg[k] = dimg[k];
+    im.numel[k] = numel[k];
+    im.off[k] = off;
+    im.nb[k] = nb;
+    nbmax = nb > nbmax ? nb : nbmax;
     off += nb;
+    n = k + 1;
   }
+  if (n > 0) hipLaunchKernelGGL(k_l1, dim3(nbmax, n), dim3(kBlock), 0, st, im, inv, partial);
   hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, off, inv, loss);
 }
 

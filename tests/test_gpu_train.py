@@ -14,21 +14,26 @@ LR = (1.6e-4, 1e-3, 1e-2, 2.5e-3, 1.25e-4, 5e-2)
 
 
 def test_l1_loss_and_gradient_match_oracle():
+    """Images of different sizes in one call (one grid row each, the large
+    one capped at its block count and strided), then two small ones again."""
     rng = np.random.default_rng(4)
-    shapes = [(3, 37, 53), (3, 64, 64)]
+    shapes = [(3, 37, 53), (3, 64, 64), (3, 720, 1280)]
     imgs = [rng.random(s).astype(np.float32) for s in shapes]
     tgts = [rng.random(s).astype(np.float32) for s in shapes]
     tgts[1][0, :3, :3] = imgs[1][0, :3, :3]  # exact ties: zero gradient
     r = G.renderer()
-    di = [torch.from_numpy(a).to(G.DEV) for a in imgs]
-    dt = [torch.from_numpy(a).to(G.DEV) for a in tgts]
-    dl = [torch.empty_like(a) for a in di]
-    loss = torch.zeros(1, device=G.DEV)
-    r.ctx.l1_loss(di, dt, dl, loss)
-    ref_loss, ref_grads = oracle.l1_loss(imgs, tgts)
-    assert abs(float(loss) - ref_loss) <= 1e-6 * ref_loss
-    for g, rg in zip(dl, ref_grads):
-        assert np.allclose(g.cpu().numpy(), rg, rtol=1e-6, atol=0)
+    for sel in ([0, 2, 1], [0, 1]):
+        im = [imgs[k] for k in sel]
+        tg = [tgts[k] for k in sel]
+        di = [torch.from_numpy(a).to(G.DEV) for a in im]
+        dt = [torch.from_numpy(a).to(G.DEV) for a in tg]
+        dl = [torch.empty_like(a) for a in di]
+        loss = torch.zeros(1, device=G.DEV)
+        r.ctx.l1_loss(di, dt, dl, loss)
+        ref_loss, ref_grads = oracle.l1_loss(im, tg)
+        assert abs(float(loss) - ref_loss) <= 1e-6 * ref_loss, sel
+        for g, rg in zip(dl, ref_grads):
+            assert np.allclose(g.cpu().numpy(), rg, rtol=1e-6, atol=0)
 
 
 @pytest.mark.parametrize("n", [1000, 1001])  # float4 and scalar kernels
