@@ -201,8 +201,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // SAVE = false renders the image only (inference): no chunk boundaries, no
 // final transmittance, last contributor or chunk counts for a backward.
+// Five wavefronts per SIMD (96 registers, no spills): with tens of thousands
+// of tiles the walks' load latency is hidden by the extra wave (c4's forward
+// 1.87 -> 1.72 ms).
 template <int TW, bool SAVE>
-__global__ void __launch_bounds__(kBlock) k_blend_fwd(ViewTable vt, DevSettings ds, const Rec* __restrict__ rec,
+__global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettings ds, const Rec* __restrict__ rec,
                                                       const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ pval, BlendState bs) {
   __shared__ FwdWaveLDS W[kWaves];
