@@ -141,7 +141,7 @@ __device__ __forceinline__ void st_store64(uint64_t* p, uint64_t v) {
 // prefix through it).  A window of predecessors is read per round trip and
 // summed nearest first until an inclusive word; a word not yet published is
 // waited on, boundedly (a timeout sets *err and gives up).
-constexpr int kLookWin = 8;
+constexpr int kLookWin = 4;
 
 __device__ __forceinline__ bool lb_incl(uint32_t s) { return (s & kStIncl) != 0; }
 __device__ __forceinline__ uint32_t lb_val(uint32_t s) { return s & kStVal; }
