@@ -281,14 +281,15 @@ def test_backward_matches_oracle_gradient(name, n, size):
     assert all(v < 1e-3 for v in errs.values())
 
 
-@pytest.mark.parametrize("batch", [256, 64])
-def test_backward_chunk_lengths_agree(batch):
+@pytest.mark.parametrize("name,batch", [("c1", 256), ("c1", 64), ("c1", 0), ("c2", 0)])
+def test_backward_chunk_lengths_agree(name, batch):
     """The backward walks each tile's list in work items of `chunk` positions,
     restarted from state the forward saved; any chunk length gives the same
-    gradient up to float32 rounding (c1 at full size: heavy tiles span many
-    chunks).  The oracle comparisons and the finite-difference check use the
-    automatic chunk (128 at their sizes)."""
-    w, pn = G.scene("c1")
+    gradient up to float32 rounding (c1 and c2 at full size: heavy tiles span
+    many chunks).  batch 0: the automatic batch depth and chunk (128 / 128
+    here), the configuration the training-step benchmark times; the oracle
+    comparisons and the finite-difference check use it too."""
+    w, pn = G.scene(name)
     cam = w.cameras[0]
     dl = torch.from_numpy(synth.upstream_gradient([cam])[0]).to(G.DEV)
     p = G.to_dev(pn)
