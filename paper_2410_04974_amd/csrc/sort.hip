@@ -748,10 +748,14 @@ __device__ __forceinline__ int order_slot(uint2* __restrict__ ranges, uint32_t t
   return kOrderBuckets - 1 - (c ? 32 - __clz(c) : 0);
 }
 
-__device__ __forceinline__ void zero_g2d_rows(int64_t i, const uint32_t* __restrict__ dval,
-                                              const uint32_t* __restrict__ counters, float* __restrict__ g2d) {
-  if (i < counters[0]) {
-    float* p = g2d + (int64_t)dval[i] * kG2D;
+// Zeroes the gradient-accumulator row of entry i if it is binned (a tile
+// count above zero).  Taken in entry order, consecutive threads write
+// consecutive rows (the binned entries in depth order would scatter them),
+// and the unbinned ones cost a 4-byte read.
+__device__ __forceinline__ void zero_g2d_entry(int64_t i, const uint32_t* __restrict__ tiles, int64_t E,
+                                               float* __restrict__ g2d) {
+  if (i < E && tiles[i] > 0) {
+    float* p = g2d + i * kG2D;
 #pragma unroll
     for (int k = 0; k < kG2D; k++) p[k] = 0.f;
   }
@@ -771,13 +775,12 @@ __device__ __forceinline__ void scan_buckets(uint32_t* s) {
 
 __global__ void __launch_bounds__(kOrderThreads) k_tile_order(uint2* __restrict__ ranges, uint32_t total_tiles,
                                                               uint32_t* __restrict__ order,
-                                                              const uint32_t* __restrict__ dval,
-                                                              const uint32_t* __restrict__ counters,
+                                                              const uint32_t* __restrict__ tiles, int64_t E,
                                                               float* __restrict__ g2d) {
   __shared__ uint32_t s_h[kOrderBuckets];
   const int t = threadIdx.x;
   if (blockIdx.x > 0) {
-    zero_g2d_rows((int64_t)(blockIdx.x - 1) * kOrderThreads + t, dval, counters, g2d);
+    zero_g2d_entry((int64_t)(blockIdx.x - 1) * kOrderThreads + t, tiles, E, g2d);
     return;
   }
   if (t < kOrderBuckets) s_h[t] = 0;
@@ -810,13 +813,12 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(uint2* __restrict_
 // workgroup, added into state[0, kOrderBuckets) (zeroed beforehand).
 __global__ void __launch_bounds__(kOrderThreads) k_order_count(uint2* __restrict__ ranges, uint32_t total_tiles,
                                                                uint32_t ngroups, uint32_t* __restrict__ state,
-                                                               const uint32_t* __restrict__ dval,
-                                                               const uint32_t* __restrict__ counters,
+                                                               const uint32_t* __restrict__ tiles, int64_t E,
                                                                float* __restrict__ g2d) {
   __shared__ uint32_t s_h[kOrderBuckets];
   const int t = threadIdx.x;
   if (blockIdx.x >= ngroups) {
-    zero_g2d_rows((int64_t)(blockIdx.x - ngroups) * kOrderThreads + t, dval, counters, g2d);
+    zero_g2d_entry((int64_t)(blockIdx.x - ngroups) * kOrderThreads + t, tiles, E, g2d);
     return;
   }
   if (t < kOrderBuckets) s_h[t] = 0;
@@ -977,11 +979,11 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bo
   if (T <= kOrderOneGroup) {
     if (T > 0 || gz)
       hipLaunchKernelGGL(k_tile_order, dim3(1 + gz), dim3(kOrderThreads), 0, st, b.ranges, T,
-                         b.tile_order, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.counters, b.g2d);
+                         b.tile_order, (const uint32_t*)b.tiles, b.E, b.g2d);
   } else {
     const uint32_t ng = (T + kOrderGroupTiles - 1) / kOrderGroupTiles;
     hipLaunchKernelGGL(k_order_count, dim3(ng + gz), dim3(kOrderThreads), 0, st, b.ranges, T, ng,
-                       b.order_state, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.counters, b.g2d);
+                       b.order_state, (const uint32_t*)b.tiles, b.E, b.g2d);
     hipLaunchKernelGGL(k_order_place, dim3(ng), dim3(kOrderThreads), 0, st, b.ranges, T,
                        b.order_state, b.tile_order);
   }
