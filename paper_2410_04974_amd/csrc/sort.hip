@@ -867,13 +867,9 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_place(uint2* __restrict
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_zero_g2d(const uint32_t* __restrict__ dval, const uint32_t* counters,
+__global__ void __launch_bounds__(kBlock) k_zero_g2d(const uint32_t* __restrict__ tiles, int64_t E,
                                                      float* __restrict__ g2d) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= counters[0]) return;
-  float* p = g2d + (int64_t)dval[i] * kG2D;
-#pragma unroll
-  for (int k = 0; k < kG2D; k++) p[k] = 0.f;
+  zero_g2d_entry((int64_t)blockIdx.x * kBlock + threadIdx.x, tiles, E, g2d);
 }
 
 __global__ void __launch_bounds__(kBlock) k_import(const float* __restrict__ u, const float* __restrict__ v,
@@ -1095,7 +1091,7 @@ int64_t order_state_words() { return kOrderStateWords; }
 
 void launch_zero_g2d(const SortBuffers& b, float* g2d, hipStream_t st) {
   const unsigned g = (unsigned)((b.E + kBlock - 1) / kBlock);
-  if (g) hipLaunchKernelGGL(k_zero_g2d, dim3(g), dim3(kBlock), 0, st, b.dval[b.dsorted], b.counters, g2d);
+  if (g) hipLaunchKernelGGL(k_zero_g2d, dim3(g), dim3(kBlock), 0, st, (const uint32_t*)b.tiles, b.E, g2d);
 }
 
 void launch_import_records(const float* u, const float* v, const float* ex, const float* ey, const float* depth,
