@@ -702,7 +702,20 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
       const uint32_t key = s_base[j] + ty * s_ntx[j] + (local - ty * w);
       pkey[q] = key;
       pval[q] = s_e[j];
-      for (int p = 0; p < npass; p++) atomicAdd(&s_h[p][(key >> (p * dbits)) & mask], 1u);
+      // Lanes whose digit equals the first active lane's add as one: the
+      // tiles of one wide Gaussian share their high digits, and same-address
+      // shared-memory atomics from one wavefront serialise.
+      const uint64_t act = __ballot(1);
+      const bool leader = __lane_id() == (unsigned)(__ffsll((unsigned long long)act) - 1);
+      for (int p = 0; p < npass; p++) {
+        const uint32_t d = (key >> (p * dbits)) & mask;
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const uint64_t same = __ballot(d == d0);
+        if (d != d0)
+          atomicAdd(&s_h[p][d], 1u);
+        else if (leader)
+          atomicAdd(&s_h[p][d0], (uint32_t)__popcll(same));
+      }
     }
     const bool done = s_o[kBlock] >= p1;
     __syncthreads();
