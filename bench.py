@@ -24,8 +24,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd Mpixels/sec & train steps/sec at 300k 6D Gaussians 800x800; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# fp32 without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published fp32 vector peak (it counts packed fp32 issue)
+FP32_PEAK_TFLOPS = 157.3
+# the same without packed issue, which this code does not use: 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # Algorithmic flops of the compositing kernels per contributing (pixel,
 # Gaussian) pair -- the pairs whose alpha reaches 1/255 before the pixel
@@ -43,6 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched-views leg of the default run")
     ap.add_argument("--cpu-pixels", type=int, default=32768)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a kernel of known traffic that "
@@ -113,6 +117,7 @@ def main():
         tr.step([cam], target)
     kt = {k: r.ctx.kernel_time(k)[0] / 3 for k in _lib.KERNEL_NAMES}
     dom = max(kt, key=kt.get)
+    adam_ms = time_adam(tr)
 
     # timed region: only the dominant kernel is bracketed by events
     r.ctx.set_timing(1 << dom)
@@ -159,9 +164,14 @@ def main():
         "wall_s_timed": round(wall, 3),
         "kernel_ms": {_lib.KERNEL_NAMES[k]: round(v, 4) for k, v in kt.items()},
         "roofline": roof,
+        "hbm": hbm_report({_lib.KERNEL_NAMES[k]: v for k, v in kt.items()}, adam_ms, ms_step, n, nb, P, px, tiles),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params_np, cam, args.cpu_pixels)
+    if not args.no_c3:
+        del tr, r, target
+        torch.cuda.empty_cache()
+        out["c3_batched_views"] = c3_leg(args.steps, args.warmup)
     if args.copy_probe_mib > 0:
         a = torch.empty(args.copy_probe_mib << 18, device=dev, dtype=torch.float32).fill_(1.0)
         b = torch.empty_like(a)
@@ -187,8 +197,10 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
         counts = float(cnt_r.ctx.export(_lib.EXPORT_COUNTS).astype(np.float64).sum())
         per = FWD_FLOPS_PER_CONTRIB if dom == _lib.K_BLEND_FWD else BWD_FLOPS_PER_CONTRIB
         achieved = per * counts / (avg_ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic(name, settings),
+        return {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic(name, settings),
+                "peak_nonpacked": round(ALU_NONPACKED_TFLOPS, 2),
+                "frac_nonpacked": round(achieved / ALU_NONPACKED_TFLOPS, 4),
                 "avg_ms": round(avg_ms, 4), "contributions_per_launch": counts, "flops_per_contribution": per}
     if dom == _lib.K_PREPROCESS:
         bytes_ = 304 * n + 4 * n + 52 * nb
@@ -199,6 +211,113 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
     achieved = bytes_ / (avg_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic(name, settings), "avg_ms": round(avg_ms, 4)}
+
+
+def alg_bytes(n, nb, P, px, tiles):
+    """Algorithmic HBM bytes per launch of each stage of a one-view training
+    step: what the method has to read and write (n Gaussians, nb of them binned
+    in the view, P (tile, Gaussian) pairs, px pixels)."""
+    return {
+        "preprocess": 304 * n + 4 * n + 52 * nb,            # params; tile count; record + depth
+        "binning": 64 * nb + 24 * P + 4 * P + 8 * tiles,    # depth sort; pair build + tile sort; ranges
+        "blend_fwd": 40 * P + 20 * px,                      # record per pair; colour, T, last per pixel
+        "l1": 12 * 3 * px,                                  # image, target, gradient
+        "blend_bwd": 40 * P + 32 * px + 36 * nb,            # as the forward + dL/dI; screen-space gradients
+        "preprocess_bwd": 608 * n + 4 * n + 36 * nb,        # params in, gradient out; screen-space gradients
+        "adam": 7 * 4 * 76 * n,                             # params, grad, m, v read; params, m, v written
+    }
+
+
+def hbm_report(kernel_ms, adam_ms, ms_step, n, nb, P, px, tiles):
+    """Achieved algorithmic GB/s and the fraction of the 8 TB/s HBM peak per
+    stage and for the whole step (the blend kernels are ALU-bound; their GB/s
+    is reported for completeness, their roofline is the fp32 rate)."""
+    b = alg_bytes(n, nb, P, px, tiles)
+    ms = dict(kernel_ms, adam=adam_ms)
+    kernels = {}
+    for k, t in ms.items():
+        if k in b and t > 0:
+            gbs = b[k] / (t * 1e-3) / 1e9
+            kernels[k] = {"ms": round(t, 4), "bytes": int(b[k]), "GBs": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "bound": "alu" if k in ("blend_fwd", "blend_bwd") else "hbm"}
+    total = sum(b.values())
+    step_gbs = total / (ms_step * 1e-3) / 1e9
+    return {"step_bytes": int(total), "step_GBs": round(step_gbs, 1), "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+            "peak_GBs": HBM_PEAK_GBS, "kernels": kernels}
+
+
+def time_adam(tr, launches=20):
+    """Average duration of the Adam kernel on the step's own sizes (on copies
+    of the state, so the training state is left alone), with HIP events on the
+    launch stream."""
+    import torch
+    from paper_2410_04974_amd import _lib
+    p, g, m, v = (t.clone() for t in (tr.params, tr.grad, tr.m, tr.v))
+    cnt = torch.zeros(1, device=p.device, dtype=torch.int32)
+    _lib.adam_devstep(p, g, m, v, tr.lr, cnt, tr.betas[0], tr.betas[1], tr.eps)
+    return _timed(lambda: _lib.adam_devstep(p, g, m, v, tr.lr, cnt, tr.betas[0], tr.betas[1], tr.eps), launches)
+
+
+def c3_leg(steps, warmup):
+    """The batched-views comparison at the library's automatic settings (no
+    autotuning, so it fits the default run): 16 uneven cameras, 500k
+    Gaussians, one captured forward + backward over all views against 16
+    per-view eager forward + backward calls, images compared bitwise."""
+    import torch
+
+    import synth
+    from paper_2410_04974_amd import Renderer
+
+    w = synth.workload("c3")
+    cams = w.cameras
+    params = torch.from_numpy(synth.make_scene(w.scene)).to("cuda:0")
+    px = sum(c.width * c.height for c in cams)
+    gen = torch.Generator(device="cuda:0").manual_seed(2)
+    dls = [torch.randn((3, c.height, c.width), device="cuda:0", generator=gen) for c in cams]
+    rb = Renderer()
+    imgs = rb.forward(params, cams)
+    torch.cuda.synchronize()
+    sz = rb.ctx.sizes()
+    rb.configure(pair_capacity=int(sz["pairs"] * 1.3) + 4096)
+    grad = torch.empty_like(params)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            rb.forward(params, cams, out=imgs)
+            rb.backward(params, dls, grad=grad)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rb.forward(params, cams, out=imgs)
+        rb.backward(params, dls, grad=grad)
+    for _ in range(warmup):
+        g.replay()
+    ms_b = _timed(g.replay, steps)
+    rb.ctx.check()
+    per = [Renderer() for _ in cams]
+    gsum = torch.empty_like(params)
+
+    def per_view():
+        for r1, c, d in zip(per, cams, dls):
+            r1.forward(params, [c])
+            r1.backward(params, [d], grad=gsum)
+
+    per_view()
+    torch.cuda.synchronize()
+    for r1 in per:
+        r1.configure(pair_capacity=int(r1.ctx.sizes()["pairs"] * 1.3) + 4096)
+    equal = all(torch.equal(per[k].forward(params, [c])[0], imgs[k]) for k, c in enumerate(cams))
+    for _ in range(max(1, warmup // 2)):
+        per_view()
+    ms_v = _timed(per_view, max(2, steps // 4))
+    return {"workload": "c3: 500k 6D Gaussians, 16 Fibonacci cameras cycling 400x400, 800x800, 1280x720, "
+                        "1600x900, forward + backward", "pixels": px, "pairs": sz["pairs"],
+            "batched_graph": {"ms_per_step": round(ms_b, 4), "mpixels_per_s": round(px / (ms_b * 1e-3) / 1e6, 3),
+                              "batch": sz["batch"], "chunk": sz["chunk"]},
+            "per_view_launches": {"ms_per_step": round(ms_v, 4), "mpixels_per_s": round(px / (ms_v * 1e-3) / 1e6, 3)},
+            "speedup": round(ms_v / ms_b, 3), "images_bitwise_equal": bool(equal)}
 
 
 def _timed(fn, steps):
@@ -420,7 +539,7 @@ def cpu_baseline(params_np, cam, npix):
     pix = synth.pixel_subset(cam.width, cam.height, npix, seed=5)
     dl = np.random.default_rng(6).normal(size=(len(pix), 3))
     t0 = time.perf_counter()
-    oracle.render(params_np, cam, pixels=pix)
+    oracle.render_plain(params_np, cam, pixels=pix)
     oracle.backward(params_np, cam, dl, pixels=pix)
     dt = time.perf_counter() - t0
     return {"value": round(len(pix) / dt / 1e6, 6), "unit": "Mpixels/s", "cores": oracle.num_threads(),

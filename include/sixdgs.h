@@ -155,26 +155,35 @@ sixdgs_status sixdgs_build_cache(const float* params, int64_t n, float* cache, v
 sixdgs_status sixdgs_forward_cached(sixdgs_ctx* ctx, const float* params, const float* cache, int64_t n,
                                     const sixdgs_camera* cams, int32_t ncam, float* const* images, void* stream);
 
-/* Backward of the last forward on this context: given dL/dI for each of its
- * cameras (host array of ncam device pointers, each [3][H][W]), writes dL/d
- * params into `grad` (device [76][n], overwritten).  `params` and `n` must be
- * those of the forward.  If `densify` is not NULL (device [2][n]) it adds, per
- * Gaussian, the norm of its screen-space mean gradient in normalised device
- * units (row 0) and the number of views it was visible in (row 1) -- the
- * statistics the adaptive density control of Sec. 4.3 consumes. */
-sixdgs_status sixdgs_backward(sixdgs_ctx* ctx, const float* params, int64_t n, const float* const* dl_dimages,
-                              float* grad, float* densify, void* stream);
+/* Backward of the last forward on this context (the derivative of the
+ * Sec. 4.4 compositing, then of the projection, the SH colour of Sec. 4.2, the
+ * slice of Sec. 3.2 eq:mu / eq:sigma and the directional opacity of Sec. 4.2
+ * eq:pdfv2, into the raw parameters of Sec. 3.1): given dL/dI for each of its
+ * ncam cameras (host array of ncam device pointers, each [3][H][W] of that
+ * camera), writes dL/d params into `grad` (device [76][n], overwritten).
+ * `params`, `n` and `ncam` must be those of the forward (STATE for other
+ * params / n, INVALID_ARG for another ncam); the dL/dI buffers must hold
+ * the forward's image sizes (not checkable here).  If `densify` is not NULL
+ * (device [2][n]) it adds, per Gaussian, the norm of its screen-space mean
+ * gradient in normalised device units (row 0) and the number of views it was
+ * visible in (row 1) -- the statistics the adaptive density control of Sec. 4.3
+ * consumes. */
+sixdgs_status sixdgs_backward(sixdgs_ctx* ctx, const float* params, int64_t n, int32_t ncam,
+                              const float* const* dl_dimages, float* grad, float* densify, void* stream);
 
-/* Backward of the last forward fused with one Adam step (the training-step
- * form of sixdgs_backward followed by sixdgs_adam): the per-Gaussian gradient
+/* Backward of the last forward fused with one Adam step: the training step of
+ * Sec. 5.1 (the paper trains with Adam, learning rate 1e-2 for the 6D
+ * covariance and 1e-3 for the direction mean, 3DGS defaults elsewhere) in the
+ * form of sixdgs_backward followed by sixdgs_adam.  The per-Gaussian gradient
  * is applied to params, m and v (device [76][n] each, updated in place) as it
  * is produced and never written to memory.  params must be the pointer the
  * forward rendered (it is modified here, so the forward's saved state is spent:
- * a further backward needs a new forward).  lr, beta1, beta2, eps and step as
- * in sixdgs_adam; densify as in sixdgs_backward. */
-sixdgs_status sixdgs_backward_adam(sixdgs_ctx* ctx, float* params, int64_t n, const float* const* dl_dimages,
-                                   float* m, float* v, const float* lr, float beta1, float beta2, float eps,
-                                   int32_t step, float* densify, void* stream);
+ * a further backward needs a new forward).  ncam and dl_dimages as in
+ * sixdgs_backward; lr, beta1, beta2, eps and step as in sixdgs_adam; densify
+ * as in sixdgs_backward. */
+sixdgs_status sixdgs_backward_adam(sixdgs_ctx* ctx, float* params, int64_t n, int32_t ncam,
+                                   const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
+                                   float beta2, float eps, int32_t step, float* densify, void* stream);
 
 /* Learnable per-Gaussian lambda (Sec. 4.2; the paper trains it over a window
  * of iterations, Sec. 5.1).  lambda_raw: device [n] float32 raw values for the
@@ -228,11 +237,12 @@ sixdgs_status sixdgs_densify_apply(sixdgs_ctx* ctx, const float* params, const f
                                    const float* lambda_raw, int64_t n, const float* noise, float* params_out,
                                    float* m_out, float* v_out, float* lambda_out, int64_t n_out, void* stream);
 
-/* L1 photometric loss over nimg (1..SIXDGS_MAX_VIEWS) image pairs:
- * loss = mean |I - I*| over every element of every image (written to the
- * device float `loss`), and dL/dI = sign(I - I*) / total_count written to
- * dl_dimages[k] (may alias nothing else).  numel[k] is the element count of
- * image k (host array). */
+/* L1 photometric loss (the L1 term of the 3DGS loss that Sec. 4.4 and Sec. 5.1
+ * keep) over nimg (1..SIXDGS_MAX_VIEWS) image pairs: loss = mean |I - I*|
+ * over every element of every image (written to the device float `loss`),
+ * and dL/dI = sign(I - I*) / total_count written to dl_dimages[k] (may alias
+ * nothing else).  numel[k] is the element count of image k (host array).
+ * INVALID_ARG for nimg out of range, NULL pointers or numel <= 0. */
 sixdgs_status sixdgs_l1_loss(sixdgs_ctx* ctx, int32_t nimg, const float* const* images, const float* const* targets,
                              const int64_t* numel, float* const* dl_dimages, float* loss, void* stream);
 
@@ -248,18 +258,22 @@ sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* ctx, int32_t nimg, const float* c
                                    const float* const* targets, const int32_t* heights, const int32_t* widths,
                                    float lambda_dssim, float* const* dl_dimages, float* loss, void* stream);
 
-/* One Adam step (Kingma and Ba, bias-corrected) on params [76][n] in place,
- * with moments m, v (device [76][n], updated in place; zero before step 1).
- * lr[6] (host) holds the learning rate of the row groups mu_p, mu_d,
- * Cholesky, SH degree 0, SH degree 1-3, opacity.  step counts from 1. */
+/* One Adam step (Kingma and Ba, bias-corrected; the optimiser of Sec. 5.1,
+ * whose learning rates are 1e-2 for the 6D covariance and 1e-3 for the
+ * direction mean, with the 3DGS defaults elsewhere) on params [76][n] in
+ * place, with moments m, v (device [76][n], updated in place; zero before
+ * step 1).  lr[6] (host) holds the learning rate of the row groups mu_p, mu_d,
+ * Cholesky, SH degree 0, SH degree 1-3, opacity.  step counts from 1.
+ * INVALID_ARG for NULL pointers with n > 0, step < 1 or betas outside [0, 1). */
 sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
                           float beta1, float beta2, float eps, int32_t step, void* stream);
 
-/* sixdgs_adam with the step count kept on the device: step_counter (device
- * int32, 0 before the first step) holds the number of steps taken; this call
- * takes step *step_counter + 1 and then increments the counter, all on the
- * stream.  Nothing about the step is baked into the launch, so a captured
- * graph of a training step advances Adam on every replay. */
+/* sixdgs_adam (the Sec. 5.1 optimiser step) with the step count kept on the
+ * device: step_counter (device int32, 0 before the first step) holds the
+ * number of steps taken; this call takes step *step_counter + 1 and then
+ * increments the counter, all on the stream.  Nothing about the step is baked
+ * into the launch, so a captured graph of a training step advances Adam on
+ * every replay.  Errors as sixdgs_adam. */
 sixdgs_status sixdgs_adam_devstep(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
                                   float beta1, float beta2, float eps, int32_t* step_counter, void* stream);
 

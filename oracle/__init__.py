@@ -34,14 +34,15 @@ _SRC = os.path.join(_HERE, "oracle6dgs.c")
 _LIB = os.path.join(_HERE, "liboracle6dgs.so")
 
 NROWS = 76
-NREC = 37
+NREC = 38
 NG2D = 9
 FIELDS = {
     "alive": (0, 1), "mu_cond": (1, 3), "sigma_cond": (4, 6), "alpha": (10, 1), "f": (11, 1),
     "D": (12, 1), "alpha_cond": (13, 1), "rgb": (14, 3), "p": (17, 3), "depth": (20, 1),
     "u": (21, 1), "v": (22, 1), "cov2d": (23, 3), "conic": (26, 3), "ex": (29, 1), "ey": (30, 1),
-    "dir": (31, 3), "sh_dir": (34, 3),
+    "dir": (31, 3), "sh_dir": (34, 3), "near_cut": (37, 1),
 }
+ENV_AMBIGUOUS, ENV_KINK, ENV_UNRESOLVED = 1, 2, 4
 
 
 def build(force: bool = False) -> str:
@@ -63,10 +64,10 @@ class _Cam(ctypes.Structure):
 class _Set(ctypes.Structure):
     _fields_ = [("lambda_opa", ctypes.c_double), ("z_near", ctypes.c_double), ("bg", ctypes.c_double * 3),
                 ("jac_guard", ctypes.c_double), ("dilation", ctypes.c_double), ("alpha_max", ctypes.c_double),
-                ("alpha_min", ctypes.c_double), ("t_min", ctypes.c_double), ("amb_alpha_min", ctypes.c_double),
-                ("amb_alpha_max", ctypes.c_double), ("amb_t_min", ctypes.c_double), ("amb_depth", ctypes.c_double),
-                ("amb_impact", ctypes.c_double), ("lambda_raw", ctypes.c_void_p), ("grad_lambda", ctypes.c_void_p),
-                ("color_rgb", ctypes.c_int64)]
+                ("alpha_min", ctypes.c_double), ("t_min", ctypes.c_double), ("m_uv", ctypes.c_double),
+                ("m_conic", ctypes.c_double), ("m_alpha", ctypes.c_double), ("m_depth", ctypes.c_double),
+                ("m_eval", ctypes.c_double), ("m_trel", ctypes.c_double), ("max_leaves", ctypes.c_int64),
+                ("lambda_raw", ctypes.c_void_p), ("grad_lambda", ctypes.c_void_p), ("color_rgb", ctypes.c_int64)]
 
 
 @dataclass
@@ -83,22 +84,32 @@ class Settings:
     alpha_max: float = 0.99
     alpha_min: float = 1.0 / 255.0
     t_min: float = 1e-4
-    # Margins within which a float32 renderer may legitimately take a threshold
-    # decision the other way; pixels with such a decision are flagged ambiguous.
-    amb_alpha_min: float = 2e-6
-    amb_alpha_max: float = 1e-5
-    amb_t_min: float = 1e-7
-    amb_depth: float = 5e-7
-    amb_impact: float = 2.5e-5
+    # Float32 error bounds of a renderer working on float32 records; they only
+    # feed the decision envelope (render_envelope), never the rendered values.
+    # m_uv is in pixels; None: uv_ulps float32 spacings at max(W, H).
+    m_uv: float | None = None
+    uv_ulps: float = 8.0
+    m_conic: float = 6e-5
+    m_alpha: float = 3e-5
+    m_depth: float = 6e-7
+    m_eval: float = 2.4e-7
+    m_trel: float = 1.2e-7
+    max_leaves: int = 4096
     # False: colour from the degree-3 SH expansion (Sec. 4.2).  True: the No-SH
     # ablation (Sec. 5), rgb = sigmoid(c) with c in the SH degree-0 rows.
     rgb_color: bool = False
 
-    def _c(self, lambda_raw=None, grad_lambda=None) -> _Set:
+    def uv_margin(self, cam) -> float:
+        if self.m_uv is not None:
+            return float(self.m_uv)
+        return float(self.uv_ulps * np.spacing(np.float32(max(int(cam.width), int(cam.height)))))
+
+    def _c(self, cam=None, lambda_raw=None, grad_lambda=None) -> _Set:
         """C settings; lambda_raw / grad_lambda are float64 arrays the caller keeps alive."""
+        m_uv = self.uv_margin(cam) if cam is not None else (self.m_uv or 0.0)
         return _Set(self.lambda_opa, self.z_near, (ctypes.c_double * 3)(*self.bg), self.jac_guard,
-                    self.dilation, self.alpha_max, self.alpha_min, self.t_min, self.amb_alpha_min,
-                    self.amb_alpha_max, self.amb_t_min, self.amb_depth, self.amb_impact,
+                    self.dilation, self.alpha_max, self.alpha_min, self.t_min, m_uv, self.m_conic, self.m_alpha,
+                    self.m_depth, self.m_eval, self.m_trel, int(self.max_leaves),
                     None if lambda_raw is None else _ptr(lambda_raw),
                     None if grad_lambda is None else _ptr(grad_lambda), int(bool(self.rgb_color)))
 
@@ -114,7 +125,9 @@ def lib():
         I64 = ctypes.c_int64
         _lib.orc_preprocess.argtypes = [I64, P, P, P, P]
         _lib.orc_static.argtypes = [I64, P, P]
-        _lib.orc_render.argtypes = [I64, P, P, P, I64, P, P, P, P, P, ctypes.c_int]
+        _lib.orc_render.argtypes = [I64, P, P, P, I64, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        _lib.orc_render_records.argtypes = [I64, P, P, P, I64, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+        _lib.orc_render_records.restype = ctypes.c_int
         _lib.orc_backward.argtypes = [I64, P, P, P, I64, P, P, P, P, ctypes.c_int]
         _lib.orc_slice.argtypes = [I64, P, P, ctypes.c_double, P]
         _lib.orc_sh_basis.argtypes = [I64, P, P]
@@ -164,7 +177,7 @@ def preprocess(params, cam, settings: Settings = Settings(), lambda_raw=None) ->
     n = p.shape[1]
     rec = np.zeros((n, NREC), np.float64)
     lam = _lam(lambda_raw, n)
-    c, s = _cam(cam), settings._c(lam)
+    c, s = _cam(cam), settings._c(cam, lam)
     lib().orc_preprocess(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), _ptr(rec))
     out = {}
     for k, (o, w) in FIELDS.items():
@@ -173,29 +186,102 @@ def preprocess(params, cam, settings: Settings = Settings(), lambda_raw=None) ->
     return out
 
 
-def render(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0, lambda_raw=None):
-    """Brute-force render.  Returns (color, T_final, n_contrib, ambiguous); with
-    ``pixels=None`` color is [3, H, W] and the others [H, W]; otherwise color is
-    [npix, 3] and the others [npix] for the listed row-major pixel ids."""
-    p = _params64(params)
-    n = p.shape[1]
-    lam = _lam(lambda_raw, n)
-    c, s = _cam(cam), settings._c(lam)
+def _render_call(fn, first, cam, settings, pixels, nthreads, lam, envelope):
+    """Runs orc_render / orc_render_records (``first`` holds their leading
+    arguments) and shapes the outputs."""
+    c, s = _cam(cam), settings._c(cam, lam)
     full = pixels is None
     npix = cam.width * cam.height if full else len(pixels)
     pix = None if full else np.ascontiguousarray(np.asarray(pixels, np.int64))
     color = np.zeros((npix, 3), np.float64)
     T = np.zeros(npix, np.float64)
     nc = np.zeros(npix, np.int64)
-    amb = np.zeros(npix, np.int32)
-    rc = lib().orc_render(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), npix,
-                          None if full else _ptr(pix), _ptr(color), _ptr(T), _ptr(nc), _ptr(amb), nthreads)
-    if rc != 0:
+    if envelope:
+        lo = np.zeros((npix, 4), np.float64)
+        hi = np.zeros((npix, 4), np.float64)
+        impact = np.zeros(npix, np.float64)
+        leaves = np.zeros(npix, np.int64)
+        flags = np.zeros(npix, np.int32)
+        env = [_ptr(lo), _ptr(hi), _ptr(impact), _ptr(leaves), _ptr(flags)]
+    else:
+        env = [None] * 5
+    rc = fn(*first, ctypes.byref(c), ctypes.byref(s), npix, None if full else _ptr(pix), _ptr(color), _ptr(T),
+            _ptr(nc), *env, nthreads)
+    if rc < 0:
         raise MemoryError("oracle render failed")
+    out = {"color": color, "T": T, "ncontrib": nc, "near_z": int(rc)}
+    if envelope:
+        out.update(lo=lo[:, :3], hi=hi[:, :3], T_lo=lo[:, 3], T_hi=hi[:, 3], leaves=leaves, flags=flags,
+                   impact=impact,
+                   ambiguous=(flags & (ENV_AMBIGUOUS | ENV_UNRESOLVED)) != 0,
+                   kink=(flags & ENV_KINK) != 0, unresolved=(flags & ENV_UNRESOLVED) != 0)
     if full:
         H, W = cam.height, cam.width
-        return color.T.reshape(3, H, W), T.reshape(H, W), nc.reshape(H, W), amb.reshape(H, W).astype(bool)
-    return color, T, nc, amb.astype(bool)
+        for k, v in list(out.items()):
+            if isinstance(v, np.ndarray):
+                out[k] = v.T.reshape(v.shape[1], H, W) if v.ndim == 2 else v.reshape(H, W)
+    return out
+
+
+def render(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0, lambda_raw=None):
+    """Brute-force render.  Returns (color, T_final, n_contrib, ambiguous); with
+    ``pixels=None`` color is [3, H, W] and the others [H, W]; otherwise color is
+    [npix, 3] and the others [npix] for the listed row-major pixel ids.
+    ``ambiguous`` marks pixels with a threshold decision a float32 renderer may
+    take the other way (see ``render_envelope``)."""
+    e = render_envelope(params, cam, settings, pixels, nthreads, lambda_raw)
+    return e["color"], e["T"], e["ncontrib"], e["ambiguous"]
+
+
+def render_plain(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0, lambda_raw=None):
+    """The brute-force render alone (no decision envelope): (color, T_final, n_contrib)."""
+    p = _params64(params)
+    e = _render_call(lib().orc_render, (p.shape[1], _ptr(p)), cam, settings, pixels, nthreads,
+                     _lam(lambda_raw, p.shape[1]), False)
+    return e["color"], e["T"], e["ncontrib"]
+
+
+def render_envelope(params, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0,
+                    lambda_raw=None) -> dict:
+    """Brute-force render plus its decision envelope (test infrastructure).
+
+    ``color``, ``T``, ``ncontrib``: the definition's values.  ``lo`` / ``hi``
+    (colour) and ``T_lo`` / ``T_hi``: the range over every combination of
+    outcomes of the threshold decisions (alpha >= 1/255, the 1e-4 stop, the
+    order at nearly equal depth) that a renderer may legitimately take the
+    other way on float32 records, i.e. records within the error bounds
+    ``settings.m_*``.  ``leaves``: the number of outcome paths; ``ambiguous``:
+    more than one path possible (or the exploration gave up, ``unresolved``);
+    ``kink``: a taken Gaussian's alpha is within the error bound of the 0.99
+    clamp (the value is continuous there, its derivative is not).
+    ``impact``: a bound on the local effect of the undecided decisions (T a
+    for a skip, stop or clamp, T a_i a_j for an order); gradient comparisons
+    leave out pixels where it is not negligible.
+    ``near_z``: Gaussians within the depth margin of z_near, whose culling no
+    envelope covers (expected 0).  Shapes as in ``render``."""
+    p = _params64(params)
+    return _render_call(lib().orc_render, (p.shape[1], _ptr(p)), cam, settings, pixels, nthreads,
+                        _lam(lambda_raw, p.shape[1]), True)
+
+
+RECORD_COLUMNS = ("u", "v", "Qxx", "Qxy", "Qyy", "alpha_cond", "r", "g", "b", "depth", "alive")
+
+
+def render_records(records, cam, settings: Settings = Settings(), pixels=None, nthreads: int = 0,
+                   envelope: bool = True) -> dict:
+    """``render_envelope`` from given per-Gaussian records ([m, 11], columns
+    RECORD_COLUMNS) instead of parameters."""
+    r = np.ascontiguousarray(np.asarray(records, np.float64))
+    assert r.ndim == 2 and r.shape[1] == len(RECORD_COLUMNS)
+    return _render_call(lib().orc_render_records, (r.shape[0], _ptr(r)), cam, settings, pixels, nthreads, None,
+                        envelope)
+
+
+def records_of(params, cam, settings: Settings = Settings()) -> np.ndarray:
+    """The records ``render_records`` takes, computed by ``preprocess``."""
+    o = preprocess(params, cam, settings)
+    return np.column_stack([o["u"], o["v"], o["conic"], o["alpha_cond"], o["rgb"], o["depth"],
+                            o["alive"] | (o["near_cut"] == 1)]).astype(np.float64)
 
 
 def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=None, nthreads: int = 0,
@@ -209,7 +295,7 @@ def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=Non
     n = p.shape[1]
     lam = _lam(lambda_raw, n)
     glam = None if lam is None else np.zeros(n, np.float64)
-    c, s = _cam(cam), settings._c(lam, glam)
+    c, s = _cam(cam), settings._c(cam, lam, glam)
     full = pixels is None
     if full:
         npix = cam.width * cam.height
@@ -226,6 +312,7 @@ def backward(params, cam, dl_dimage, settings: Settings = Settings(), pixels=Non
     if rc != 0:
         raise MemoryError("oracle backward failed")
     return (grad, g2d) if lam is None else (grad, g2d, glam)
+
 
 
 def static_part(params) -> np.ndarray:
@@ -266,7 +353,7 @@ def record_vjp(params, cam, g2d, settings: Settings = Settings()) -> np.ndarray:
     n = p.shape[1]
     g = np.ascontiguousarray(np.asarray(g2d, np.float64).reshape(n, NG2D))
     grad = np.zeros((NROWS, n), np.float64)
-    c, s = _cam(cam), settings._c()
+    c, s = _cam(cam), settings._c(cam)
     lib().orc_record_vjp(n, _ptr(p), ctypes.byref(c), ctypes.byref(s), _ptr(g), _ptr(grad))
     return grad
 
@@ -276,5 +363,6 @@ from .train import adam_step, l1_loss, densify_stats  # noqa: E402
 from .density import decompose, decisions, densify  # noqa: E402
 from .dssim import l1_dssim_loss, ssim  # noqa: E402
 
-__all__ = ["Settings", "build", "preprocess", "render", "backward", "slice_gaussians", "sh_basis",
+__all__ = ["Settings", "build", "preprocess", "render", "render_plain", "render_envelope", "render_records",
+           "records_of", "backward", "slice_gaussians", "sh_basis",
            "record_vjp", "bin_records", "tile_grid", "adam_step", "l1_loss", "densify_stats", "num_threads"]

@@ -69,7 +69,9 @@ enum {
   F_EY = 30,
   F_DIR = 31,     /* 3: slice direction d */
   F_SHDIR = 34,   /* 3: SH direction */
-  NREC = 37
+  F_NEARCUT = 37, /* 1: culled by alpha_cond < 1/255 within the alpha margin of the cut;
+                     2: depth within the depth margin of z_near (see the decision envelope) */
+  NREC = 38
 };
 
 typedef struct {
@@ -88,13 +90,17 @@ typedef struct {
   double alpha_max;  /* 0.99 */
   double alpha_min;  /* 1/255 */
   double t_min;      /* 1e-4 */
-  /* ambiguity margins: a pixel is flagged when a decision of the walk lies
-   * within these of its threshold, where float32 rounding could flip it */
-  double amb_alpha_min; /* |a - alpha_min| */
-  double amb_alpha_max; /* |alpha_raw - alpha_max| (kink of the clamp) */
-  double amb_t_min;     /* |T' - t_min| */
-  double amb_depth;     /* relative depth gap between consecutive contributors */
-  double amb_impact;    /* smallest colour change a flip at the 1/255 cut must be able to make */
+  /* Float32 error bounds of a renderer that takes the walk's decisions on
+   * float32 records (test infrastructure: they feed only the decision
+   * envelope below, never the rendered values).  A decision whose outcome can
+   * change when the record fields move within these bounds is ambiguous. */
+  double m_uv;      /* |u_f32 - u|, |v_f32 - v| in pixels */
+  double m_conic;   /* |x^T (Q_f32 - Q) x| <= m_conic x^T Q x: the conic's error in its own metric */
+  double m_alpha;   /* relative error of alpha_cond */
+  double m_depth;   /* relative error of the depth */
+  double m_eval;    /* rounding of ln(alpha) evaluated in float32, relative to its terms' magnitudes */
+  double m_trel;    /* relative rounding of one float32 operation of the transmittance update */
+  int64_t max_leaves; /* outcome states kept per pixel before giving up (flag UNRESOLVED) */
   /* learnable per-Gaussian lambda (Sec. 4.2, trained over a window of
    * iterations per Sec. 5.1): when lambda_raw is not NULL Gaussian i uses
    * lambda = sigmoid(lambda_raw[i]) instead of lambda_opa, and the backward
@@ -369,6 +375,7 @@ static void record_one(const double *params, int64_t n, int64_t i, const orc_cam
     p[r] = cam->R[3 * r] * mu_c[0] + cam->R[3 * r + 1] * mu_c[1] + cam->R[3 * r + 2] * mu_c[2] + cam->t[r];
   for (int k = 0; k < 3; k++) rec[F_P + k] = p[k];
   rec[F_DEPTH] = p[2];
+  if (fabs(p[2] - s->z_near) <= s->m_depth * fabs(p[2])) rec[F_NEARCUT] = 2.0;
   if (!(p[2] > s->z_near)) return;
   double z = p[2];
   rec[F_U] = cam->fx * p[0] / z + cam->cx;
@@ -393,7 +400,10 @@ static void record_one(const double *params, int64_t n, int64_t i, const orc_cam
   rec[F_CONIC + 0] = cyy / det;
   rec[F_CONIC + 1] = -cxy / det;
   rec[F_CONIC + 2] = cxx / det;
-  if (!(ac * 255.0 >= 1.0)) return;
+  if (!(ac * 255.0 >= 1.0)) {
+    if (ac * 255.0 * (1.0 + s->m_alpha) >= 1.0 && rec[F_NEARCUT] == 0.0) rec[F_NEARCUT] = 1.0;
+    return;
+  }
   double qmax = 2.0 * log(255.0 * ac);
   rec[F_EX] = sqrt(qmax * cxx);
   rec[F_EY] = sqrt(qmax * cyy);
@@ -414,20 +424,27 @@ static int cmp_order(const void *a, const void *b) {
   return (x->idx < y->idx) ? -1 : (x->idx > y->idx);
 }
 
-/* Alive Gaussians sorted by (depth, index); returns their count. */
-static int64_t global_order(int64_t n, const double *rec, int64_t *order) {
+/* Gaussians selected by `pick` (alive ones, or alive and near-cut ones),
+ * sorted by (depth, index); returns their count. */
+static int64_t global_order(int64_t n, const double *rec, int64_t *order, int with_nearcut) {
   order_item *it = malloc(sizeof(order_item) * (n > 0 ? n : 1));
   int64_t m = 0;
-  for (int64_t i = 0; i < n; i++)
-    if (rec[NREC * i + F_ALIVE] != 0.0) { it[m].depth = rec[NREC * i + F_DEPTH]; it[m].idx = i; m++; }
+  for (int64_t i = 0; i < n; i++) {
+    const double *r = rec + NREC * i;
+    if (r[F_ALIVE] != 0.0 || (with_nearcut && r[F_NEARCUT] == 1.0)) {
+      it[m].depth = r[F_DEPTH];
+      it[m].idx = i;
+      m++;
+    }
+  }
   qsort(it, m, sizeof(order_item), cmp_order);
   for (int64_t k = 0; k < m; k++) order[k] = it[k].idx;
   free(it);
   return m;
 }
 
-/* Compact view of the sorted alive records, so the per-pixel walk reads one array. */
-typedef struct { double u, v, qa, qb, qc, ac, r, g, b, depth; } sorted_rec;
+/* Compact view of the sorted records, so the per-pixel walk reads one array. */
+typedef struct { double u, v, qa, qb, qc, ac, r, g, b, depth; int live; } sorted_rec;
 
 static sorted_rec *make_sorted(const double *rec, const int64_t *order, int64_t m) {
   sorted_rec *sr = malloc(sizeof(sorted_rec) * (m > 0 ? m : 1));
@@ -438,59 +455,278 @@ static sorted_rec *make_sorted(const double *rec, const int64_t *order, int64_t 
     sr[k].ac = r[F_ALPHAC];
     sr[k].r = r[F_RGB]; sr[k].g = r[F_RGB + 1]; sr[k].b = r[F_RGB + 2];
     sr[k].depth = r[F_DEPTH];
+    sr[k].live = r[F_ALIVE] != 0.0;
   }
   return sr;
 }
 
 /* ----------------------------------------------------- per-pixel compositing */
-/* Walks one pixel; fills colour, final T, contributor count and the ambiguity
- * flag; if clist != NULL stores the contributors' sorted positions, their alpha
- * before the clamp and the transmittance in front of them. */
+/* Walks one pixel front to back over the alive Gaussians in depth order: the
+ * definition of the rendered value.  Fills colour, final T and the contributor
+ * count; if clist != NULL stores the contributors' sorted positions, their
+ * alpha before the clamp and the transmittance in front of them. */
 typedef struct {
   double color[3];
   double T;
   int64_t ncontrib;
-  int ambiguous;
 } pix_out;
 
 static void walk_pixel(const sorted_rec *sr, int64_t m, double px, double py, const orc_settings *s,
                        pix_out *o, int64_t *clist, double *araw_list, double *T_list) {
   double T = 1.0, C[3] = {0, 0, 0};
   int64_t nc = 0;
-  int amb = 0;
-  double last_depth = 0.0, last_wt = 0.0; /* depth and a*T of the previous contributor */
   for (int64_t k = 0; k < m; k++) {
     const sorted_rec *g = sr + k;
     double dx = px - g->u, dy = py - g->v;
     double q = g->qa * dx * dx + 2.0 * g->qb * dx * dy + g->qc * dy * dy;
     double araw = g->ac * exp(-0.5 * q);
     double a = fmin(s->alpha_max, araw);
-    /* including or skipping a Gaussian right at the 1/255 cut changes this
-     * pixel by at most about 2 T a; only flag where that is not negligible */
-    if (fabs(a - s->alpha_min) < s->amb_alpha_min && 2.0 * T * a > s->amb_impact) amb = 1;
     if (a < s->alpha_min) continue;
-    if (fabs(araw - s->alpha_max) < s->amb_alpha_max) amb = 1;
-    /* swapping two consecutive contributors changes the pixel by at most
-     * T_prev a_prev a (colours lie in [0, 1]) */
-    if (nc > 0 && fabs(g->depth - last_depth) < s->amb_depth * fmax(fabs(g->depth), fabs(last_depth)) &&
-        last_wt * a > s->amb_impact)
-      amb = 1;
     double Tn = T * (1.0 - a);
-    if (fabs(Tn - s->t_min) < s->amb_t_min) amb = 1;
     if (Tn < s->t_min) break;
     C[0] += g->r * a * T;
     C[1] += g->g * a * T;
     C[2] += g->b * a * T;
     if (clist) { clist[nc] = k; araw_list[nc] = araw; T_list[nc] = T; }
-    last_wt = a * T;
     T = Tn;
     nc++;
-    last_depth = g->depth;
   }
   for (int c = 0; c < 3; c++) o->color[c] = C[c] + T * s->bg[c];
   o->T = T;
   o->ncontrib = nc;
-  o->ambiguous = amb;
+}
+
+/* ------------------------------------------------------ decision envelope */
+/* Test infrastructure for comparing a float32 renderer with the definition.
+ * The walk above takes three kinds of threshold decisions -- skip a Gaussian
+ * whose alpha is below 1/255, stop before the transmittance falls below 1e-4,
+ * and the front-to-back order of Gaussians at (nearly) equal depth -- and a
+ * renderer working on float32 records may legitimately take any of them the
+ * other way when the record fields move within the float32 error bounds m_*
+ * of the settings.  For one pixel this follows every combination of outcomes
+ * of such decisions (each path a walk of the definition with those outcomes
+ * forced) and returns the range of colour and final transmittance over all of
+ * them.  A pixel with one outcome path is unambiguous, and its range is the
+ * single value walk_pixel returns.
+ *
+ * The paths are followed breadth first over the candidates in depth order.
+ * Everything a path decides later depends on its transmittance alone, not on
+ * the colour gathered so far, so paths that reach a candidate with the same
+ * transmittance are merged into one state that carries the range of their
+ * colours.  Candidates whose depths lie within the depth margin of each other
+ * form a group that is taken in every order. */
+enum { ENV_AMBIGUOUS = 1, ENV_KINK = 2, ENV_UNRESOLVED = 4 };
+
+typedef struct {
+  double a;       /* alpha after the clamp */
+  double rel;     /* relative uncertainty of a */
+  double depth;
+  double rgb[3];
+  int take_nom;   /* the definition takes it (alpha >= 1/255, alive) */
+  int can_flip;   /* the 1/255 decision may go the other way */
+  int kink;       /* the 0.99 clamp may go the other way (value continuous, derivative not) */
+} cand;
+
+typedef struct {
+  double T, Trel;       /* transmittance in front of the next candidate, its relative uncertainty */
+  double lo[3], hi[3];  /* range of the colour gathered so far */
+} env_state;
+
+typedef struct {
+  const orc_settings *s;
+  env_state *nxt;       /* states after the current group */
+  int64_t nnxt, cap;
+  double lo[4], hi[4];  /* colour (3) and final T over the finished paths */
+  int64_t leaves;
+  int flags;
+  double impact;        /* largest local effect of an undecided decision (see pixel_envelope) */
+} envelope;
+
+/* Bound on |ln a' - ln a| at pixel offset d = (dx, dy) from the Gaussian's
+ * mean when the record moves within the margins: the mean by e = m_uv per
+ * axis; the conic Q by E with |x^T E x| <= m_conic x^T Q x for every x (its
+ * error in its own metric); alpha_cond by the factor (1 +- m_alpha); plus the
+ * float32 evaluation of ln a, whose rounding is m_eval relative to the
+ * magnitudes of its terms.  With d' = d - eps,
+ *   q' = d'^T (Q + E) d' = (1 + t) d'^T Q d',  |t| <= m_conic,
+ *   d'^T Q d' = q - 2 eps^T Q d + eps^T Q eps,
+ * |eps^T Q d| <= e (|(Qd)_x| + |(Qd)_y|) and eps^T Q eps <= 2 e^2 (Qxx + Qyy). */
+static double ln_alpha_margin(const orc_settings *s, const sorted_rec *g, double dx, double dy) {
+  const double e = s->m_uv;
+  const double q = g->qa * dx * dx + 2.0 * g->qb * dx * dy + g->qc * dy * dy;
+  const double gx = fabs(g->qa * dx + g->qb * dy), gy = fabs(g->qb * dx + g->qc * dy);
+  const double shift = 2.0 * e * (gx + gy) + 2.0 * e * e * (g->qa + g->qc);
+  const double dq = shift + s->m_conic * (q + shift);
+  const double l1 = fabs(dx) + fabs(dy);
+  const double terms = 1.0 + fabs(log(g->ac)) + fmax(fabs(g->qa), fabs(g->qc)) * l1 * l1;
+  return -log1p(-s->m_alpha) + 0.5 * dq + s->m_eval * terms;
+}
+
+/* A finished path: its walk stopped, or ran out of candidates. */
+static void env_leaf(envelope *e, double T, const double lo[3], const double hi[3]) {
+  const double *bg = e->s->bg;
+  const double vl[4] = {lo[0] + T * bg[0], lo[1] + T * bg[1], lo[2] + T * bg[2], T};
+  const double vh[4] = {hi[0] + T * bg[0], hi[1] + T * bg[1], hi[2] + T * bg[2], T};
+  for (int k = 0; k < 4; k++) {
+    if (e->leaves == 0 || vl[k] < e->lo[k]) e->lo[k] = vl[k];
+    if (e->leaves == 0 || vh[k] > e->hi[k]) e->hi[k] = vh[k];
+  }
+  e->leaves++;
+}
+
+static void env_push(envelope *e, double T, double Trel, const double lo[3], const double hi[3]) {
+  if (e->nnxt == e->cap) { e->flags |= ENV_UNRESOLVED; return; }
+  env_state *x = e->nxt + e->nnxt++;
+  x->T = T; x->Trel = Trel;
+  for (int c = 0; c < 3; c++) { x->lo[c] = lo[c]; x->hi[c] = hi[c]; }
+}
+
+/* Members k.. of a group in the order perm: every outcome of each member's
+ * decisions; paths that get through the group become states of the next. */
+static void env_members(envelope *e, const cand *c, const int64_t *perm, int64_t g, int64_t k, double T, double Trel,
+                        const double lo[3], const double hi[3]) {
+  if (k == g) { env_push(e, T, Trel, lo, hi); return; }
+  const orc_settings *s = e->s;
+  const cand *x = c + perm[k];
+  if (x->can_flip) {
+    e->flags |= ENV_AMBIGUOUS;
+    e->impact = fmax(e->impact, T * x->a);
+  }
+  if (!x->take_nom || x->can_flip) env_members(e, c, perm, g, k + 1, T, Trel, lo, hi); /* skipped */
+  if (!x->take_nom && !x->can_flip) return;
+  /* taken: T' = T (1 - a) carries the uncertainty of T, of a, and one rounding each of 1 - a and the product */
+  const double Tn = T * (1.0 - x->a);
+  const double Trel_n = Trel + (x->a * x->rel + s->m_trel) / (1.0 - x->a) + s->m_trel;
+  const int may_stop = Tn * (1.0 - Trel_n) < s->t_min;
+  const int may_go = Tn * (1.0 + Trel_n) >= s->t_min;
+  if (may_stop && may_go) {
+    e->flags |= ENV_AMBIGUOUS;
+    e->impact = fmax(e->impact, T * x->a);
+  }
+  if (x->kink) {
+    e->flags |= ENV_KINK;
+    e->impact = fmax(e->impact, T * x->a);
+  }
+  if (may_stop) env_leaf(e, T, lo, hi);
+  if (may_go) {
+    double l2[3], h2[3];
+    for (int ch = 0; ch < 3; ch++) {
+      l2[ch] = lo[ch] + x->rgb[ch] * x->a * T;
+      h2[ch] = hi[ch] + x->rgb[ch] * x->a * T;
+    }
+    env_members(e, c, perm, g, k + 1, Tn, Trel_n, l2, h2);
+  }
+}
+
+/* Every order of perm[pos..g) for one incoming state. */
+static void env_orders(envelope *e, const cand *c, int64_t *perm, int64_t g, int64_t pos, const env_state *st) {
+  if (pos == g) { env_members(e, c, perm, g, 0, st->T, st->Trel, st->lo, st->hi); return; }
+  for (int64_t i = pos; i < g; i++) {
+    int64_t t = perm[pos]; perm[pos] = perm[i]; perm[i] = t;
+    env_orders(e, c, perm, g, pos + 1, st);
+    t = perm[pos]; perm[pos] = perm[i]; perm[i] = t;
+  }
+}
+
+static int cmp_state(const void *a, const void *b) {
+  const double x = ((const env_state *)a)->T, y = ((const env_state *)b)->T;
+  return (x > y) - (x < y);
+}
+
+/* Merges states whose transmittances agree to 1e-12 relative (orders of one
+ * group give the same product up to rounding). */
+static int64_t env_merge(env_state *st, int64_t n) {
+  if (n <= 1) return n;
+  qsort(st, n, sizeof(env_state), cmp_state);
+  int64_t m = 0;
+  for (int64_t i = 1; i < n; i++) {
+    env_state *a = st + m, *b = st + i;
+    if (b->T - a->T <= 1e-12 * fmax(a->T, b->T)) {
+      a->Trel = fmax(a->Trel, b->Trel) + 1e-12;
+      for (int c = 0; c < 3; c++) { a->lo[c] = fmin(a->lo[c], b->lo[c]); a->hi[c] = fmax(a->hi[c], b->hi[c]); }
+    } else {
+      st[++m] = *b;
+    }
+  }
+  return m + 1;
+}
+
+/* Largest group of depth-undecided candidates that is permuted (5! orders). */
+#define ENV_MAX_GROUP 5
+
+/* Envelope of one pixel over sr (alive and near-cut Gaussians in depth
+ * order).  cbuf holds m candidates, sbuf 2 * cap states.  *impact bounds
+ * the local effect of the undecided decisions, which is what a gradient
+ * comparison must stay clear of: a flipped skip or stop adds or removes one
+ * term of size T a; a swap of two Gaussians scales the transmittance in
+ * front of one of them by 1 - a of the other, a change of T a_i a_j to its
+ * term (the transmittance behind the pair does not depend on their order);
+ * a clamp that may go the other way changes the derivative of a term T a. */
+static void pixel_envelope(const sorted_rec *sr, int64_t m, double px, double py, const orc_settings *s,
+                           cand *cbuf, env_state *sbuf, int64_t cap, double lo[4], double hi[4], int64_t *leaves,
+                           int *flags, double *impact) {
+  const double ln_min = log(s->alpha_min);
+  int64_t nc = 0;
+  int fl = 0;
+  for (int64_t k = 0; k < m; k++) {
+    const sorted_rec *g = sr + k;
+    const double dx = px - g->u, dy = py - g->v;
+    const double q = g->qa * dx * dx + 2.0 * g->qb * dx * dy + g->qc * dy * dy;
+    const double lna = log(g->ac) - 0.5 * q;
+    if (lna < ln_min - 0.5) continue; /* far below the cut: no margin here comes near 0.5 */
+    const double dl = ln_alpha_margin(s, g, dx, dy);
+    if (dl >= 0.5) fl |= ENV_UNRESOLVED;
+    if (lna + dl < ln_min) continue;
+    const double araw = g->ac * exp(-0.5 * q);
+    cand *c = cbuf + nc;
+    c->a = fmin(s->alpha_max, araw);
+    c->take_nom = g->live && c->a >= s->alpha_min;
+    c->can_flip = (araw * exp(-dl) < s->alpha_min) && (araw * exp(dl) >= s->alpha_min);
+    const int clamped_lo = araw * exp(-dl) >= s->alpha_max; /* clamped whatever the error */
+    c->kink = !clamped_lo && araw * exp(dl) >= s->alpha_max;
+    c->rel = clamped_lo ? 0.0 : expm1(dl);
+    c->depth = g->depth;
+    c->rgb[0] = g->r; c->rgb[1] = g->g; c->rgb[2] = g->b;
+    nc++;
+  }
+  envelope e;
+  e.s = s; e.cap = cap; e.leaves = 0; e.flags = fl; e.impact = 0.0;
+  env_state *cur = sbuf, *nxt = sbuf + cap;
+  int64_t ncur = 1;
+  cur[0].T = 1.0; cur[0].Trel = 0.0;
+  for (int c = 0; c < 3; c++) cur[0].lo[c] = cur[0].hi[c] = 0.0;
+  int64_t perm[ENV_MAX_GROUP];
+  for (int64_t j = 0; j < nc && ncur > 0 && !(e.flags & ENV_UNRESOLVED);) {
+    /* the group: consecutive candidates whose depths lie within the depth margin */
+    int64_t r = j;
+    while (r + 1 < nc && fabs(cbuf[r + 1].depth - cbuf[r].depth) <=
+                             s->m_depth * (fabs(cbuf[r + 1].depth) + fabs(cbuf[r].depth)))
+      r++;
+    const int64_t g = r - j + 1;
+    if (g > ENV_MAX_GROUP) { e.flags |= ENV_UNRESOLVED; break; }
+    if (g > 1) {
+      e.flags |= ENV_AMBIGUOUS;
+      double tmax = 0.0, a1 = 0.0, a2 = 0.0; /* the largest state T and the two largest alphas */
+      for (int64_t i = 0; i < ncur; i++) tmax = fmax(tmax, cur[i].T);
+      for (int64_t k = j; k <= r; k++) {
+        if (cbuf[k].a > a1) { a2 = a1; a1 = cbuf[k].a; }
+        else if (cbuf[k].a > a2) a2 = cbuf[k].a;
+      }
+      e.impact = fmax(e.impact, tmax * a1 * a2);
+    }
+    for (int64_t k = 0; k < g; k++) perm[k] = k;
+    e.nxt = nxt;
+    e.nnxt = 0;
+    for (int64_t i = 0; i < ncur; i++) env_orders(&e, cbuf + j, perm, g, 0, cur + i);
+    ncur = env_merge(nxt, e.nnxt);
+    env_state *t = cur; cur = nxt; nxt = t;
+    j = r + 1;
+  }
+  for (int64_t i = 0; i < ncur; i++) env_leaf(&e, cur[i].T, cur[i].lo, cur[i].hi);
+  for (int k = 0; k < 4; k++) { lo[k] = e.lo[k]; hi[k] = e.hi[k]; }
+  *leaves = e.leaves;
+  *flags = e.flags;
+  *impact = e.impact;
 }
 
 static int num_threads(int req) {
@@ -512,7 +748,13 @@ typedef struct {
   /* forward outputs */
   double *color, *Tf;
   int64_t *ncontrib;
-  int32_t *amb;
+  /* decision envelope (NULL: not wanted): the alive and near-cut records */
+  const sorted_rec *sr_env;
+  int64_t m_env;
+  double *env_lo, *env_hi; /* [npix][4] */
+  double *env_impact;
+  int64_t *env_leaves;
+  int32_t *env_flags;
   /* backward */
   const double *dl_dc;   /* [npix][3] */
   const double *rec;     /* sorted positions -> per Gaussian via order */
@@ -529,6 +771,9 @@ static void pixel_xy(const job *j, int64_t k, double *px, double *py) {
 
 static void *fwd_worker(void *arg) {
   job *j = arg;
+  const int64_t me = j->m_env > 0 ? j->m_env : 1, cap = j->s->max_leaves > 0 ? j->s->max_leaves : 1;
+  cand *cb = j->env_lo ? malloc(sizeof(cand) * me) : NULL;
+  env_state *sb = j->env_lo ? malloc(sizeof(env_state) * 2 * cap) : NULL;
   for (int64_t k = j->tid; k < j->npix; k += j->nthreads) {
     double px, py;
     pixel_xy(j, k, &px, &py);
@@ -537,33 +782,108 @@ static void *fwd_worker(void *arg) {
     for (int c = 0; c < 3; c++) j->color[3 * k + c] = o.color[c];
     j->Tf[k] = o.T;
     j->ncontrib[k] = o.ncontrib;
-    j->amb[k] = o.ambiguous;
+    if (j->env_lo) {
+      int fl;
+      pixel_envelope(j->sr_env, j->m_env, px, py, j->s, cb, sb, cap, j->env_lo + 4 * k, j->env_hi + 4 * k,
+                     j->env_leaves + k, &fl, j->env_impact + k);
+      j->env_flags[k] = fl;
+    }
   }
+  free(cb);
+  free(sb);
   return NULL;
 }
 
-/* Render the listed pixels (row-major ids j*W+i; all pixels if pix == NULL). */
+/* Shared by the two render entry points: walks the listed pixels (row-major
+ * ids j*W+i; all pixels if pix == NULL) over the sorted records; the envelope
+ * outputs may be NULL. */
+static int render_sorted(const sorted_rec *sr, int64_t m, const sorted_rec *sr_env, int64_t m_env,
+                         const orc_camera *cam, const orc_settings *s, int64_t npix, const int64_t *pix,
+                         double *color, double *T_final, int64_t *ncontrib, double *env_lo, double *env_hi,
+                         double *env_impact, int64_t *env_leaves, int32_t *env_flags, int nthreads_req) {
+  int nt = num_threads(nthreads_req);
+  pthread_t *th = malloc(sizeof(pthread_t) * nt);
+  job *jobs = calloc(nt, sizeof(job));
+  if (!th || !jobs) return -1;
+  for (int t = 0; t < nt; t++) {
+    job *jb = jobs + t;
+    jb->sr = sr; jb->m = m; jb->cam = cam; jb->s = s; jb->npix = npix; jb->pix = pix;
+    jb->nthreads = nt; jb->tid = t;
+    jb->color = color; jb->Tf = T_final; jb->ncontrib = ncontrib;
+    jb->sr_env = sr_env; jb->m_env = m_env;
+    jb->env_lo = env_lo; jb->env_hi = env_hi; jb->env_impact = env_impact;
+    jb->env_leaves = env_leaves; jb->env_flags = env_flags;
+    pthread_create(&th[t], NULL, fwd_worker, jb);
+  }
+  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+  free(th);
+  free(jobs);
+  return 0;
+}
+
+/* Render the listed pixels (row-major ids j*W+i; all pixels if pix == NULL).
+ * env_* (each NULL, or all given): the decision envelope per pixel, lo / hi
+ * [npix][4] (colour, final T), the impact bound, the number of finished
+ * outcome paths and the ENV_* flags.  Returns the number of Gaussians whose depth lies within the depth
+ * margin of z_near (their culling is a decision no envelope covers), or -1 if
+ * memory ran out. */
 int orc_render(int64_t n, const double *params, const orc_camera *cam, const orc_settings *s, int64_t npix,
-               const int64_t *pix, double *color, double *T_final, int64_t *ncontrib, int32_t *ambiguous,
-               int nthreads_req) {
+               const int64_t *pix, double *color, double *T_final, int64_t *ncontrib, double *env_lo,
+               double *env_hi, double *env_impact, int64_t *env_leaves, int32_t *env_flags, int nthreads_req) {
   sh_init();
   double *rec = malloc(sizeof(double) * NREC * (n > 0 ? n : 1));
   int64_t *order = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
   if (!rec || !order) return -1;
   orc_preprocess(n, params, cam, s, rec);
-  int64_t m = global_order(n, rec, order);
+  int64_t m = global_order(n, rec, order, 0);
   sorted_rec *sr = make_sorted(rec, order, m);
-  int nt = num_threads(nthreads_req);
-  pthread_t *th = malloc(sizeof(pthread_t) * nt);
-  job *jobs = malloc(sizeof(job) * nt);
-  for (int t = 0; t < nt; t++) {
-    job jb = {sr, m, cam, s, npix, pix, nt, t, color, T_final, ncontrib, ambiguous, NULL, NULL, NULL, NULL};
-    jobs[t] = jb;
-    pthread_create(&th[t], NULL, fwd_worker, &jobs[t]);
+  sorted_rec *sr_env = NULL;
+  int64_t m_env = 0, near_z = 0;
+  if (env_lo) {
+    m_env = global_order(n, rec, order, 1);
+    sr_env = make_sorted(rec, order, m_env);
   }
-  for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
-  free(th); free(jobs); free(sr); free(order); free(rec);
-  return 0;
+  for (int64_t i = 0; i < n; i++) near_z += rec[NREC * i + F_NEARCUT] == 2.0;
+  int rc = render_sorted(sr, m, sr_env, m_env, cam, s, npix, pix, color, T_final, ncontrib, env_lo, env_hi,
+                         env_impact, env_leaves, env_flags, nthreads_req);
+  free(sr_env); free(sr); free(order); free(rec);
+  return rc < 0 ? -1 : (int)near_z;
+}
+
+/* Render from given records instead of parameters (m Gaussians, any order;
+ * recs [m][11]: u, v, Qxx, Qxy, Qyy, alpha_cond, r, g, b, depth, alive), with
+ * the same outputs as orc_render.  Used to check the envelope: records moved
+ * within the margins must render inside the envelope of the unmoved ones. */
+int orc_render_records(int64_t m, const double *recs, const orc_camera *cam, const orc_settings *s, int64_t npix,
+                       const int64_t *pix, double *color, double *T_final, int64_t *ncontrib, double *env_lo,
+                       double *env_hi, double *env_impact, int64_t *env_leaves, int32_t *env_flags,
+                       int nthreads_req) {
+  double *rec = calloc((size_t)NREC * (m > 0 ? m : 1), sizeof(double));
+  int64_t *order = malloc(sizeof(int64_t) * (m > 0 ? m : 1));
+  if (!rec || !order) return -1;
+  for (int64_t i = 0; i < m; i++) {
+    const double *x = recs + 11 * i;
+    double *r = rec + NREC * i;
+    r[F_U] = x[0]; r[F_V] = x[1];
+    r[F_CONIC] = x[2]; r[F_CONIC + 1] = x[3]; r[F_CONIC + 2] = x[4];
+    r[F_ALPHAC] = x[5];
+    r[F_RGB] = x[6]; r[F_RGB + 1] = x[7]; r[F_RGB + 2] = x[8];
+    r[F_DEPTH] = x[9];
+    r[F_ALIVE] = x[10] != 0.0 && x[5] * 255.0 >= 1.0;
+    r[F_NEARCUT] = x[10] != 0.0 && !(x[5] * 255.0 >= 1.0) && x[5] * 255.0 * (1.0 + s->m_alpha) >= 1.0;
+  }
+  int64_t mm = global_order(m, rec, order, 0);
+  sorted_rec *sr = make_sorted(rec, order, mm);
+  sorted_rec *sr_env = NULL;
+  int64_t m_env = 0;
+  if (env_lo) {
+    m_env = global_order(m, rec, order, 1);
+    sr_env = make_sorted(rec, order, m_env);
+  }
+  int rc = render_sorted(sr, mm, sr_env, m_env, cam, s, npix, pix, color, T_final, ncontrib, env_lo, env_hi,
+                         env_impact, env_leaves, env_flags, nthreads_req);
+  free(sr_env); free(sr); free(order); free(rec);
+  return rc;
 }
 
 /* ----------------------------------------------------- backward: compositing */
@@ -779,7 +1099,11 @@ void orc_record_vjp(int64_t n, const double *params, const orc_camera *cam, cons
                     const double *g2d, double *grad) {
   sh_init();
   memset(grad, 0, sizeof(double) * NROWS * n);
-  for (int64_t i = 0; i < n; i++) record_vjp(params, n, i, cam, s, g2d + NG2D * i, grad);
+  for (int64_t i = 0; i < n; i++) {
+    int any = 0;
+    for (int c = 0; c < NG2D; c++) any |= g2d[NG2D * i + c] != 0.0;
+    if (any) record_vjp(params, n, i, cam, s, g2d + NG2D * i, grad); /* else it adds nothing */
+  }
 }
 
 /* Full backward for the listed pixels with upstream dL/dC ([npix][3]):
@@ -792,7 +1116,7 @@ int orc_backward(int64_t n, const double *params, const orc_camera *cam, const o
   int64_t *order = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
   if (!rec || !order) return -1;
   orc_preprocess(n, params, cam, s, rec);
-  int64_t m = global_order(n, rec, order);
+  int64_t m = global_order(n, rec, order, 0);
   sorted_rec *sr = make_sorted(rec, order, m);
   int nt = num_threads(nthreads_req);
   pthread_t *th = malloc(sizeof(pthread_t) * nt);
@@ -800,7 +1124,10 @@ int orc_backward(int64_t n, const double *params, const orc_camera *cam, const o
   double *acc = calloc((size_t)nt * NG2D * (n > 0 ? n : 1), sizeof(double));
   if (!acc) return -1;
   for (int t = 0; t < nt; t++) {
-    job jb = {sr, m, cam, s, npix, pix, nt, t, NULL, NULL, NULL, NULL, dl_dc, rec, order, acc + (size_t)t * NG2D * n};
+    job jb;
+    memset(&jb, 0, sizeof(jb));
+    jb.sr = sr; jb.m = m; jb.cam = cam; jb.s = s; jb.npix = npix; jb.pix = pix; jb.nthreads = nt; jb.tid = t;
+    jb.dl_dc = dl_dc; jb.rec = rec; jb.order = order; jb.g2d = acc + (size_t)t * NG2D * n;
     jobs[t] = jb;
     pthread_create(&th[t], NULL, bwd_worker, &jobs[t]);
   }

@@ -73,8 +73,8 @@ def lib():
         L.sixdgs_forward.argtypes = [P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
         L.sixdgs_build_cache.argtypes = [P, I64, P, P]
         L.sixdgs_forward_cached.argtypes = [P, P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
-        L.sixdgs_backward.argtypes = [P, P, I64, PP, P, P, P]
-        L.sixdgs_backward_adam.argtypes = [P, P, I64, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
+        L.sixdgs_backward.argtypes = [P, P, I64, I32, PP, P, P, P]
+        L.sixdgs_backward_adam.argtypes = [P, P, I64, I32, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
         L.sixdgs_adam_devstep.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, P, P]
@@ -161,6 +161,10 @@ class Context:
             raise SixDGSError(rc, "create failed (unsupported settings?)")
         self._h = h
         self.settings = s
+        # the last forward that left state for a backward: its number (forwards
+        # on this context count from 1; 0 = none) and image sizes
+        self.generation = 0
+        self._fwd_sizes = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -228,8 +232,11 @@ class Context:
             if im.numel() != 3 * int(c.width) * int(c.height):
                 raise ValueError("each image must hold 3*H*W floats")
         ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
+        self._fwd_sizes = None
         self._rc(lib().sixdgs_forward(self._h, ctypes.c_void_p(params.data_ptr()), n, ccams, len(cams),
                                       _ptrs(images), ctypes.c_void_p(_stream(stream))))
+        self.generation += 1
+        self._fwd_sizes = [3 * int(c.width) * int(c.height) for c in cams]
 
     def forward_cached(self, params, cache, cams, images, stream=None):
         """Render-only forward from an inference cache (see build_cache)."""
@@ -247,14 +254,29 @@ class Context:
             if im.numel() != 3 * int(c.width) * int(c.height):
                 raise ValueError("each image must hold 3*H*W floats")
         ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
+        self._fwd_sizes = None  # a render-only forward leaves no state for a backward
+        self.generation += 1
         self._rc(lib().sixdgs_forward_cached(self._h, ctypes.c_void_p(params.data_ptr()),
                                              ctypes.c_void_p(cache.data_ptr()), n, ccams, len(cams), _ptrs(images),
                                              ctypes.c_void_p(_stream(stream))))
+
+    def _check_upstream(self, dl_dimages):
+        """dL/dI must match the last forward's views one for one (the library
+        can check their count, not the sizes of the buffers behind them)."""
+        if self._fwd_sizes is None:
+            return  # the library reports the missing forward
+        if len(dl_dimages) != len(self._fwd_sizes):
+            raise ValueError(f"{len(dl_dimages)} dL/dI images for a forward of {len(self._fwd_sizes)} views")
+        for k, (t, want) in enumerate(zip(dl_dimages, self._fwd_sizes)):
+            _check_f32_cuda(t, "dl_dimage")
+            if t.numel() != want:
+                raise ValueError(f"dL/dI {k} holds {t.numel()} floats, its view {want}")
 
     def backward(self, params, dl_dimages, grad, densify=None, stream=None):
         n = params.shape[1]
         for t in dl_dimages:
             _check_f32_cuda(t, "dl_dimage")
+        self._check_upstream(dl_dimages)
         _check_f32_cuda(grad, "grad")
         if grad.shape != params.shape:
             raise ValueError("grad must have the shape of params")
@@ -263,7 +285,8 @@ class Context:
             if densify.numel() != 2 * n:
                 raise ValueError("densify must hold [2, N] floats")
         dens = ctypes.c_void_p(densify.data_ptr()) if densify is not None else None
-        self._rc(lib().sixdgs_backward(self._h, ctypes.c_void_p(params.data_ptr()), n, _ptrs(dl_dimages),
+        self._rc(lib().sixdgs_backward(self._h, ctypes.c_void_p(params.data_ptr()), n, len(dl_dimages),
+                                       _ptrs(dl_dimages),
                                        ctypes.c_void_p(grad.data_ptr()), dens, ctypes.c_void_p(_stream(stream))))
 
     def backward_adam(self, params, dl_dimages, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, densify=None,
@@ -271,6 +294,7 @@ class Context:
         n = params.shape[1]
         for t in dl_dimages:
             _check_f32_cuda(t, "dl_dimage")
+        self._check_upstream(dl_dimages)
         for t, nm in ((m, "m"), (v, "v")):
             _check_f32_cuda(t, nm)
             if t.shape != params.shape:
@@ -281,9 +305,12 @@ class Context:
                 raise ValueError("densify must hold [2, N] floats")
         lrs = (ctypes.c_float * 6)(*[float(x) for x in lr])
         dens = ctypes.c_void_p(densify.data_ptr()) if densify is not None else None
-        self._rc(lib().sixdgs_backward_adam(self._h, ctypes.c_void_p(params.data_ptr()), n, _ptrs(dl_dimages),
+        self._rc(lib().sixdgs_backward_adam(self._h, ctypes.c_void_p(params.data_ptr()), n, len(dl_dimages),
+                                            _ptrs(dl_dimages),
                                             ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), lrs,
                                             beta1, beta2, eps, int(step), dens, ctypes.c_void_p(_stream(stream))))
+        self._fwd_sizes = None  # the parameters moved: the forward's state is spent
+        self.generation += 1
 
     def l1_loss(self, images, targets, dl_dimages, loss, stream=None):
         for a, b, g in zip(images, targets, dl_dimages):
@@ -320,6 +347,8 @@ class Context:
         if not (alive.is_cuda and alive.dtype == torch.int32 and alive.numel() == n * len(cams)):
             raise ValueError("alive must be an int32 CUDA tensor of n * ncam entries")
         ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
+        self._fwd_sizes = None  # the binning replaces the forward's state
+        self.generation += 1
         self._rc(lib().sixdgs_bin(self._h, n, ccams, len(cams), *[ctypes.c_void_p(t.data_ptr()) for t in
                                                                    (u, v, ex, ey, depth, alive)],
                                   ctypes.c_void_p(_stream(stream))))

@@ -569,13 +569,14 @@ sixdgs_status sixdgs_forward_cached(sixdgs_ctx* c, const float* params, const fl
   return forward_impl(c, params, cache, n, cams, ncam, images, true, stream);
 }
 
-sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, const float* const* dl_dimages,
-                              float* grad, float* densify, void* stream) {
+sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, int32_t ncam,
+                              const float* const* dl_dimages, float* grad, float* densify, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
   if (params != c->fwd_params || n != c->fwd_n)
     return fail(c, SIXDGS_ERR_STATE, "params / n differ from the last forward");
+  if (ncam != c->vt.nview) return fail(c, SIXDGS_ERR_INVALID_ARG, "ncam differs from the last forward's");
   if (!dl_dimages) return fail(c, SIXDGS_ERR_INVALID_ARG, "dl_dimages is NULL");
   if (n > 0 && !grad) return fail(c, SIXDGS_ERR_INVALID_ARG, "grad is NULL");
   ViewTable vt = c->vt;
@@ -605,14 +606,15 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, con
   return check_launch(c, "preprocess backward");
 }
 
-sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, const float* const* dl_dimages,
-                                   float* m, float* v, const float* lr, float beta1, float beta2, float eps,
-                                   int32_t step, float* densify, void* stream) {
+sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, int32_t ncam,
+                                   const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
+                                   float beta2, float eps, int32_t step, float* densify, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
   if (params != c->fwd_params || n != c->fwd_n)
     return fail(c, SIXDGS_ERR_STATE, "params / n differ from the last forward");
+  if (ncam != c->vt.nview) return fail(c, SIXDGS_ERR_INVALID_ARG, "ncam differs from the last forward's");
   if (!dl_dimages || !lr) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
   if (n > 0 && (!m || !v)) return fail(c, SIXDGS_ERR_INVALID_ARG, "m or v is NULL");
   if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))

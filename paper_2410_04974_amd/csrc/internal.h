@@ -221,6 +221,8 @@ void launch_density_apply(const float* params, const float* m, const float* v, c
                           float* vo, float* lo, int64_t n_out, hipStream_t st);
 
 // train.hip
+// Workgroups of the L1 kernel per image at most (one partial sum each).
+constexpr int kL1MaxBlocks = 1024;
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,
                float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
 int64_t l1_partial_count(int nimg, const int64_t* numel);

@@ -6,7 +6,6 @@
 namespace sixdgs {
 namespace {
 
-constexpr int kL1MaxBlocks = 1024;
 constexpr int kL1PerThread = 4;
 
 __device__ __forceinline__ float block_sum(float v) {

@@ -60,7 +60,10 @@ class Render6D(torch.autograd.Function):
 
     params is a contiguous float32 CUDA tensor [76, N] (layout in include/sixdgs.h).
     Returns one [3, H, W] image per camera.  The renderer keeps the state the
-    backward needs, so a renderer serves one forward/backward pair at a time."""
+    backward needs, so a renderer serves one forward/backward pair at a time:
+    the backward of an output whose renderer has rendered again since raises
+    instead of differentiating the later forward (use one renderer per pending
+    backward)."""
 
     @staticmethod
     def forward(ctx, params, renderer, cams):
@@ -68,11 +71,15 @@ class Render6D(torch.autograd.Function):
         imgs = renderer.forward(params, cams)
         ctx.renderer = renderer
         ctx.cams = cams
+        ctx.generation = renderer.ctx.generation
         ctx.save_for_backward(params)
         return tuple(imgs)
 
     @staticmethod
     def backward(ctx, *grads):
+        if ctx.renderer.ctx.generation != ctx.generation:
+            raise RuntimeError("this render's renderer has run another forward since; its backward state is "
+                               "gone (use one Renderer per pending backward)")
         (params,) = ctx.saved_tensors
         dl = [g.contiguous() if g is not None else
               torch.zeros((3, c.height, c.width), device=params.device, dtype=torch.float32)

@@ -1,0 +1,147 @@
+"""Argument and state checks of the C ABI, called through ctypes: every bad
+call returns its status before anything is launched and leaves the outputs
+as they were; a backward is tied to the forward whose state it consumes."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2410_04974_amd import _lib
+    return _lib
+
+
+def _cams(L, cams):
+    return (L.Camera * len(cams))(*[L.to_camera(c) for c in cams])
+
+
+def _forward_status(L, ctx, p, n, ccams, ncam, images):
+    return L.lib().sixdgs_forward(ctx._h, ctypes.c_void_p(p.data_ptr()), n, ccams, ncam, images,
+                                  ctypes.c_void_p(L._stream(None)))
+
+
+def test_forward_rejects_bad_arguments_before_any_launch(L):
+    w, pn = G.scene("c0", 200)
+    p = G.to_dev(pn)
+    cam = synth.default_camera(48, 32)
+    ctx = L.Context()
+    img = torch.full((3, 32, 48), 7.0, device=G.DEV)
+    imgs = L._ptrs([img])
+    good = _cams(L, [cam])
+    assert _forward_status(L, ctx, p, pn.shape[1], good, 1, imgs) == L.OK
+    torch.cuda.synchronize()
+    ref = img.clone()
+    img.fill_(7.0)
+
+    def bad_cam(**kw):
+        c = L.to_camera(cam)
+        for k, v in kw.items():
+            if k in ("R", "t"):
+                getattr(c, k)[0] = v
+            else:
+                setattr(c, k, v)
+        return (L.Camera * 1)(c)
+
+    cases = {
+        "null cams": (None, 1, imgs),
+        "ncam 0": (good, 0, imgs),
+        "ncam above the maximum": (_cams(L, [cam] * (L.MAX_VIEWS + 1)), L.MAX_VIEWS + 1,
+                                   L._ptrs([img] * (L.MAX_VIEWS + 1))),
+        "null image array": (good, 1, None),
+        "null image": (good, 1, (ctypes.c_void_p * 1)(None)),
+        "non-finite rotation": (bad_cam(R=math.nan), 1, imgs),
+        "non-finite translation": (bad_cam(t=math.inf), 1, imgs),
+        "zero focal length": (bad_cam(fx=0.0), 1, imgs),
+        "non-finite principal point": (bad_cam(cx=math.nan), 1, imgs),
+        "zero width": (bad_cam(width=0), 1, imgs),
+        "negative height": (bad_cam(height=-4), 1, imgs),
+        "oversized image": (bad_cam(width=20000), 1, imgs),
+    }
+    for name, (cc, ncam, ims) in cases.items():
+        rc = _forward_status(L, ctx, p, pn.shape[1], cc, ncam, ims)
+        assert rc == L.ERR_INVALID_ARG, name
+        assert L.lib().sixdgs_last_error(ctx._h)  # a message
+    rc = L.lib().sixdgs_forward(ctx._h, None, 5, good, 1, imgs, ctypes.c_void_p(L._stream(None)))
+    assert rc == L.ERR_INVALID_ARG  # NULL params with n > 0
+    rc = L.lib().sixdgs_forward(ctx._h, ctypes.c_void_p(p.data_ptr()), -1, good, 1, imgs,
+                                ctypes.c_void_p(L._stream(None)))
+    assert rc == L.ERR_INVALID_ARG  # negative n
+    torch.cuda.synchronize()
+    assert bool((img == 7.0).all())  # nothing was written
+    # a rejected call changes nothing: the state of the last good forward still serves its backward
+    dl = torch.ones_like(img)
+    g = torch.zeros_like(p)
+    rc = L.lib().sixdgs_backward(ctx._h, ctypes.c_void_p(p.data_ptr()), pn.shape[1], 1, L._ptrs([dl]),
+                                 ctypes.c_void_p(g.data_ptr()), None, ctypes.c_void_p(L._stream(None)))
+    assert rc == L.OK
+    g_ref = torch.zeros_like(p)
+    ctx2 = L.Context()
+    ctx2.forward(p, [cam], [torch.empty_like(img)])
+    ctx2.backward(p, [dl], g_ref)
+    torch.cuda.synchronize()
+    assert torch.allclose(g, g_ref, rtol=1e-5, atol=1e-6 * float(g_ref.abs().max()))
+    # and the context still renders
+    assert _forward_status(L, ctx, p, pn.shape[1], good, 1, imgs) == L.OK
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref)
+    # a context that never rendered has no state for a backward
+    ctx3 = L.Context()
+    rc = L.lib().sixdgs_backward(ctx3._h, ctypes.c_void_p(p.data_ptr()), pn.shape[1], 1, L._ptrs([dl]),
+                                 ctypes.c_void_p(g.data_ptr()), None, ctypes.c_void_p(L._stream(None)))
+    assert rc == L.ERR_STATE
+
+
+def test_backward_view_count_must_match_the_forward(L):
+    w, pn = G.scene("c0", 300)
+    p = G.to_dev(pn)
+    cams = [synth.default_camera(40, 32), synth.default_camera(24, 24)]
+    ctx = L.Context()
+    imgs = [torch.empty((3, c.height, c.width), device=G.DEV) for c in cams]
+    ctx.forward(p, cams, imgs)
+    dls = [torch.ones_like(i) for i in imgs]
+    g = torch.full_like(p, 3.0)
+    for ncam in (1, 3):
+        rc = L.lib().sixdgs_backward(ctx._h, ctypes.c_void_p(p.data_ptr()), pn.shape[1], ncam,
+                                     L._ptrs(dls + dls[:1]), ctypes.c_void_p(g.data_ptr()), None,
+                                     ctypes.c_void_p(L._stream(None)))
+        assert rc == L.ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((g == 3.0).all())
+    # the binding checks the count and every buffer's size against the forward's views
+    with pytest.raises(ValueError):
+        ctx.backward(p, dls[:1], g)
+    with pytest.raises(ValueError):
+        ctx.backward(p, [dls[1], dls[0]], g)
+    ctx.backward(p, dls, g)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(g).all()) and not bool((g == 3.0).all())
+
+
+def test_stale_autograd_backward_raises_instead_of_using_a_later_forward(L):
+    """Two renders on one renderer before backward: the first render's backward
+    would find the second's state, so it raises; the second's is exact."""
+    from paper_2410_04974_amd import Renderer, render
+    w, pn = G.scene("c1", 3000)
+    cam_a, cam_b = synth.default_camera(64, 48), synth.default_camera(32, 32)
+    p = G.to_dev(pn).requires_grad_(True)
+    r = Renderer()
+    (ia,) = render(p, r, [cam_a])
+    (ib,) = render(p, r, [cam_b])
+    ib.sum().backward()
+    g_b = p.grad.clone()
+    p.grad = None
+    with pytest.raises(RuntimeError):
+        ia.sum().backward()
+    # the same gradient from a renderer of its own
+    (ib2,) = render(p, Renderer(), [cam_b])
+    ib2.sum().backward()
+    assert torch.allclose(p.grad, g_b, rtol=1e-5, atol=1e-6 * float(g_b.abs().max()))

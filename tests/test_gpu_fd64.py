@@ -3,7 +3,8 @@ FP64 central finite differences of the oracle's forward, on a seeded subset
 of 64 alive Gaussians.
 
 The upstream gradient dL/dI ~ N(0, 1) lives on a 64x64 window of the image
-(zero elsewhere and on pixels the oracle flags as ambiguous), so a
+(zero elsewhere and on pixels where a threshold decision of the walk is
+undecided in float32, the oracle's decision envelope), so a
 perturbation of one Gaussian only changes the loss through the window pixels
 inside that Gaussian's extent box; the oracle renders exactly those pixels,
 brute force over all 100k Gaussians.  Each Gaussian gets 4 of its 76
@@ -34,7 +35,7 @@ def test_gradient_matches_fp64_finite_differences_on_64_gaussians():
     x0, y0, ww, wh = WIN
     jj, ii = np.mgrid[y0:y0 + wh, x0:x0 + ww]
     win = (jj * W + ii).reshape(-1)
-    _, _, _, amb = oracle.render(pn, cam, pixels=win)
+    amb = G.grad_mask(oracle.render_envelope(pn, cam, pixels=win))
     rng = np.random.default_rng(synth.SEED_UPSTREAM)
     dl_win = rng.normal(size=(len(win), 3))
     dl_win[amb] = 0.0
@@ -50,8 +51,8 @@ def test_gradient_matches_fp64_finite_differences_on_64_gaussians():
     near = np.nonzero(rec["alive"] & (rec["u"] + rec["ex"] > x0 - m) & (rec["u"] - rec["ex"] < x0 + ww + m) &
                       (rec["v"] + rec["ey"] > y0 - m) & (rec["v"] - rec["ey"] < y0 + wh + m))[0]
     sub = pn[:, near].astype(np.float64)  # index order kept: same depth tie-breaks
-    col_full, _, _, _ = oracle.render(pn, cam, pixels=win)
-    col_sub, _, _, _ = oracle.render(sub, cam, pixels=win)
+    col_full, _, _ = oracle.render_plain(pn, cam, pixels=win)
+    col_sub, _, _ = oracle.render_plain(sub, cam, pixels=win)
     assert np.abs(col_full - col_sub).max() < 1e-12  # the reduced scene is the same function on the window
     cand = np.nonzero(rec["alive"][near] & (rec["u"][near] + rec["ex"][near] > x0) &
                       (rec["u"][near] - rec["ex"][near] < x0 + ww) & (rec["v"][near] + rec["ey"][near] > y0) &
@@ -60,7 +61,7 @@ def test_gradient_matches_fp64_finite_differences_on_64_gaussians():
     dl_map = {int(k): dl_win[i] for i, k in enumerate(win)}
 
     def local_loss(params, pixels):
-        col, _, _, _ = oracle.render(params, cam, pixels=pixels)
+        col, _, _ = oracle.render_plain(params, cam, pixels=pixels)
         return float(sum((col[k] * dl_map[int(px)]).sum() for k, px in enumerate(pixels)))
 
     fd, an, rows_used = [], [], []

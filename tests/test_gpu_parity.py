@@ -4,9 +4,13 @@ same seeded inputs.
 Bars (derived from float32 arithmetic against float64, see the design notes):
   * integer stage (tile counts, keys, order, ranges) bit-exact given the same
     float32 records;
-  * pixels within 1e-4 absolute everywhere the oracle does not flag a
-    threshold decision as ambiguous;
-  * gradients within 1e-3 relative (norm per parameter group).
+  * records within the float32 error bounds the oracle's decision envelope
+    assumes;
+  * every pixel inside its decision envelope up to 1e-4 absolute (the
+    definition's value itself where no threshold decision is undecided);
+  * gradients within 1e-3 relative (norm per parameter group, and per element
+    against a floor of 1e-2 of the group's largest), with the upstream
+    gradient zeroed where an undecided decision could move a term.
 """
 import math
 
@@ -20,7 +24,7 @@ from tests import _gpu as G
 
 pytestmark = pytest.mark.gpu
 
-PIX_TOL = 1e-4
+PIX_TOL = G.PIX_TOL
 
 
 def _say(*a):
@@ -36,40 +40,54 @@ def _device():
 
 
 # ------------------------------------------------------------------ records
-@pytest.mark.parametrize("name,n", [("c0", None), ("c1", 20000), ("c2", 20000)])
-def test_records_match_oracle(name, n):
+def _conic_metric_error(gpu, ref):
+    """max |x^T (Q_gpu - Q) x| / x^T Q x over x: the conic's error in its own
+    metric (the largest |eigenvalue| of Q^-1 (Q_gpu - Q))."""
+    m = len(ref)
+    Q = np.zeros((m, 2, 2))
+    dQ = np.zeros((m, 2, 2))
+    Q[:, 0, 0], Q[:, 0, 1], Q[:, 1, 0], Q[:, 1, 1] = ref[:, 0], ref[:, 1], ref[:, 1], ref[:, 2]
+    g = gpu.astype(np.float64) - ref
+    dQ[:, 0, 0], dQ[:, 0, 1], dQ[:, 1, 0], dQ[:, 1, 1] = g[:, 0], g[:, 1], g[:, 1], g[:, 2]
+    return np.abs(np.linalg.eigvals(np.linalg.solve(Q, dQ))).max(axis=1)
+
+
+@pytest.mark.parametrize("name,n,view", [("c0", None, 0), ("c1", None, 0), ("c2", None, 0), ("r1", None, 0),
+                                         ("r2", None, 0), ("c4", None, 5)])
+def test_records_match_oracle(name, n, view):
+    """The GPU's float32 records against the FP64 ones at full size, and within
+    the float32 error bounds that the oracle's decision envelope assumes (so
+    the envelope covers every decision the GPU can take the other way)."""
     w, p = G.scene(name, n)
-    cam = w.cameras[0]
+    cam = w.cameras[view]
     r, _, _ = G.render(p, [cam])
     rec, tiles = G.records(r)
     o = oracle.preprocess(p, cam)
+    st = oracle.Settings()
     alive_o = o["alive"]
     binned = tiles > 0
-    # every GPU-binned entry is alive for the oracle (up to threshold cases)
+    # an entry binned on one side only is one the envelope treats as near the cut
+    one_side = binned ^ alive_o
+    assert (o["near_cut"][one_side & ~alive_o] == 1).all()
     both = binned & alive_o
-    _say(name, "binned", binned.sum(), "oracle alive", alive_o.sum(), "both", both.sum())
+    _say(name, "binned", binned.sum(), "oracle alive", alive_o.sum(), "one side only", one_side.sum())
     assert both.sum() >= 0.999 * binned.sum()
     e = {}
-    e["u"] = np.abs(rec[both, G.REC_U] - o["u"][both]).max()
-    e["v"] = np.abs(rec[both, G.REC_V] - o["v"][both]).max()
-    for k, col in (("Qxx", G.REC_QXX), ("Qxy", G.REC_QXY), ("Qyy", G.REC_QYY)):
-        ref = o["conic"][both, {"Qxx": 0, "Qxy": 1, "Qyy": 2}[k]]
-        scale = np.maximum(np.abs(o["conic"][both, 0]), np.abs(o["conic"][both, 2]))
-        e[k] = (np.abs(rec[both, col] - ref) / scale).max()
-    e["alpha_c"] = G.rel_err(rec[both, G.REC_AC], o["alpha_cond"][both], 1e-6).max()
+    e["uv"] = max(np.abs(rec[both, G.REC_U] - o["u"][both]).max(), np.abs(rec[both, G.REC_V] - o["v"][both]).max())
+    e["conic"] = _conic_metric_error(rec[both][:, [G.REC_QXX, G.REC_QXY, G.REC_QYY]], o["conic"][both]).max()
+    e["alpha_c"] = G.rel_err(rec[both, G.REC_AC], o["alpha_cond"][both], 1e-30).max()
     e["rgb"] = np.abs(rec[both][:, [G.REC_R, G.REC_G, G.REC_B]] - o["rgb"][both]).max()
-    e["depth"] = G.rel_err(rec[both, G.REC_DEPTH], o["depth"][both], 1e-6).max()
+    e["depth"] = G.rel_err(rec[both, G.REC_DEPTH], o["depth"][both], 1e-30).max()
     # the extents are sqrt(q_max * Sigma2D_xx) with q_max = 2 ln(255 alpha_cond): compare the
     # q_max they imply (its absolute error, unlike the extent's relative one, stays bounded as
     # alpha_cond approaches 1/255)
     e["qmax_x"] = (np.abs(rec[both, G.REC_EX].astype(np.float64) ** 2 - o["ex"][both] ** 2) / o["cov2d"][both, 0]).max()
     e["qmax_y"] = (np.abs(rec[both, G.REC_EY].astype(np.float64) ** 2 - o["ey"][both] ** 2) / o["cov2d"][both, 2]).max()
-    _say(name, {k: f"{v:.2e}" for k, v in e.items()})
-    assert e["u"] < 2e-3 and e["v"] < 2e-3
-    assert max(e["Qxx"], e["Qxy"], e["Qyy"]) < 2e-4
-    assert e["alpha_c"] < 2e-5
-    assert e["rgb"] < 2e-6
-    assert e["depth"] < 1e-6
+    bounds = {"uv": st.uv_margin(cam), "conic": st.m_conic, "alpha_c": st.m_alpha, "depth": st.m_depth}
+    _say(name, {k: f"{v:.2e}" + (f" (bound {bounds[k]:.1e})" if k in bounds else "") for k, v in e.items()})
+    for k, b in bounds.items():
+        assert e[k] <= b, (k, e[k], b)
+    assert e["rgb"] < 1e-6
     assert max(e["qmax_x"], e["qmax_y"]) < 1e-4
 
 
@@ -193,17 +211,6 @@ def test_pair_overflow_at_fixed_capacity_is_reported_and_renders_background():
 
 
 # ------------------------------------------------------------------ forward
-def _compare_pixels(img, T, ref_img, ref_T, amb, tag):
-    ok = ~amb
-    err = np.abs(img - ref_img).max(axis=0)
-    terr = np.abs(T - ref_T)
-    _say(tag, "max err (non-ambiguous)", f"{err[ok].max():.2e}", "T err", f"{terr[ok].max():.2e}",
-         "ambiguous frac", f"{amb.mean():.4f}", "max err on ambiguous", f"{err[amb].max() if amb.any() else 0:.2e}")
-    assert err[ok].max() < PIX_TOL
-    assert terr[ok].max() < PIX_TOL
-    return err
-
-
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
 def test_forward_full_frame_c0(tile):
     w, p = G.scene("c0")
@@ -212,37 +219,53 @@ def test_forward_full_frame_c0(tile):
     from paper_2410_04974_amd import _lib
     T = r.ctx.export(_lib.EXPORT_T_FINAL).reshape(cam.height, cam.width)
     cnt = r.ctx.export(_lib.EXPORT_COUNTS).reshape(cam.height, cam.width)
-    ref, refT, refn, amb = oracle.render(p, cam)
-    _compare_pixels(imgs[0], T, ref, refT, amb, f"c0 {tile}")
-    assert np.array_equal(cnt[~amb], refn[~amb])
+    env = oracle.render_envelope(p, cam)
+    G.check_envelope(imgs[0], T, env, f"c0 {tile}", _say)
+    ok = ~env["ambiguous"]
+    assert np.array_equal(cnt[ok], env["ncontrib"][ok])
 
 
 def test_forward_ragged_multi_tile_scene_with_background():
     """Image sizes that are not tile multiples, a non-zero background and a
-    scene dense enough to fill many tiles."""
+    scene dense enough to fill many tiles; every pixel checked."""
     w, p = G.scene("c1", 30000)
     cam = synth.default_camera(203, 150)
     st = oracle.Settings(bg=(0.25, 0.5, 1.0))
     r, _, imgs = G.render(p, [cam], bg=st.bg)
     from paper_2410_04974_amd import _lib
     T = r.ctx.export(_lib.EXPORT_T_FINAL).reshape(cam.height, cam.width)
-    ref, refT, _, amb = oracle.render(p, cam, st)
-    _compare_pixels(imgs[0], T, ref, refT, amb, "ragged")
+    G.check_envelope(imgs[0], T, oracle.render_envelope(p, cam, st), "ragged", _say)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "r1", "r2"])
 def test_forward_sampled_pixels_full_size(name):
-    """Full-size workload, 4096 seeded pixels against the oracle."""
+    """Full-size workload, 4096 seeded pixels against the oracle, each inside
+    its decision envelope."""
     w, p = G.scene(name)
     cam = w.cameras[0]
     r, _, imgs = G.render(p, [cam])
     from paper_2410_04974_amd import _lib
     T = r.ctx.export(_lib.EXPORT_T_FINAL)
     pix = synth.pixel_subset(cam.width, cam.height, 4096)
-    ref, refT, _, amb = oracle.render(p, cam, pixels=pix)
+    env = oracle.render_envelope(p, cam, pixels=pix)
     img = imgs[0].reshape(3, -1)[:, pix]
-    _compare_pixels(img, T[pix], ref.T, refT, amb, name)
-    assert amb.mean() < 0.15
+    st = G.check_envelope(img, T[pix], env, name, _say)
+    # a loosened check (an envelope wider than the bar) on a small minority only
+    assert st["width_gt_tol_frac"] < 0.03
+
+
+def test_forward_sampled_pixels_c4_view():
+    """One 1920x1080 view of the 1M-Gaussian mixed scene (near Gaussians of the
+    cube part, the widest depth range of the workloads)."""
+    w, p = G.scene("c4")
+    cam = w.cameras[5]
+    r, _, imgs = G.render(p, [cam])
+    from paper_2410_04974_amd import _lib
+    T = r.ctx.export(_lib.EXPORT_T_FINAL)
+    pix = synth.pixel_subset(cam.width, cam.height, 4096)
+    env = oracle.render_envelope(p, cam, pixels=pix)
+    st = G.check_envelope(imgs[0].reshape(3, -1)[:, pix], T[pix], env, "c4 view 5", _say)
+    assert st["width_gt_tol_frac"] < 0.03
 
 
 def test_forward_tile_shapes_bitwise_equal():
@@ -270,15 +293,60 @@ def _group_errors(g, ref):
 def test_backward_matches_oracle_gradient(name, n, size):
     w, p = G.scene(name, n)
     cam = synth.default_camera(*size)
-    ref_img, _, _, amb = oracle.render(p, cam)
+    env = oracle.render_envelope(p, cam)
     dl = synth.upstream_gradient([cam])[0].astype(np.float64)
-    dl[:, amb] = 0.0  # no gradient through pixels whose threshold decisions may legitimately differ
+    skip = G.grad_mask(env)
+    dl[:, skip] = 0.0  # no gradient through pixels with an undecided threshold decision
     r, pt, _ = G.render(p, [cam])
     g = r.backward(pt, [torch.from_numpy(dl.astype(np.float32)).to(G.DEV)]).cpu().numpy().astype(np.float64)
     ref, _ = oracle.backward(p, cam, dl)
     errs = _group_errors(g, ref)
-    _say(name, "grad rel err per group", {k: f"{v:.2e}" for k, v in errs.items()})
+    _say(name, "pixels left out", f"{skip.mean():.4f}", "grad rel err per group", {k: f"{v:.2e}" for k, v in errs.items()})
     assert all(v < 1e-3 for v in errs.values())
+
+
+def _element_errors(g, ref):
+    """Per-element error against 1e-3 max(|g*|, 1e-2 max|g*|) per parameter group."""
+    out = {}
+    for nm, (a, b) in {"mu_p": (0, 3), "mu_d": (3, 6), "L": (6, 27), "sh": (27, 75), "opacity": (75, 76)}.items():
+        r = ref[a:b]
+        bar = 1e-3 * np.maximum(np.abs(r), 1e-2 * np.abs(r).max())
+        out[nm] = float((np.abs(g[a:b] - r) / bar).max())
+    return out
+
+
+@pytest.mark.parametrize("name", ["c2", "c1"])
+def test_backward_full_size_sampled_pixels_match_oracle(name):
+    """The benchmarked configuration at full size: 300k Gaussians (c2: strong
+    spatial-direction coupling, L_dp raw N(0, 0.3)) at 800x800 with the
+    automatic batch depth and chunk (128 / 128: heavy tiles span dozens of
+    backward work items restarted from forward-saved state).  dL/dI is
+    non-zero on the seeded sample of 4096 pixels only, and zero on those of
+    them with any undecided threshold decision (the gradient there depends on
+    which way float32 takes it); the 76-row gradient is compared with the
+    oracle's analytic gradient of the same pixels, per group and per element."""
+    w, p = G.scene(name)
+    cam = w.cameras[0]
+    pix = synth.pixel_subset(cam.width, cam.height, 4096)
+    env = oracle.render_envelope(p, cam, pixels=pix)
+    keep = ~G.grad_mask(env)
+    rng = np.random.default_rng(synth.SEED_UPSTREAM)
+    dsub = (rng.normal(0.0, 1.0, (len(pix), 3)) * keep[:, None]).astype(np.float32)
+    dl = np.zeros((3, cam.height * cam.width), np.float32)
+    dl[:, pix] = dsub.T
+    r, pt, _ = G.render(p, [cam])
+    sz = r.ctx.sizes()
+    g = r.backward(pt, [torch.from_numpy(dl.reshape(3, cam.height, cam.width)).to(G.DEV)]).cpu().numpy()
+    g = g.astype(np.float64)
+    ref, _ = oracle.backward(p, cam, dsub.astype(np.float64), pixels=pix)
+    errs = _group_errors(g, ref)
+    el = _element_errors(g, ref)
+    _say(name, "batch/chunk", sz["batch"], sz["chunk"], "pixels used", int(keep.sum()),
+         "group", {k: f"{v:.1e}" for k, v in errs.items()}, "element / bar", {k: f"{v:.2f}" for k, v in el.items()})
+    assert (sz["batch"], sz["chunk"]) == (128, 128)
+    assert keep.sum() > 2048
+    assert all(v < 1e-3 for v in errs.values())
+    assert all(v <= 1.0 for v in el.values())
 
 
 @pytest.mark.parametrize("name,batch", [("c1", 256), ("c1", 64), ("c1", 0), ("c2", 0)])

@@ -93,7 +93,7 @@ def test_densify_statistics_match_oracle():
     dls = synth.upstream_gradient(cams)
     ambs = []
     for c, dl in zip(cams, dls):
-        _, _, _, amb = oracle.render(pn, c)
+        amb = G.grad_mask(oracle.render_envelope(pn, c))
         dl[:, amb] = 0.0
         ambs.append(amb)
     dens = torch.zeros((2, pn.shape[1]), device=G.DEV)
