@@ -57,8 +57,20 @@ def test_gradient_matches_fp64_finite_differences_on_64_gaussians():
     cand = np.nonzero(rec["alive"][near] & (rec["u"][near] + rec["ex"][near] > x0) &
                       (rec["u"][near] - rec["ex"][near] < x0 + ww) & (rec["v"][near] + rec["ey"][near] > y0) &
                       (rec["v"][near] - rec["ey"][near] < y0 + wh))[0]
-    pick = np.sort(np.random.default_rng(synth.SEED_FD_SUBSET).choice(cand, 64, replace=False))
     dl_map = {int(k): dl_win[i] for i, k in enumerate(win)}
+    px = ii.reshape(-1) + 0.5
+    py = jj.reshape(-1) + 0.5
+    live = np.array([np.any(dl_map[int(k)] != 0) for k in win])
+
+    def box_pixels(gi):
+        """Window pixels with an upstream gradient inside the (slightly grown) extent box of Gaussian gi."""
+        bx0, bx1 = rec["u"][gi] - rec["ex"][gi] - 2, rec["u"][gi] + rec["ex"][gi] + 2
+        by0, by1 = rec["v"][gi] - rec["ey"][gi] - 2, rec["v"][gi] + rec["ey"][gi] + 2
+        return win[live & (px >= bx0) & (px <= bx1) & (py >= by0) & (py <= by1)]
+
+    # the subset is drawn from the Gaussians that reach a window pixel with an upstream gradient
+    cand = np.array([si for si in cand if len(box_pixels(near[si])) > 0])
+    pick = np.sort(np.random.default_rng(synth.SEED_FD_SUBSET).choice(cand, 64, replace=False))
 
     def local_loss(params, pixels):
         col, _, _ = oracle.render_plain(params, cam, pixels=pixels)
@@ -68,15 +80,7 @@ def test_gradient_matches_fp64_finite_differences_on_64_gaussians():
     discarded = 0
     for k, si in enumerate(pick):
         gi = near[si]  # index in the full scene
-        # window pixels inside the (slightly grown) extent box of this Gaussian
-        bx0, bx1 = rec["u"][gi] - rec["ex"][gi] - 2, rec["u"][gi] + rec["ex"][gi] + 2
-        by0, by1 = rec["v"][gi] - rec["ey"][gi] - 2, rec["v"][gi] + rec["ey"][gi] + 2
-        px = ii.reshape(-1) + 0.5
-        py = jj.reshape(-1) + 0.5
-        sel = win[(px >= bx0) & (px <= bx1) & (py >= by0) & (py <= by1)]
-        sel = np.array([s for s in sel if np.any(dl_map[int(s)] != 0)], np.int64)
-        if len(sel) == 0:
-            continue
+        sel = box_pixels(gi)
         for j in range(4):
             row = (4 * k + j) % 76
             base = float(sub[row, si])
