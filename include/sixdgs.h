@@ -246,6 +246,22 @@ sixdgs_status sixdgs_densify_apply(sixdgs_ctx* ctx, const float* params, const f
 sixdgs_status sixdgs_l1_loss(sixdgs_ctx* ctx, int32_t nimg, const float* const* images, const float* const* targets,
                              const int64_t* numel, float* const* dl_dimages, float* loss, void* stream);
 
+/* sixdgs_l1_loss without a context and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * asynchrony as sixdgs_l1_loss.  Its scratch (the per-workgroup partial sums)
+ * is a fixed 64 KiB array in device memory of every GPU the library runs on,
+ * held until the process ends, sized for the largest call (SIXDGS_MAX_VIEWS
+ * images of any size): a call never needs more (it returns
+ * SIXDGS_ERR_CAPACITY if it ever would, before any launch).  The array is
+ * shared by all calls on one GPU and keeps the last call's contents; calls
+ * whose executions overlap on one GPU (different streams, or different host
+ * threads, without ordering between them) race on it, so order them.
+ * INVALID_ARG as sixdgs_l1_loss; SIXDGS_ERR_HIP if the array's device address
+ * cannot be looked up or the launch fails. */
+sixdgs_status sixdgs_l1_loss_noalloc(int32_t nimg, const float* const* images, const float* const* targets,
+                                     const int64_t* numel, float* const* dl_dimages, float* loss, void* stream);
+
 /* The full 3DGS photometric loss (Sec. 4.4, Sec. 5.1: the paper keeps it):
  * loss = (1 - lambda_dssim) L1 + lambda_dssim (1 - SSIM) over nimg
  * (1..SIXDGS_MAX_VIEWS) views, both terms means over every channel and pixel

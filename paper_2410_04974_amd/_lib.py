@@ -76,6 +76,7 @@ def lib():
         L.sixdgs_backward.argtypes = [P, P, I64, I32, PP, P, P, P]
         L.sixdgs_backward_adam.argtypes = [P, P, I64, I32, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
+        L.sixdgs_l1_loss_noalloc.argtypes = [I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
         L.sixdgs_adam_devstep.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, P, P]
         L.sixdgs_adam_vec.argtypes = [P, P, P, P, I64, F, F, F, F, I32, P, P]
@@ -91,7 +92,7 @@ def lib():
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
                      "sixdgs_build_cache", "sixdgs_forward_cached",
-                     "sixdgs_backward_adam", "sixdgs_l1_loss",
+                     "sixdgs_backward_adam", "sixdgs_l1_loss", "sixdgs_l1_loss_noalloc",
                      "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check",
                      "sixdgs_set_timing",
                      "sixdgs_kernel_time"):
@@ -102,7 +103,7 @@ def lib():
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
             "sixdgs_last_error", "sixdgs_forward", "sixdgs_build_cache", "sixdgs_forward_cached",
-            "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss",
+            "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss", "sixdgs_l1_loss_noalloc",
             "sixdgs_l1_dssim_loss",
             "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_decompose",
             "sixdgs_densify_plan", "sixdgs_densify_apply", "sixdgs_bin",
@@ -441,6 +442,24 @@ def build_cache(params, out=None, stream=None):
     if rc != OK:
         raise SixDGSError(rc, "build_cache failed (bad arguments)")
     return cache
+
+
+def l1_loss_noalloc(images, targets, dl_dimages, loss, stream=None):
+    """sixdgs_l1_loss_noalloc: the L1 loss and its gradient with the library's
+    fixed per-device scratch (no context, no allocation)."""
+    for a, b, g in zip(images, targets, dl_dimages):
+        for t in (a, b, g):
+            _check_f32_cuda(t, "image")
+        if not (a.numel() == b.numel() == g.numel()):
+            raise ValueError("image, target and gradient sizes differ")
+    if not (len(images) == len(targets) == len(dl_dimages)):
+        raise ValueError("one target and one gradient per image")
+    _check_f32_cuda(loss, "loss")
+    numel = (ctypes.c_int64 * len(images))(*[t.numel() for t in images])
+    rc = lib().sixdgs_l1_loss_noalloc(len(images), _ptrs(images), _ptrs(targets), numel, _ptrs(dl_dimages),
+                                      ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(_stream(stream)))
+    if rc != OK:
+        raise SixDGSError(rc, "l1_loss_noalloc failed (bad arguments, or the scratch lookup failed)")
 
 
 def adam_devstep(params, grad, m, v, lr, step_counter, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -661,6 +662,55 @@ sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* im
   if (!c->l1_partial.ensure(parts)) return fail(c, SIXDGS_ERR_OOM, "loss partials");
   launch_l1(nimg, images, targets, numel, dl_dimages, c->l1_partial.p, c->l1_partial.cap, loss, (hipStream_t)stream);
   return check_launch(c, "l1 loss");
+}
+
+}  // extern "C"
+
+// Scratch of the allocation-free L1 loss: the per-workgroup partial sums of
+// k_l1, at most kL1MaxBlocks per image for SIXDGS_MAX_VIEWS images (64 KiB on
+// every device the library runs on, held until the process ends).  Its name
+// is a host-side stand-in: host code uses only the device address looked up
+// for the current device below.
+static constexpr int64_t kL1ScratchFloats = (int64_t)kMaxViews * kL1MaxBlocks;
+static __device__ __align__(256) float scratch[kL1ScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device; nullptr if the lookup fails.
+float* l1_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+sixdgs_status sixdgs_l1_loss_noalloc(int32_t nimg, const float* const* images, const float* const* targets,
+                                     const int64_t* numel, float* const* dl_dimages, float* loss, void* stream) {
+  if (nimg < 1 || nimg > kMaxViews) return SIXDGS_ERR_INVALID_ARG;
+  if (!images || !targets || !numel || !dl_dimages || !loss) return SIXDGS_ERR_INVALID_ARG;
+  for (int k = 0; k < nimg; k++) {
+    if (!images[k] || !targets[k] || !dl_dimages[k]) return SIXDGS_ERR_INVALID_ARG;
+    if (numel[k] <= 0) return SIXDGS_ERR_INVALID_ARG;
+  }
+  // every image takes at most kL1MaxBlocks partial sums, so the scratch always suffices
+  if (l1_partial_count(nimg, numel) > kL1ScratchFloats) return SIXDGS_ERR_CAPACITY;
+  float* partial = l1_scratch();
+  if (!partial) return SIXDGS_ERR_HIP;
+  // k_l1 writes every partial sum that k_l1_final reads: nothing needs clearing
+  launch_l1(nimg, images, targets, numel, dl_dimages, partial, kL1ScratchFloats, loss, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
 }
 
 sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images,

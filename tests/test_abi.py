@@ -52,3 +52,13 @@ def test_create_rejects_unsupported_settings():
         s = _lib.default_settings(**kw)
         assert L.sixdgs_create(ctypes.byref(h), ctypes.byref(s)) == _lib.ERR_INVALID_ARG
         assert not h.value
+
+
+def test_l1_noalloc_rejects_bad_arguments_on_host():
+    """The allocation-free L1 loss refuses bad arguments before touching a device."""
+    L = _lib.lib()
+    n1 = (ctypes.c_int64 * 1)(48)
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.sixdgs_l1_loss_noalloc(0, arr, arr, n1, arr, None, None) == _lib.ERR_INVALID_ARG
+    assert L.sixdgs_l1_loss_noalloc(_lib.MAX_VIEWS + 1, arr, arr, n1, arr, None, None) == _lib.ERR_INVALID_ARG
+    assert L.sixdgs_l1_loss_noalloc(1, arr, arr, n1, arr, None, None) == _lib.ERR_INVALID_ARG
