@@ -204,7 +204,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Five wavefronts per SIMD (96 registers, no spills): with tens of thousands
 // of tiles the walks' load latency is hidden by the extra wave (eight 1080p
 // views of 1M Gaussians: 1.87 -> 1.72 ms).
-template <int TW, bool SAVE>
+// COUNTS additionally counts each pixel's contributors (a debug export).
+template <int TW, bool SAVE, bool COUNTS>
 __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettings ds, const Rec* __restrict__ rec,
                                                       const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ pval, BlendState bs) {
@@ -255,28 +256,31 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
         Cc[u] = B.c[4 * g + u];
       }
       // predicated rather than branched, also past the last slot, so the four
-      // records are read at once: the lanes of a wavefront rarely agree
+      // records are read at once: the lanes of a wavefront rarely agree.  A
+      // Gaussian the pixel does not take gets alpha 0, which leaves T exactly
+      // as it is; T never falls below 1e-4 (it is only updated when the step
+      // does not stop), so such a step never stops either.
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const float p = log2_alpha(A[u], make_float4(Bq[u].x, Bq[u].y, 0.f, 0.f), fx - A[u].x, fy - A[u].y);
-        const float a = fminf(kAlphaMax, exp2_fast(p));
-        const float Tn = T * (1.0f - a);
         const bool take = (uint32_t)u < nu && !done && p >= kLog2AlphaMin;
-        const bool stop = take && Tn < kTMin;
+        // the clamp doubles as the mask: min(0, .) is 0 even for a stale slot's inf or NaN
+        const float a = fminf(take ? kAlphaMax : 0.f, exp2_fast(p));
+        const float Tn = __fmaf_rn(-T, a, T);  // T (1 - a)
+        const bool stop = Tn < kTMin;
         done = done || stop;
-        const bool use = take && !stop;
-        const float wgt = use ? a * T : 0.f;
+        const float wgt = stop ? 0.f : a * T;
         C0 += Cc[u].x * wgt;
         C1 += Cc[u].y * wgt;
         C2 += Cc[u].z * wgt;
-        T = use ? Tn : T;
+        T = stop ? T : Tn;
         if constexpr (SAVE) {
           K0 += Cc[u].x * wgt;
           K1 += Cc[u].y * wgt;
           K2 += Cc[u].z * wgt;
-          last = use ? __float_as_uint(Cc[u].w) : last;
-          cnt += use ? 1u : 0u;
+          last = wgt != 0.f ? __float_as_uint(Cc[u].w) : last;
         }
+        if constexpr (COUNTS) cnt += wgt != 0.f ? 1u : 0u;
       }
     }
   };
@@ -356,7 +360,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
     vd.img[2 * HW + pix] = C2 + T * ds.bg[2];
     bs.T_final[vd.pix_base + pix] = T;
     bs.last[vd.pix_base + pix] = last;
-    if (bs.counts) bs.counts[vd.pix_base + pix] = cnt;
+    if constexpr (COUNTS) bs.counts[vd.pix_base + pix] = cnt;
   }
   const uint32_t wlast = wave_max(last);
   if (l == 0) atomicMax(&s_maxlast, wlast);
@@ -611,17 +615,19 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
 
 }  // namespace
 
-template <bool SAVE>
+template <bool SAVE, bool COUNTS>
 void launch_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
                 const uint32_t* pval, const BlendState& bs, hipStream_t st) {
   const dim3 grid(vt.total_tiles);
   switch (vt.tile_w) {
-    case 8: hipLaunchKernelGGL((k_blend_fwd<8, SAVE>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs); break;
+    case 8:
+      hipLaunchKernelGGL((k_blend_fwd<8, SAVE, COUNTS>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
+      break;
     case 32:
-      hipLaunchKernelGGL((k_blend_fwd<32, SAVE>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
+      hipLaunchKernelGGL((k_blend_fwd<32, SAVE, COUNTS>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
       break;
     default:
-      hipLaunchKernelGGL((k_blend_fwd<16, SAVE>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
+      hipLaunchKernelGGL((k_blend_fwd<16, SAVE, COUNTS>), grid, dim3(kBlock), 0, st, vt, s, rec, ranges, pval, bs);
       break;
   }
 }
@@ -629,10 +635,12 @@ void launch_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const
 void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
                       const uint32_t* pval, BlendState bs, int batch, bool save, hipStream_t st) {
   if (vt.total_tiles <= 0) return;
-  if (save)
-    launch_fwd<true>(vt, s, rec, ranges, pval, bs, st);
+  if (!save)
+    launch_fwd<false, false>(vt, s, rec, ranges, pval, bs, st);
+  else if (bs.counts)
+    launch_fwd<true, true>(vt, s, rec, ranges, pval, bs, st);
   else
-    launch_fwd<false>(vt, s, rec, ranges, pval, bs, st);
+    launch_fwd<true, false>(vt, s, rec, ranges, pval, bs, st);
 }
 
 void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,

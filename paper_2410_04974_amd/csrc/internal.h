@@ -90,24 +90,40 @@ __device__ __forceinline__ void tile_rect(float u, float v, float ex, float ey, 
   y1 = min(max(y1, 0), nty);
 }
 
-// One Adam step's constants (bias corrections folded in by the host).
+// One Adam step's constants.  The bias corrections 1 - b^t enter as two
+// factors: mhat = m / (1 - b1^t) and sqrt(vhat) = sqrt(v) / sqrt(1 - b2^t), so
+// an element takes one square root and one reciprocal (the hardware ones,
+// correct to about an ulp).  lb1, lb2 = ln b1, ln b2 (for a step count read
+// on the device).
 struct AdamArgs {
   float lr[6];  // row groups: mu_p, mu_d, Cholesky, SH degree 0, SH degrees 1-3, opacity
-  float b1, b2, eps, bc1, bc2;
+  float b1, b2, eps;
+  float inv_bc1;       // 1 / (1 - b1^t)
+  float inv_sqrt_bc2;  // 1 / sqrt(1 - b2^t)
+  float lb1, lb2;
 };
 AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int step);
+
+// The bias-correction factors of step t = step_count + 1 (uniform: every lane
+// computes the same), with 1 - b^t = -expm1(t ln b), which keeps its relative
+// precision where b^t is close to 1.
+__device__ __forceinline__ void adam_device_step(AdamArgs& a, int32_t step_count) {
+  const float t = (float)(step_count + 1);
+  a.inv_bc1 = -1.0f / expm1f(t * a.lb1);
+  a.inv_sqrt_bc2 = 1.0f / sqrtf(-expm1f(t * a.lb2));
+}
 
 __device__ __forceinline__ int adam_row_group(int r) {
   return r < 3 ? 0 : r < 6 ? 1 : r < 27 ? 2 : r < 30 ? 3 : r < 75 ? 4 : 5;
 }
 
-// Bias-corrected Adam update of one parameter.
+// Bias-corrected Adam update of one parameter:
+// p -= lr mhat / (sqrt(vhat) + eps).
 __device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float lr, const AdamArgs& a) {
   m = a.b1 * m + (1.f - a.b1) * g;
   v = a.b2 * v + (1.f - a.b2) * g * g;
-  const float mh = m / a.bc1;
-  const float vh = v / a.bc2;
-  p -= lr * mh / (sqrtf(vh) + a.eps);
+  const float den = __builtin_amdgcn_sqrtf(v) * a.inv_sqrt_bc2 + a.eps;
+  p -= (lr * a.inv_bc1) * m * __builtin_amdgcn_rcpf(den);
 }
 
 // ----------------------------------------------------------- host launchers

@@ -494,11 +494,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bwd_gaussian(params, n, g, vt, ds, tiles, g2d, GradToLDS{s_g[wv]}, densify);
-  if (step_dev) {
-    const float t = (float)(*step_dev + 1);
-    a.bc1 = 1.0f - powf(a.b1, t);
-    a.bc2 = 1.0f - powf(a.b2, t);
-  }
+  if (step_dev) adam_device_step(a, *step_dev);
   // each lane reads back only what it wrote: ordering the wavefront's own LDS
   // accesses is enough
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

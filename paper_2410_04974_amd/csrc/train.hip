@@ -221,11 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_ssim_final(const float* __restrict__
 // from the step about to be taken (*step + 1), so a captured graph advances
 // the step on every replay; k_step_inc then moves the counter on.
 __device__ __forceinline__ void device_bias(AdamArgs& a, const int32_t* step_dev) {
-  if (step_dev) {
-    const float t = (float)(*step_dev + 1);
-    a.bc1 = 1.0f - powf(a.b1, t);
-    a.bc2 = 1.0f - powf(a.b2, t);
-  }
+  if (step_dev) adam_device_step(a, *step_dev);
 }
 
 __global__ void k_step_inc(int32_t* step_dev) { *step_dev += 1; }
@@ -336,8 +332,10 @@ AdamArgs make_adam_args(const float lr[6], float b1, float b2, float eps, int st
   a.b1 = b1;
   a.b2 = b2;
   a.eps = eps;
-  a.bc1 = (float)(1.0 - __builtin_pow((double)b1, (double)step));
-  a.bc2 = (float)(1.0 - __builtin_pow((double)b2, (double)step));
+  a.inv_bc1 = (float)(1.0 / (1.0 - __builtin_pow((double)b1, (double)step)));
+  a.inv_sqrt_bc2 = (float)(1.0 / __builtin_sqrt(1.0 - __builtin_pow((double)b2, (double)step)));
+  a.lb1 = (float)__builtin_log((double)b1);
+  a.lb2 = (float)__builtin_log((double)b2);
   return a;
 }
 
