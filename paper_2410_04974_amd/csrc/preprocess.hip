@@ -80,48 +80,66 @@ struct ViewState {
 
 // Slice for the view (Sec. 3.2 eq:mu, Sec. 4.2 eq:pdfv2), camera transform and
 // EWA projection with the 3DGS guard and dilation.  Returns false when culled.
-__device__ __forceinline__ bool view_state(const Static& s, const ViewDesc& vd, float lambda, float z_near,
-                                           ViewState& w) {
+// The slice at camera centre C (Sec. 3.2): view direction d = (mu_p - C)/|mu_p - C|,
+// its offset x = d - mu_d from the direction mean, conditional mean mu_c = mu_p + K x.
+template <bool FAST = false>
+__device__ __forceinline__ void slice_mean(const Static& s, const ViewDesc& vd, float d[3], float& nd, float x[3],
+                                           float mu_c[3]) {
   float nd2 = 0.f;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    w.d[k] = s.mu_p[k] - vd.C[k];
-    nd2 += w.d[k] * w.d[k];
+    d[k] = s.mu_p[k] - vd.C[k];
+    nd2 += d[k] * d[k];
   }
-  w.nd = sqrtf(nd2);
+  using M = SliceMath<FAST>;
+  nd = M::sqrt(nd2);
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    w.d[k] = w.d[k] / w.nd;
-    w.x[k] = w.d[k] - s.mu_d[k];
+    d[k] = M::div(d[k], nd);
+    x[k] = d[k] - s.mu_d[k];
   }
 #pragma unroll
-  for (int r = 0; r < 3; r++) {
-    w.Ax[r] = s.A[r][0] * w.x[0] + s.A[r][1] * w.x[1] + s.A[r][2] * w.x[2];
-    w.mu_c[r] = s.mu_p[r] + (s.K[r][0] * w.x[0] + s.K[r][1] * w.x[1] + s.K[r][2] * w.x[2]);
-  }
-  w.D = w.x[0] * w.Ax[0] + w.x[1] * w.Ax[1] + w.x[2] * w.Ax[2];
-  w.f = expf(-lambda * w.D);
-  w.ac = s.alpha * w.f;
+  for (int r = 0; r < 3; r++) mu_c[r] = s.mu_p[r] + (s.K[r][0] * x[0] + s.K[r][1] * x[1] + s.K[r][2] * x[2]);
+}
+
+// The SH evaluation direction (mu_c - C)/|mu_c - C| (Sec. 4.2) and the distance.
+template <bool FAST = false>
+__device__ __forceinline__ void sh_direction(const float mu_c[3], const ViewDesc& vd, float sdir[3], float& ns) {
   float ns2 = 0.f;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    w.sdir[k] = w.mu_c[k] - vd.C[k];
-    ns2 += w.sdir[k] * w.sdir[k];
+    sdir[k] = mu_c[k] - vd.C[k];
+    ns2 += sdir[k] * sdir[k];
   }
-  w.ns = sqrtf(ns2);
+  using M = SliceMath<FAST>;
+  ns = M::sqrt(ns2);
 #pragma unroll
-  for (int k = 0; k < 3; k++) w.sdir[k] = w.sdir[k] / w.ns;
+  for (int k = 0; k < 3; k++) sdir[k] = M::div(sdir[k], ns);
+}
+
+template <bool FAST = false>
+__device__ __forceinline__ bool view_state(const Static& s, const ViewDesc& vd, float lambda, float z_near,
+                                           ViewState& w) {
+  using M = SliceMath<FAST>;
+  slice_mean<FAST>(s, vd, w.d, w.nd, w.x, w.mu_c);
+#pragma unroll
+  for (int r = 0; r < 3; r++) w.Ax[r] = s.A[r][0] * w.x[0] + s.A[r][1] * w.x[1] + s.A[r][2] * w.x[2];
+  w.D = w.x[0] * w.Ax[0] + w.x[1] * w.Ax[1] + w.x[2] * w.Ax[2];
+  w.f = M::exp(-lambda * w.D);
+  w.ac = s.alpha * w.f;
+  sh_direction<FAST>(w.mu_c, vd, w.sdir, w.ns);
 #pragma unroll
   for (int r = 0; r < 3; r++)
     w.p[r] = vd.R[3 * r] * w.mu_c[0] + vd.R[3 * r + 1] * w.mu_c[1] + vd.R[3 * r + 2] * w.mu_c[2] + vd.t[r];
   if (!(w.p[2] > z_near)) return false;
   const float z = w.p[2];
-  const float rx = w.p[0] / z, ry = w.p[1] / z;
+  const float rx = M::div(w.p[0], z), ry = M::div(w.p[1], z);
   w.clx = (rx < -vd.limx) || (rx > vd.limx);
   w.cly = (ry < -vd.limy) || (ry > vd.limy);
   w.xt = fminf(vd.limx, fmaxf(-vd.limx, rx));
   w.yt = fminf(vd.limy, fmaxf(-vd.limy, ry));
-  const float j00 = vd.fx / z, j02 = -vd.fx * w.xt / z, j11 = vd.fy / z, j12 = -vd.fy * w.yt / z;
+  const float j00 = M::div(vd.fx, z), j02 = M::div(-vd.fx * w.xt, z), j11 = M::div(vd.fy, z),
+              j12 = M::div(-vd.fy * w.yt, z);
 #pragma unroll
   for (int c = 0; c < 3; c++) {
     w.T[0][c] = j00 * vd.R[c] + j02 * vd.R[6 + c];
@@ -137,7 +155,7 @@ __device__ __forceinline__ bool view_state(const Static& s, const ViewDesc& vd, 
   w.cov[2] = TS[1][0] * w.T[1][0] + TS[1][1] * w.T[1][1] + TS[1][2] * w.T[1][2] + kDilation;
   const float det = w.cov[0] * w.cov[2] - w.cov[1] * w.cov[1];
   if (!(det > 0.f)) return false;
-  const float idet = 1.0f / det;
+  const float idet = M::div(1.0f, det);
   w.Q[0] = w.cov[2] * idet;
   w.Q[1] = -w.cov[1] * idet;
   w.Q[2] = w.cov[0] * idet;
@@ -162,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__
 #pragma unroll
   for (int k = 0; k < 16; k++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) beta[k][c] = params[(kRowSH + 3 * k + c) * n + g];
+    for (int c = 0; c < 3; c++) beta[k][c] = row_ld(params, kRowSH + 3 * k + c, n, g);
   const float lam = gaussian_lambda(ds, g);
   for (int vi = 0; vi < vt.nview; vi++) {
     const ViewDesc& vd = vt.v[vi];
@@ -220,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_build_cache(const float* __restrict_
                                s.K[2][0],  s.K[2][1],  s.K[2][2],  s.A[0][0],  s.A[0][1],  s.A[0][2],
                                s.A[1][1],  s.A[1][2],  s.A[2][2],  s.alpha};
 #pragma unroll
-  for (int k = 0; k < kCacheRows; k++) cache[k * n + g] = v[k];
+  for (int k = 0; k < kCacheRows; k++) row_st(cache, k, n, g, v[k]);
 }
 
 // ------------------------------------------------------------------ backward
@@ -228,7 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_build_cache(const float* __restrict_
 // an Adam step on the parameters (the gradient then never reaches memory).
 struct GradToBuffer {
   float* grad;
-  __device__ void put(int row, int64_t n, int64_t g, float v) const { grad[row * n + g] = v; }
+  __device__ void put(int row, int64_t n, int64_t g, float v) const { row_st(grad, row, n, g, v); }
 };
 // ... or to this wavefront's rows in LDS ([kRows][64]), for an Adam step
 // that streams the parameter and moment rows afterwards.
@@ -246,9 +264,24 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
                                              const DevSettings& ds, const uint32_t* __restrict__ tiles,
                                              const float* __restrict__ g2d, const Sink& sink,
                                              float* __restrict__ densify) {
+  using M = SliceMath<true>;  // the backward differentiates at recomputed values
   if (g >= n) return;
-  bool any = false;
-  for (int vi = 0; vi < vt.nview; vi++) any |= tiles[(int64_t)vi * n + g] > 0;
+  // Every load that depends on no other is issued before the first branch, so
+  // a wavefront waits for memory once: the 76 parameter rows and the first
+  // view's tile count and screen-space gradients.
+  RawGeom raw;
+  load_raw_geom(params, n, g, raw);
+  float beta[16][3];
+#pragma unroll
+  for (int k = 0; k < 16; k++)
+#pragma unroll
+    for (int c = 0; c < 3; c++) beta[k][c] = row_ld(params, kRowSH + 3 * k + c, n, g);
+  const uint32_t tiles0 = row_ld(tiles, 0, n, g);
+  float gp0[kG2D];
+#pragma unroll
+  for (int k = 0; k < kG2D; k++) gp0[k] = g2d[g * kG2D + k];
+  bool any = tiles0 > 0;
+  for (int vi = 1; vi < vt.nview; vi++) any |= row_ld(tiles, vi, n, g) > 0;
   // Only a wavefront with no visible Gaussian leaves early: its lanes store
   // together.  Otherwise invisible lanes run along with zero accumulators
   // (every view is skipped), so each gradient row is written by one store
@@ -259,12 +292,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     return;
   }
   Static s;
-  load_static(params, n, g, s);
-  float beta[16][3];
-#pragma unroll
-  for (int k = 0; k < 16; k++)
-#pragma unroll
-    for (int c = 0; c < 3; c++) beta[k][c] = params[(kRowSH + 3 * k + c) * n + g];
+  static_from_raw<true>(raw, s);
 
   // an invisible lane's rows are exact zeros whatever its parameters
   auto put = [&](int row, float v) { sink.put(row, n, g, any ? v : 0.f); };
@@ -285,13 +313,15 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
   for (int vi = 0; vi < vt.nview; vi++) {
     const ViewDesc& vd = vt.v[vi];
     const int64_t e = (int64_t)vi * n + g;
-    if (tiles[e] == 0) continue;
+    if ((vi == 0 ? tiles0 : row_ld(tiles, vi, n, g)) == 0) continue;
+    float gp[kG2D];
+#pragma unroll
+    for (int k = 0; k < kG2D; k++) gp[k] = vi == 0 ? gp0[k] : g2d[e * kG2D + k];
     ViewState w;
-    view_state(s, vd, lam, ds.z_near, w);
-    const float* gp = g2d + e * kG2D;
+    view_state<true>(s, vd, lam, ds.z_near, w);
     const float gu = gp[0], gv = gp[1], gqxx = gp[2], gqxy = gp[3], gqyy = gp[4], gac = gp[5];
     const float z = w.p[2], fx = vd.fx, fy = vd.fy;
-    dens_norm += sqrtf((gu * 0.5f * vd.W) * (gu * 0.5f * vd.W) + (gv * 0.5f * vd.H) * (gv * 0.5f * vd.H));
+    dens_norm += M::sqrt((gu * 0.5f * vd.W) * (gu * 0.5f * vd.W) + (gv * 0.5f * vd.H) * (gv * 0.5f * vd.H));
     dens_cnt += 1.f;
     // conic -> 2D covariance: G_S = -Q G_Q Q
     const float Q00 = w.Q[0], Q01 = w.Q[1], Q11 = w.Q[2];
@@ -322,7 +352,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     const float dJ02 = dT[0][0] * vd.R[6] + dT[0][1] * vd.R[7] + dT[0][2] * vd.R[8];
     const float dJ11 = dT[1][0] * vd.R[3] + dT[1][1] * vd.R[4] + dT[1][2] * vd.R[5];
     const float dJ12 = dT[1][0] * vd.R[6] + dT[1][1] * vd.R[7] + dT[1][2] * vd.R[8];
-    const float iz = 1.0f / z, iz2 = iz * iz;
+    const float iz = M::div(1.0f, z), iz2 = iz * iz;
     float dp0 = 0.f, dp1 = 0.f, dp2 = -(dJ00 * fx + dJ11 * fy) * iz2;
     if (!w.clx) {
       dp0 += -dJ02 * fx * iz2;
@@ -348,7 +378,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
       // No-SH colour: rgb = sigmoid(c), no dependence on the viewing direction
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        const float col = sigmoidf(beta[0][c]);
+        const float col = M::sigmoid(beta[0][c]);
         g_beta[0][c] += gp[6 + c] * col * (1.f - col);
       }
     } else {
@@ -363,7 +393,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
-        const float col = sigmoidf(acc);
+        const float col = M::sigmoid(acc);
         const float dsc = gp[6 + c] * col * (1.f - col);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
@@ -375,7 +405,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
       sh_basis_vjp(w.sdir[0], w.sdir[1], w.sdir[2], wsum, gs);
       const float sdot = w.sdir[0] * gs[0] + w.sdir[1] * gs[1] + w.sdir[2] * gs[2];
 #pragma unroll
-      for (int k = 0; k < 3; k++) gmu[k] += (gs[k] - w.sdir[k] * sdot) / w.ns;
+      for (int k = 0; k < 3; k++) gmu[k] += M::div(gs[k] - w.sdir[k] * sdot, w.ns);
     }
     // slice (Sec. 3.2): mu_c = mu_p + K x, D = x^T A x, alpha_c = alpha exp(-lambda D)
     const float dD = -lam * w.ac * gac;
@@ -387,7 +417,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       g_mud[k] -= gx[k];
-      g_mup[k] += gmu[k] + (gx[k] - w.d[k] * ddot) / w.nd;
+      g_mup[k] += gmu[k] + M::div(gx[k] - w.d[k] * ddot, w.nd);
     }
     g_alpha += gac * w.f;
     float st_g[3];  // Sigma_pd^T gmu
