@@ -50,6 +50,8 @@ typedef int32_t sixdgs_status;
 #define SIXDGS_ERR_HIP 3         /* a HIP runtime call failed */
 #define SIXDGS_ERR_CAPACITY 4    /* fixed pair capacity was exceeded (output invalid) */
 #define SIXDGS_ERR_STATE 5       /* backward without a matching forward, etc. */
+#define SIXDGS_ERR_DEBUG 6       /* a debug-mode check failed (SIXDGS_FLAG_DEBUG): a workspace
+                                    guard was overwritten or a binning invariant does not hold */
 
 #define SIXDGS_NROWS 76
 #define SIXDGS_ROW_MU_P 0
@@ -99,6 +101,19 @@ typedef struct {
  * higher SH rows are ignored and receive zero gradient.  Without the flag the
  * colour is the sigmoid of the degree-3 SH expansion (Sec. 4.2). */
 #define SIXDGS_FLAG_RGB_COLOR 2
+/* Debug mode, for finding indexing faults without a GPU debugger.  Every
+ * workspace buffer the context allocates is padded with 4 KiB guards of a
+ * fixed byte before and after it.  After each call on the context that
+ * launches work, the host waits for the stream and reads every guard back.
+ * After a forward or sixdgs_bin it also checks the integer stage's outputs
+ * against sixdgs_debug_check_bins (and, after a forward, each pixel's last
+ * contributor and final transmittance against its tile).  A failure returns
+ * SIXDGS_ERR_DEBUG with a message that names the buffer or the invariant.
+ * Results are bitwise those of the normal mode.  Each call waits for its
+ * stream, so the mode is for tests, not for speed.  Turning the flag on or off
+ * with sixdgs_set_settings frees the workspace, which drops the state of the
+ * last forward. */
+#define SIXDGS_FLAG_DEBUG 4
 
 /* Fills `s` with the defaults: lambda 0.35, z_near 0.2, bg 0, 16x16 tiles,
  * batch 0 (automatic), pair_capacity 0, flags 0, chunk 0 (automatic). */
@@ -338,10 +353,53 @@ sixdgs_status sixdgs_bin(sixdgs_ctx* ctx, int64_t n, const sixdgs_camera* cams, 
  * receives the byte count.  Returns INVALID_ARG if it does not fit. */
 sixdgs_status sixdgs_export(sixdgs_ctx* ctx, int32_t what, void* dst, int64_t cap_bytes, int64_t* written);
 
+/* Host copies of the integer stage's outputs for one binning: E entries
+ * (entry e = view * n + gaussian), P (tile, entry) pairs, T global tiles.
+ * Rows are as sixdgs_export writes them. */
+typedef struct {
+  int64_t E, P, T;
+  const uint32_t* tiles;   /* [E] tiles each entry touches */
+  const float* depth;      /* [E] camera depth of each entry (the depth sort's key) */
+  const uint32_t* keys;    /* [P] global tile id of each sorted pair */
+  const uint32_t* values;  /* [P] entry id of each sorted pair */
+  const uint32_t* ranges;  /* [2T] [start, end) of each tile's run of pairs, (0, 0) if none */
+  const uint32_t* order;   /* [T] the compositing order of the tiles, or NULL */
+  int32_t chunk;           /* the backward's chunk length (with nch and items) */
+  const uint32_t* nch;     /* [T] backward chunks per tile, or NULL (no work items) */
+  const uint32_t* items;   /* [2 n_items] (tile, chunk) work items */
+  int64_t n_items;
+} sixdgs_bin_state;
+
+/* Checks the invariants of one binning (the tile binning and (tile, depth)
+ * sort of the 3DGS rasteriser, Sec. 4.4, and the backward's chunked work
+ * items) on host copies, without a GPU:
+ *   - the tile counts sum to P;
+ *   - pairs are sorted by tile, and within a tile by (depth, entry id), with
+ *     tile ids below T and entry ids below E;
+ *   - each entry appears in exactly tiles[e] pairs;
+ *   - every range is the exact run of its tile's pairs;
+ *   - the order, if given, is a permutation with list lengths of
+ *     non-increasing bit length;
+ *   - each tile, if nch is given, has at most ceil(run / chunk) chunks, and
+ *     the items are exactly (t, 0 .. nch[t] - 1) for t in the order.
+ * Returns SIXDGS_OK, SIXDGS_ERR_DEBUG with the first violation written to
+ * msg (NUL-terminated, at most msg_cap bytes, if msg is not NULL), or
+ * SIXDGS_ERR_INVALID_ARG for a NULL or inconsistent state.  The debug mode
+ * runs it after every binning. */
+sixdgs_status sixdgs_debug_check_bins(const sixdgs_bin_state* state, char* msg, int32_t msg_cap);
+
+/* Debug mode only: the device address and byte size of the workspace buffer
+ * called `name` (as debug-mode messages name them, e.g. "ranges"), so that a
+ * test can check that the guard checks see a write placed just outside it
+ * with hipMemcpy.  Returns SIXDGS_ERR_STATE outside the debug mode or before
+ * the buffer exists, and INVALID_ARG for an unknown name. */
+sixdgs_status sixdgs_debug_buffer(sixdgs_ctx* ctx, const char* name, void** ptr, int64_t* bytes);
+
 /* Waits for the context's last stream and reports a capacity overflow of the
  * fixed-capacity mode (SIXDGS_ERR_CAPACITY), or a sort pass whose bounded
  * wait on an earlier workgroup ran out (SIXDGS_ERR_HIP); the flag is then
- * cleared. */
+ * cleared.  In the debug mode it also checks every workspace guard
+ * (SIXDGS_ERR_DEBUG). */
 sixdgs_status sixdgs_check(sixdgs_ctx* ctx);
 
 /* Kernel timing with HIP events recorded on the launch stream around the

@@ -15,10 +15,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # SIXDGS_LIB selects another build of the same library (e.g. to compare two builds)
 LIB_PATH = os.environ.get("SIXDGS_LIB", os.path.join(_HERE, "lib6dgs.so"))
 
-OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_STATE = range(6)
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_CAPACITY, ERR_STATE, ERR_DEBUG = range(7)
 MAX_VIEWS = 16
 FLAG_COUNTS = 1
 FLAG_RGB_COLOR = 2
+FLAG_DEBUG = 4
 CACHE_ROWS = 22  # rows of the inference cache (SIXDGS_CACHE_ROWS)
 EXPORT_RECORDS, EXPORT_TILES, EXPORT_KEYS, EXPORT_VALUES, EXPORT_RANGES, EXPORT_T_FINAL, EXPORT_LAST, \
     EXPORT_COUNTS, EXPORT_SIZES = range(9)
@@ -42,6 +43,15 @@ class Settings(ctypes.Structure):
 class DensitySettings(ctypes.Structure):
     _fields_ = [("grad_threshold", ctypes.c_float), ("percent_dense", ctypes.c_float), ("extent", ctypes.c_float),
                 ("min_opacity", ctypes.c_float)]
+
+
+class BinState(ctypes.Structure):
+    """sixdgs_bin_state: host copies of one binning's outputs."""
+    _fields_ = [("E", ctypes.c_int64), ("P", ctypes.c_int64), ("T", ctypes.c_int64),
+                ("tiles", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("keys", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("ranges", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("chunk", ctypes.c_int32), ("nch", ctypes.c_void_p), ("items", ctypes.c_void_p),
+                ("n_items", ctypes.c_int64)]
 
 
 class SixDGSError(RuntimeError):
@@ -88,14 +98,16 @@ def lib():
         L.sixdgs_bin.argtypes = [P, I64, ctypes.POINTER(Camera), I32, P, P, P, P, P, P, P]
         L.sixdgs_export.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
         L.sixdgs_check.argtypes = [P]
+        L.sixdgs_debug_check_bins.argtypes = [ctypes.POINTER(BinState), ctypes.c_char_p, I32]
+        L.sixdgs_debug_buffer.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P), ctypes.POINTER(I64)]
         L.sixdgs_set_timing.argtypes = [P, I32]
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
                      "sixdgs_build_cache", "sixdgs_forward_cached",
                      "sixdgs_backward_adam", "sixdgs_l1_loss", "sixdgs_l1_loss_noalloc",
                      "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check",
-                     "sixdgs_set_timing",
-                     "sixdgs_kernel_time"):
+                     "sixdgs_set_timing", "sixdgs_kernel_time", "sixdgs_debug_check_bins",
+                     "sixdgs_debug_buffer"):
             getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -107,7 +119,27 @@ EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdg
             "sixdgs_l1_dssim_loss",
             "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_decompose",
             "sixdgs_densify_plan", "sixdgs_densify_apply", "sixdgs_bin",
-            "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time"]
+            "sixdgs_export", "sixdgs_check", "sixdgs_set_timing", "sixdgs_kernel_time",
+            "sixdgs_debug_check_bins", "sixdgs_debug_buffer"]
+
+
+def check_bins(tiles, depth, keys, values, ranges, order=None, chunk=0, nch=None, items=None):
+    """sixdgs_debug_check_bins on numpy arrays (uint32, except depth float32;
+    ranges [T][2], items [n_items][2]).  Returns (status, message)."""
+    def arr(a, dt):
+        return None if a is None else np.ascontiguousarray(a, dt)
+    a = {k: arr(v, np.float32 if k == "depth" else np.uint32)
+         for k, v in dict(tiles=tiles, depth=depth, keys=keys, values=values, ranges=ranges, order=order,
+                          nch=nch, items=items).items()}
+    b = BinState()
+    b.E, b.P, b.T = len(a["tiles"]), len(a["keys"]), len(a["ranges"].reshape(-1)) // 2
+    for k in ("tiles", "depth", "keys", "values", "ranges", "order", "nch", "items"):
+        setattr(b, k, None if a[k] is None else a[k].ctypes.data)
+    b.chunk = int(chunk)
+    b.n_items = 0 if a["items"] is None else len(a["items"].reshape(-1)) // 2
+    msg = ctypes.create_string_buffer(512)
+    rc = lib().sixdgs_debug_check_bins(ctypes.byref(b), msg, 512)
+    return rc, msg.value.decode()
 
 
 def default_settings(**kw) -> Settings:

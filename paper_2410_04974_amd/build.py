@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "lib6dgs.so")
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "train.hip", "density.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "train.hip", "density.hip", "debug.hip"]
 ARCH = os.environ.get("SIXDGS_ARCH", "gfx950")
 
 FLAGS = [

@@ -14,29 +14,60 @@ using namespace sixdgs;
 
 namespace {
 
+// Debug mode: guards of kGuardBytes bytes of kGuardByte before and after
+// every workspace buffer.
+constexpr size_t kGuardBytes = 4096;
+constexpr uint8_t kGuardByte = 0xA7;
+
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   int64_t cap = 0;
+  bool guarded = false;     // allocate with guards (set while the buffer is empty)
+  uint8_t* raw = nullptr;   // the allocation: front guard, cap elements, back guard
   // Grows to at least `count` elements (contents are not kept).
   bool ensure(int64_t count, double slack = 1.0) {
     if (count <= cap) return true;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
+    release();
     int64_t want = (int64_t)std::ceil((double)count * slack);
     if (want < 1) want = 1;
-    if (hipMalloc((void**)&p, (size_t)want * sizeof(T)) != hipSuccess) {
-      p = nullptr;
+    const size_t bytes = (size_t)want * sizeof(T), pad = guarded ? kGuardBytes : 0;
+    if (hipMalloc((void**)&raw, bytes + 2 * pad) != hipSuccess) {
+      raw = nullptr;
       return false;
     }
+    if (pad && (hipMemset(raw, kGuardByte, pad) != hipSuccess ||
+                hipMemset(raw + pad + bytes, kGuardByte, pad) != hipSuccess)) {
+      release();
+      return false;
+    }
+    p = (T*)(raw + pad);
     cap = want;
     return true;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (raw) (void)hipFree(raw);
+    raw = nullptr;
     p = nullptr;
     cap = 0;
+  }
+  int64_t bytes() const { return cap * (int64_t)sizeof(T); }
+  // Reads both guards back (synchronously); "" if they are intact.
+  std::string guard_damage(const char* name) const {
+    if (!guarded || !raw) return "";
+    std::vector<uint8_t> h(kGuardBytes);
+    for (int side = 0; side < 2; side++) {
+      const uint8_t* src = side == 0 ? raw : raw + kGuardBytes + bytes();
+      if (hipMemcpy(h.data(), src, kGuardBytes, hipMemcpyDeviceToHost) != hipSuccess)
+        return std::string("guard read-back of ") + name + " failed";
+      for (size_t i = 0; i < kGuardBytes; i++)
+        if (h[i] != kGuardByte) {
+          const int64_t off = side == 0 ? -(int64_t)(kGuardBytes - i) : (int64_t)i;
+          return std::string(name) + (side == 0 ? ": written before its start (byte " : ": written past its end (byte ") +
+                 std::to_string(off) + (side == 0 ? ")" : " after the end)");
+        }
+    }
+    return "";
   }
 };
 
@@ -100,7 +131,48 @@ struct sixdgs_ctx {
   std::vector<hipEvent_t> free_events;
   double ms[SIXDGS_K_COUNT] = {0};
   int64_t launches[SIXDGS_K_COUNT] = {0};
+  bool debug = false;  // SIXDGS_FLAG_DEBUG: guarded workspace, checks after every call
 };
+
+namespace {
+// Every workspace buffer of the context with the name debug-mode messages use.
+template <class F>
+void for_each_buf(sixdgs_ctx* c, F f) {
+  f(c->rec, "records");
+  f(c->tiles, "tiles");
+  f(c->dkey0, "depth keys 0");
+  f(c->dkey1, "depth keys 1");
+  f(c->dval0, "depth values 0");
+  f(c->dval1, "depth values 1");
+  f(c->poff, "pair offsets");
+  f(c->depth, "depth");
+  f(c->pkey0, "pair keys 0");
+  f(c->pkey1, "pair keys 1");
+  f(c->pval0, "pair values 0");
+  f(c->pval1, "pair values 1");
+  f(c->ranges, "ranges");
+  f(c->T_final, "final transmittance");
+  f(c->last, "last contributor");
+  f(c->counts, "contributor counts");
+  f(c->bound, "chunk boundary state");
+  f(c->tile_nch, "tile chunk counts");
+  f(c->chunk_state, "work item scan state");
+  f(c->items, "work items");
+  f(c->dens_dec, "density decisions");
+  f(c->dens_cnt, "density counts");
+  f(c->dens_off, "density offsets");
+  f(c->dens_state, "density scan state");
+  f(c->g2d, "screen-space gradients");
+  f(c->l1_partial, "l1 partial sums");
+  f(c->ssim_maps, "ssim maps");
+  f(c->ssim_partial, "ssim partial sums");
+  f(c->rstate, "sort state");
+  f(c->blk_start, "emission block starts");
+  f(c->counters, "counters");
+  f(c->tile_order, "tile order");
+  f(c->order_state, "tile order state");
+}
+}  // namespace
 
 namespace {
 
@@ -131,7 +203,10 @@ bool valid_settings(const sixdgs_settings* s, std::string& why) {
     return false;
   }
   if (s->pair_capacity < 0 || s->pair_capacity > kMaxItems) { why = "pair_capacity out of range"; return false; }
-  if (s->flags & ~(SIXDGS_FLAG_COUNTS | SIXDGS_FLAG_RGB_COLOR)) { why = "unknown flag bits"; return false; }
+  if (s->flags & ~(SIXDGS_FLAG_COUNTS | SIXDGS_FLAG_RGB_COLOR | SIXDGS_FLAG_DEBUG)) {
+    why = "unknown flag bits";
+    return false;
+  }
   if (s->chunk != 0 && (s->chunk < std::max(s->batch, 64) || s->chunk > 16384 || (s->chunk & (s->chunk - 1)) != 0)) {
     why = "chunk must be 0 (automatic) or a power of two between batch (64 at least) and 16384";
     return false;
@@ -364,6 +439,127 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
   return check_launch(c, "binning");
 }
 
+// Empties the workspace and sets whether it is allocated with guards; the
+// state of the last forward, binning and density plan is dropped with it.
+void set_debug(sixdgs_ctx* c, bool on) {
+  c->debug = on;
+  for_each_buf(c, [on](auto& b, const char*) {
+    b.release();
+    b.guarded = on;
+  });
+  c->have_fwd = false;
+  c->g2d_clean = false;
+  c->counts_valid = false;
+  c->dens_n = -1;
+  c->fwd_E = 0;
+  c->fwd_px = 0;
+  c->vt = ViewTable{};
+  c->sb = SortBuffers{};
+}
+
+// The error flags in counters[2..3] are only ever set by kernels and cleared by sixdgs_check.
+bool init_counters(sixdgs_ctx* c) {
+  return c->counters.ensure(kCounters) && hipMemset(c->counters.p, 0, kCounters * sizeof(uint32_t)) == hipSuccess;
+}
+
+template <class T>
+bool read_back(std::vector<T>& h, const T* d, int64_t count) {
+  h.resize((size_t)std::max<int64_t>(count, 0));
+  return count <= 0 || hipMemcpy(h.data(), d, (size_t)count * sizeof(T), hipMemcpyDeviceToHost) == hipSuccess;
+}
+
+// The invariants of the last binning (sixdgs_debug_check_bins on host copies
+// of its outputs); with `items`, also the backward's work items and each
+// pixel's last contributor and final transmittance against its tile.  "" if
+// they hold.
+std::string debug_check_binning(sixdgs_ctx* c, const float* depth_dev, bool items) {
+  uint32_t cnt[kCounters];
+  if (hipMemcpy(cnt, c->counters.p, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return "counter read-back failed";
+  const int64_t E = c->sb.E, P = cnt[1], T = c->vt.total_tiles;
+  if (P > c->sb.pcap) return "";  // overflow of the fixed capacity: no output to check (sixdgs_check reports it)
+  std::vector<uint32_t> tiles, keys, vals, ranges, order, nch, its;
+  std::vector<float> depth;
+  if (!read_back(tiles, c->tiles.p, E) || !read_back(depth, depth_dev, E) ||
+      !read_back(keys, (const uint32_t*)c->sb.pkey[c->sb.psorted], P) ||
+      !read_back(vals, (const uint32_t*)c->sb.pval[c->sb.psorted], P) ||
+      !read_back(ranges, (const uint32_t*)c->ranges.p, 2 * T) || !read_back(order, (const uint32_t*)c->tile_order.p, T))
+    return "binning read-back failed";
+  if ((int64_t)cnt[0] > E) return "binned entries " + std::to_string(cnt[0]) + " > " + std::to_string(E);
+  sixdgs_bin_state b{};
+  b.E = E;
+  b.P = P;
+  b.T = T;
+  b.tiles = tiles.data();
+  b.depth = depth.data();
+  b.keys = keys.data();
+  b.values = vals.data();
+  b.ranges = ranges.data();
+  b.order = order.data();
+  b.chunk = c->fwd_chunk;
+  if (items) {
+    const int64_t ni = cnt[4];
+    if (ni > c->items.cap) return std::to_string(ni) + " work items > capacity " + std::to_string(c->items.cap);
+    if (!read_back(nch, (const uint32_t*)c->tile_nch.p, T) || !read_back(its, (const uint32_t*)c->items.p, 2 * ni))
+      return "work item read-back failed";
+    b.nch = nch.data();
+    b.items = its.data();
+    b.n_items = ni;
+  }
+  char msg[512];
+  if (sixdgs_debug_check_bins(&b, msg, sizeof(msg)) != SIXDGS_OK) return msg;
+  if (!items) return "";
+  // per pixel: the last contributor lies in its tile's run, T_final in [kTMin, 1];
+  // per tile: chunks = ceil(largest last contributor / chunk)
+  std::vector<uint32_t> last;
+  std::vector<float> Tf;
+  if (!read_back(last, (const uint32_t*)c->last.p, c->fwd_px) || !read_back(Tf, (const float*)c->T_final.p, c->fwd_px))
+    return "pixel state read-back failed";
+  std::vector<uint32_t> maxlast((size_t)std::max<int64_t>(T, 1), 0u);
+  for (int k = 0; k < c->vt.nview; k++) {
+    const ViewDesc& vd = c->vt.v[k];
+    for (int y = 0; y < vd.H; y++)
+      for (int x = 0; x < vd.W; x++) {
+        const int64_t pix = vd.pix_base + (int64_t)y * vd.W + x;
+        const uint32_t t = (uint32_t)(vd.tile_base + (y >> c->vt.tile_shift_y) * vd.ntx + (x >> c->vt.tile_shift_x));
+        const uint32_t run = ranges[2 * t + 1] - ranges[2 * t];
+        if (last[pix] > run)
+          return "view " + std::to_string(k) + " pixel (" + std::to_string(x) + ", " + std::to_string(y) +
+                 "): last contributor " + std::to_string(last[pix]) + " past its tile's " + std::to_string(run) +
+                 " pairs";
+        if (!(Tf[pix] >= kTMin && Tf[pix] <= 1.0f))
+          return "view " + std::to_string(k) + " pixel (" + std::to_string(x) + ", " + std::to_string(y) +
+                 "): final transmittance " + std::to_string(Tf[pix]) + " outside [1e-4, 1]";
+        maxlast[t] = std::max(maxlast[t], last[pix]);
+      }
+  }
+  for (int64_t t = 0; t < T; t++) {
+    const uint32_t want = (uint32_t)(((int64_t)maxlast[t] + c->fwd_chunk - 1) / c->fwd_chunk);
+    if (nch[t] != want)
+      return "tile " + std::to_string(t) + ": " + std::to_string(nch[t]) + " chunks, its last contributor needs " +
+             std::to_string(want);
+  }
+  return "";
+}
+
+// Debug mode: after a call that launched work, waits for it and checks every
+// guard; after a binning (bins = 1), or a training forward (bins = 2: with
+// the work items and the pixel state), also the invariants of the outputs.
+sixdgs_status debug_after(sixdgs_ctx* c, void* stream, sixdgs_status rc, int bins, const float* depth_dev = nullptr) {
+  if (!c->debug || rc != SIXDGS_OK) return rc;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(c, SIXDGS_ERR_HIP, "stream synchronisation failed");
+  std::string why;
+  for_each_buf(c, [&](auto& b, const char* name) {
+    if (why.empty()) why = b.guard_damage(name);
+  });
+  if (!why.empty()) return fail(c, SIXDGS_ERR_DEBUG, "debug: guard of " + why);
+  if (bins) {
+    why = debug_check_binning(c, depth_dev ? depth_dev : c->depth.p, bins == 2);
+    if (!why.empty()) return fail(c, SIXDGS_ERR_DEBUG, "debug: " + why);
+  }
+  return SIXDGS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,8 +592,8 @@ sixdgs_status sixdgs_create(sixdgs_ctx** out, const sixdgs_settings* s) {
     delete c;
     return SIXDGS_ERR_HIP;
   }
-  // the error flags in counters[2..3] are only ever set by kernels and cleared by sixdgs_check
-  if (!c->counters.ensure(kCounters) || hipMemset(c->counters.p, 0, kCounters * sizeof(uint32_t)) != hipSuccess) {
+  set_debug(c, (s->flags & SIXDGS_FLAG_DEBUG) != 0);
+  if (!init_counters(c)) {
     sixdgs_destroy(c);
     return SIXDGS_ERR_OOM;
   }
@@ -410,39 +606,7 @@ void sixdgs_destroy(sixdgs_ctx* c) {
   (void)hipDeviceSynchronize();
   collect_timing(c);
   for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
-  c->rec.release();
-  c->depth.release();
-  c->tiles.release();
-  c->dkey0.release();
-  c->dkey1.release();
-  c->dval0.release();
-  c->dval1.release();
-  c->poff.release();
-  c->pkey0.release();
-  c->pkey1.release();
-  c->pval0.release();
-  c->pval1.release();
-  c->ranges.release();
-  c->T_final.release();
-  c->bound.release();
-  c->tile_nch.release();
-  c->chunk_state.release();
-  c->items.release();
-  c->last.release();
-  c->counts.release();
-  c->g2d.release();
-  c->l1_partial.release();
-  c->ssim_maps.release();
-  c->ssim_partial.release();
-  c->rstate.release();
-  c->dens_dec.release();
-  c->dens_cnt.release();
-  c->dens_off.release();
-  c->dens_state.release();
-  c->blk_start.release();
-  c->tile_order.release();
-  c->order_state.release();
-  c->counters.release();
+  for_each_buf(c, [](auto& b, const char*) { b.release(); });
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   delete c;
 }
@@ -451,7 +615,13 @@ sixdgs_status sixdgs_set_settings(sixdgs_ctx* c, const sixdgs_settings* s) {
   if (!c || !s) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
   std::string why;
   if (!valid_settings(s, why)) return fail(c, SIXDGS_ERR_INVALID_ARG, why);
+  const bool debug = (s->flags & SIXDGS_FLAG_DEBUG) != 0;
   c->s = *s;
+  if (debug != c->debug) {
+    (void)hipDeviceSynchronize();
+    set_debug(c, debug);
+    if (!init_counters(c)) return fail(c, SIXDGS_ERR_OOM, "counters");
+  }
   return SIXDGS_OK;
 }
 
@@ -553,7 +723,7 @@ extern "C" {
 sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, const sixdgs_camera* cams, int32_t ncam,
                              float* const* images, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
-  return forward_impl(c, params, nullptr, n, cams, ncam, images, false, stream);
+  return debug_after(c, stream, forward_impl(c, params, nullptr, n, cams, ncam, images, false, stream), 2);
 }
 
 sixdgs_status sixdgs_build_cache(const float* params, int64_t n, float* cache, void* stream) {
@@ -567,11 +737,11 @@ sixdgs_status sixdgs_forward_cached(sixdgs_ctx* c, const float* params, const fl
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   if (n > 0 && !cache) return fail(c, SIXDGS_ERR_INVALID_ARG, "cache is NULL");
   if (c->lambda_raw) return fail(c, SIXDGS_ERR_STATE, "a cached forward takes the scalar lambda: detach the array");
-  return forward_impl(c, params, cache, n, cams, ncam, images, true, stream);
+  return debug_after(c, stream, forward_impl(c, params, cache, n, cams, ncam, images, true, stream), 1);
 }
 
-sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, int32_t ncam,
-                              const float* const* dl_dimages, float* grad, float* densify, void* stream) {
+static sixdgs_status backward_body(sixdgs_ctx* c, const float* params, int64_t n, int32_t ncam,
+                                   const float* const* dl_dimages, float* grad, float* densify, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
@@ -607,9 +777,15 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, int
   return check_launch(c, "preprocess backward");
 }
 
-sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, int32_t ncam,
-                                   const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
-                                   float beta2, float eps, int32_t step, float* densify, void* stream) {
+sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, int32_t ncam,
+                              const float* const* dl_dimages, float* grad, float* densify, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(c, stream, backward_body(c, params, n, ncam, dl_dimages, grad, densify, stream), 0);
+}
+
+static sixdgs_status backward_adam_body(sixdgs_ctx* c, float* params, int64_t n, int32_t ncam,
+                                        const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
+                                        float beta2, float eps, int32_t step, float* densify, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
@@ -649,8 +825,17 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, int3
   return check_launch(c, "preprocess backward + Adam");
 }
 
-sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images, const float* const* targets,
-                             const int64_t* numel, float* const* dl_dimages, float* loss, void* stream) {
+sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, int32_t ncam,
+                                   const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
+                                   float beta2, float eps, int32_t step, float* densify, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(
+      c, stream, backward_adam_body(c, params, n, ncam, dl_dimages, m, v, lr, beta1, beta2, eps, step, densify, stream),
+      0);
+}
+
+static sixdgs_status l1_loss_body(sixdgs_ctx* c, int32_t nimg, const float* const* images, const float* const* targets,
+                                  const int64_t* numel, float* const* dl_dimages, float* loss, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   if (nimg < 1 || nimg > kMaxViews) return fail(c, SIXDGS_ERR_INVALID_ARG, "nimg out of range");
   if (!images || !targets || !numel || !dl_dimages || !loss) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
@@ -662,6 +847,12 @@ sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* im
   if (!c->l1_partial.ensure(parts)) return fail(c, SIXDGS_ERR_OOM, "loss partials");
   launch_l1(nimg, images, targets, numel, dl_dimages, c->l1_partial.p, c->l1_partial.cap, loss, (hipStream_t)stream);
   return check_launch(c, "l1 loss");
+}
+
+sixdgs_status sixdgs_l1_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images, const float* const* targets,
+                             const int64_t* numel, float* const* dl_dimages, float* loss, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(c, stream, l1_loss_body(c, nimg, images, targets, numel, dl_dimages, loss, stream), 0);
 }
 
 }  // extern "C"
@@ -713,9 +904,9 @@ sixdgs_status sixdgs_l1_loss_noalloc(int32_t nimg, const float* const* images, c
   return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
 }
 
-sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images,
-                                   const float* const* targets, const int32_t* heights, const int32_t* widths,
-                                   float lambda_dssim, float* const* dl_dimages, float* loss, void* stream) {
+static sixdgs_status l1_dssim_loss_body(sixdgs_ctx* c, int32_t nimg, const float* const* images,
+                                        const float* const* targets, const int32_t* heights, const int32_t* widths,
+                                        float lambda_dssim, float* const* dl_dimages, float* loss, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   if (nimg < 1 || nimg > kMaxViews) return fail(c, SIXDGS_ERR_INVALID_ARG, "nimg out of range");
   if (!images || !targets || !heights || !widths || !dl_dimages || !loss)
@@ -734,6 +925,15 @@ sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* c, int32_t nimg, const float* con
   launch_l1_dssim(nimg, images, targets, heights, widths, lambda_dssim, dl_dimages, c->ssim_maps.p,
                   c->ssim_partial.p, loss, (hipStream_t)stream);
   return check_launch(c, "l1 + d-ssim loss");
+}
+
+sixdgs_status sixdgs_l1_dssim_loss(sixdgs_ctx* c, int32_t nimg, const float* const* images,
+                                   const float* const* targets, const int32_t* heights, const int32_t* widths,
+                                   float lambda_dssim, float* const* dl_dimages, float* loss, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(
+      c, stream,
+      l1_dssim_loss_body(c, nimg, images, targets, heights, widths, lambda_dssim, dl_dimages, loss, stream), 0);
 }
 
 sixdgs_status sixdgs_adam(float* params, const float* grad, float* m, float* v, int64_t n, const float* lr,
@@ -768,8 +968,8 @@ sixdgs_status sixdgs_decompose(const float* params, int64_t n, float* R, float* 
   return hipGetLastError() == hipSuccess ? SIXDGS_OK : SIXDGS_ERR_HIP;
 }
 
-sixdgs_status sixdgs_densify_plan(sixdgs_ctx* c, const float* params, int64_t n, const float* stats,
-                                  const sixdgs_density_settings* d, int64_t* n_out, void* stream) {
+static sixdgs_status densify_plan_body(sixdgs_ctx* c, const float* params, int64_t n, const float* stats,
+                                       const sixdgs_density_settings* d, int64_t* n_out, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (n < 0 || n > kMaxItems) return fail(c, SIXDGS_ERR_INVALID_ARG, "n out of range");
@@ -796,9 +996,15 @@ sixdgs_status sixdgs_densify_plan(sixdgs_ctx* c, const float* params, int64_t n,
   return check_launch(c, "density plan");
 }
 
-sixdgs_status sixdgs_densify_apply(sixdgs_ctx* c, const float* params, const float* m, const float* v,
-                                   const float* lambda_raw, int64_t n, const float* noise, float* params_out,
-                                   float* m_out, float* v_out, float* lambda_out, int64_t n_out, void* stream) {
+sixdgs_status sixdgs_densify_plan(sixdgs_ctx* c, const float* params, int64_t n, const float* stats,
+                                  const sixdgs_density_settings* d, int64_t* n_out, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(c, stream, densify_plan_body(c, params, n, stats, d, n_out, stream), 0);
+}
+
+static sixdgs_status densify_apply_body(sixdgs_ctx* c, const float* params, const float* m, const float* v,
+                                        const float* lambda_raw, int64_t n, const float* noise, float* params_out,
+                                        float* m_out, float* v_out, float* lambda_out, int64_t n_out, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   if (c->dens_n < 0 || c->dens_n != n || c->dens_params != params || c->dens_total != n_out)
     return fail(c, SIXDGS_ERR_STATE, "no matching sixdgs_densify_plan for these params, n and n_out");
@@ -812,6 +1018,16 @@ sixdgs_status sixdgs_densify_apply(sixdgs_ctx* c, const float* params, const flo
   return check_launch(c, "density apply");
 }
 
+sixdgs_status sixdgs_densify_apply(sixdgs_ctx* c, const float* params, const float* m, const float* v,
+                                   const float* lambda_raw, int64_t n, const float* noise, float* params_out,
+                                   float* m_out, float* v_out, float* lambda_out, int64_t n_out, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(c, stream,
+                     densify_apply_body(c, params, m, v, lambda_raw, n, noise, params_out, m_out, v_out, lambda_out,
+                                        n_out, stream),
+                     0);
+}
+
 sixdgs_status sixdgs_set_lambda(sixdgs_ctx* c, const float* lambda_raw, float* grad_lambda) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   if (!lambda_raw && grad_lambda) return fail(c, SIXDGS_ERR_INVALID_ARG, "grad_lambda needs lambda_raw");
@@ -820,9 +1036,9 @@ sixdgs_status sixdgs_set_lambda(sixdgs_ctx* c, const float* lambda_raw, float* g
   return SIXDGS_OK;
 }
 
-sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, int32_t ncam, const float* u,
-                         const float* v, const float* ex, const float* ey, const float* depth, const int32_t* alive,
-                         void* stream) {
+static sixdgs_status bin_body(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, int32_t ncam, const float* u,
+                              const float* v, const float* ex, const float* ey, const float* depth, const int32_t* alive,
+                              void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (n < 0) return fail(c, SIXDGS_ERR_INVALID_ARG, "n must be >= 0");
@@ -845,6 +1061,13 @@ sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, in
   c->fwd_n = n;
   c->stream = st;
   return rc;
+}
+
+sixdgs_status sixdgs_bin(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cams, int32_t ncam, const float* u,
+                         const float* v, const float* ex, const float* ey, const float* depth, const int32_t* alive,
+                         void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  return debug_after(c, stream, bin_body(c, n, cams, ncam, u, v, ex, ey, depth, alive, stream), 1, depth);
 }
 
 sixdgs_status sixdgs_export(sixdgs_ctx* c, int32_t what, void* dst, int64_t cap_bytes, int64_t* written) {
@@ -911,6 +1134,8 @@ sixdgs_status sixdgs_export(sixdgs_ctx* c, int32_t what, void* dst, int64_t cap_
 sixdgs_status sixdgs_check(sixdgs_ctx* c) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, SIXDGS_ERR_HIP, "stream synchronisation failed");
+  const sixdgs_status rc = debug_after(c, c->stream, SIXDGS_OK, 0);
+  if (rc != SIXDGS_OK) return rc;
   if (!c->counters.p) return SIXDGS_OK;
   uint32_t cnt[4];
   if (hipMemcpy(cnt, c->counters.p, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
@@ -926,6 +1151,24 @@ sixdgs_status sixdgs_check(sixdgs_ctx* c) {
     return fail(c, SIXDGS_ERR_CAPACITY,
                 "pair capacity exceeded: " + std::to_string(cnt[1]) + " pairs > " + std::to_string(c->sb.pcap));
   }
+  return SIXDGS_OK;
+}
+
+sixdgs_status sixdgs_debug_buffer(sixdgs_ctx* c, const char* name, void** ptr, int64_t* bytes) {
+  if (!c || !name || !ptr || !bytes) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
+  *ptr = nullptr;
+  *bytes = 0;
+  if (!c->debug) return fail(c, SIXDGS_ERR_STATE, "not in the debug mode");
+  bool known = false;
+  for_each_buf(c, [&](auto& b, const char* nm) {
+    if (std::strcmp(nm, name) == 0) {
+      known = true;
+      *ptr = b.p;
+      *bytes = b.bytes();
+    }
+  });
+  if (!known) return fail(c, SIXDGS_ERR_INVALID_ARG, std::string("no workspace buffer called ") + name);
+  if (!*ptr) return fail(c, SIXDGS_ERR_STATE, std::string(name) + " is not allocated");
   return SIXDGS_OK;
 }
 

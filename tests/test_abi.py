@@ -48,10 +48,25 @@ def test_create_rejects_unsupported_settings():
     h = ctypes.c_void_p()
     for kw in ({"tile_w": 16, "tile_h": 8}, {"batch": 100}, {"batch": 32}, {"lambda_opa": 1.5}, {"z_near": 0.0},
                {"pair_capacity": -1}, {"tile_w": 32, "tile_h": 16}, {"pair_capacity": 1 << 30},
-               {"batch": 256, "chunk": 128}, {"chunk": 32}, {"chunk": 1536}, {"chunk": 32768}, {"batch": -1}):
+               {"batch": 256, "chunk": 128}, {"chunk": 32}, {"chunk": 1536}, {"chunk": 32768}, {"batch": -1},
+               {"flags": 8}, {"flags": _lib.FLAG_DEBUG | 16}):
         s = _lib.default_settings(**kw)
         assert L.sixdgs_create(ctypes.byref(h), ctypes.byref(s)) == _lib.ERR_INVALID_ARG
         assert not h.value
+
+
+def test_every_documented_flag_passes_the_settings_check():
+    """Valid settings get past the checks (on a host without a device the
+    context then fails at its first HIP call, not as an argument error)."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    for f in (_lib.FLAG_COUNTS, _lib.FLAG_RGB_COLOR, _lib.FLAG_DEBUG,
+              _lib.FLAG_COUNTS | _lib.FLAG_RGB_COLOR | _lib.FLAG_DEBUG):
+        s = _lib.default_settings(flags=f, chunk=64, batch=64)
+        rc = L.sixdgs_create(ctypes.byref(h), ctypes.byref(s))
+        assert rc != _lib.ERR_INVALID_ARG, f
+        if rc == _lib.OK:
+            L.sixdgs_destroy(h)
 
 
 def test_l1_noalloc_rejects_bad_arguments_on_host():
