@@ -117,7 +117,6 @@ def main():
         tr.step([cam], target)
     kt = {k: r.ctx.kernel_time(k)[0] / 3 for k in _lib.KERNEL_NAMES}
     dom = max(kt, key=kt.get)
-    adam_ms = time_adam(tr)
 
     # timed region: only the dominant kernel is bracketed by events
     r.ctx.set_timing(1 << dom)
@@ -164,7 +163,7 @@ def main():
         "wall_s_timed": round(wall, 3),
         "kernel_ms": {_lib.KERNEL_NAMES[k]: round(v, 4) for k, v in kt.items()},
         "roofline": roof,
-        "hbm": hbm_report({_lib.KERNEL_NAMES[k]: v for k, v in kt.items()}, adam_ms, ms_step, n, nb, P, px, tiles),
+        "hbm": hbm_report({_lib.KERNEL_NAMES[k]: v for k, v in kt.items()}, ms_step, n, nb, P, px, tiles),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params_np, cam, args.cpu_pixels)
@@ -205,7 +204,7 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
     if dom == _lib.K_PREPROCESS:
         bytes_ = 304 * n + 4 * n + 52 * nb
     elif dom == _lib.K_PREPROCESS_BWD:
-        bytes_ = 608 * n + 4 * n + 36 * nb
+        bytes_ = alg_bytes(n, nb, P, px, tiles)["preprocess_bwd"]
     else:  # integer stage: depth keys and pair lists (sort passes read and write 8 B per item)
         bytes_ = 4 * n + 8 * nb * 2 * 4 + 8 * P * 2 * 2 + 8 * tiles
     achieved = bytes_ / (avg_ms * 1e-3) / 1e9
@@ -223,17 +222,18 @@ def alg_bytes(n, nb, P, px, tiles):
         "blend_fwd": 40 * P + 20 * px,                      # record per pair; colour, T, last per pixel
         "l1": 12 * 3 * px,                                  # image, target, gradient
         "blend_bwd": 40 * P + 32 * px + 36 * nb,            # as the forward + dL/dI; screen-space gradients
-        "preprocess_bwd": 608 * n + 4 * n + 36 * nb,        # params in, gradient out; screen-space gradients
-        "adam": 7 * 4 * 76 * n,                             # params, grad, m, v read; params, m, v written
+        # the chain rule fused with Adam: params, m, v in and out; tile counts; screen-space gradients
+        "preprocess_bwd": 6 * 304 * n + 4 * n + 36 * nb,
     }
 
 
-def hbm_report(kernel_ms, adam_ms, ms_step, n, nb, P, px, tiles):
+def hbm_report(kernel_ms, ms_step, n, nb, P, px, tiles):
     """Achieved algorithmic GB/s and the fraction of the 8 TB/s HBM peak per
     stage and for the whole step (the blend kernels are ALU-bound; their GB/s
-    is reported for completeness, their roofline is the fp32 rate)."""
+    is reported for completeness, their roofline is the fp32 rate).  The
+    step's Adam runs inside the preprocess backward."""
     b = alg_bytes(n, nb, P, px, tiles)
-    ms = dict(kernel_ms, adam=adam_ms)
+    ms = dict(kernel_ms)
     kernels = {}
     for k, t in ms.items():
         if k in b and t > 0:
@@ -245,18 +245,6 @@ def hbm_report(kernel_ms, adam_ms, ms_step, n, nb, P, px, tiles):
     step_gbs = total / (ms_step * 1e-3) / 1e9
     return {"step_bytes": int(total), "step_GBs": round(step_gbs, 1), "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
             "peak_GBs": HBM_PEAK_GBS, "kernels": kernels}
-
-
-def time_adam(tr, launches=20):
-    """Average duration of the Adam kernel on the step's own sizes (on copies
-    of the state, so the training state is left alone), with HIP events on the
-    launch stream."""
-    import torch
-    from paper_2410_04974_amd import _lib
-    p, g, m, v = (t.clone() for t in (tr.params, tr.grad, tr.m, tr.v))
-    cnt = torch.zeros(1, device=p.device, dtype=torch.int32)
-    _lib.adam_devstep(p, g, m, v, tr.lr, cnt, tr.betas[0], tr.betas[1], tr.eps)
-    return _timed(lambda: _lib.adam_devstep(p, g, m, v, tr.lr, cnt, tr.betas[0], tr.betas[1], tr.eps), launches)
 
 
 def c3_leg(steps, warmup):

@@ -200,6 +200,18 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* ctx, float* params, int64_t n, in
                                    const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
                                    float beta2, float eps, int32_t step, float* densify, void* stream);
 
+/* sixdgs_backward_adam with the step count on the device, for training steps
+ * captured in a graph (Sec. 5.1 training with Adam): the bias correction uses
+ * step = *step_counter + 1 (step_counter: device int32, required).  With
+ * advance != 0 the kernel's last workgroup increments *step_counter once every
+ * workgroup has read it; with advance = 0 the counter is left for the caller
+ * to advance (e.g. after another Adam that shares the step, sixdgs_adam_vec).
+ * Other arguments and errors as sixdgs_backward_adam. */
+sixdgs_status sixdgs_backward_adam_devstep(sixdgs_ctx* ctx, float* params, int64_t n, int32_t ncam,
+                                           const float* const* dl_dimages, float* m, float* v, const float* lr,
+                                           float beta1, float beta2, float eps, int32_t* step_counter,
+                                           int32_t advance, float* densify, void* stream);
+
 /* Learnable per-Gaussian lambda (Sec. 4.2; the paper trains it over a window
  * of iterations, Sec. 5.1).  lambda_raw: device [n] float32 raw values for the
  * following forwards on this context, Gaussian i using lambda =

@@ -85,6 +85,8 @@ def lib():
         L.sixdgs_forward_cached.argtypes = [P, P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
         L.sixdgs_backward.argtypes = [P, P, I64, I32, PP, P, P, P]
         L.sixdgs_backward_adam.argtypes = [P, P, I64, I32, PP, P, P, ctypes.POINTER(F), F, F, F, I32, P, P]
+        L.sixdgs_backward_adam_devstep.argtypes = [P, P, I64, I32, PP, P, P, ctypes.POINTER(F), F, F, F, P, I32, P,
+                                                   P]
         L.sixdgs_l1_loss.argtypes = [P, I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_l1_loss_noalloc.argtypes = [I32, PP, PP, ctypes.POINTER(I64), PP, P, P]
         L.sixdgs_adam.argtypes = [P, P, P, P, I64, ctypes.POINTER(F), F, F, F, I32, P]
@@ -104,7 +106,8 @@ def lib():
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
                      "sixdgs_build_cache", "sixdgs_forward_cached",
-                     "sixdgs_backward_adam", "sixdgs_l1_loss", "sixdgs_l1_loss_noalloc",
+                     "sixdgs_backward_adam", "sixdgs_backward_adam_devstep", "sixdgs_l1_loss",
+                     "sixdgs_l1_loss_noalloc",
                      "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_bin", "sixdgs_export", "sixdgs_check",
                      "sixdgs_set_timing", "sixdgs_kernel_time", "sixdgs_debug_check_bins",
                      "sixdgs_debug_buffer"):
@@ -115,7 +118,8 @@ def lib():
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
             "sixdgs_last_error", "sixdgs_forward", "sixdgs_build_cache", "sixdgs_forward_cached",
-            "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_l1_loss", "sixdgs_l1_loss_noalloc",
+            "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_backward_adam_devstep", "sixdgs_l1_loss",
+            "sixdgs_l1_loss_noalloc",
             "sixdgs_l1_dssim_loss",
             "sixdgs_adam", "sixdgs_adam_devstep", "sixdgs_adam_vec", "sixdgs_set_lambda", "sixdgs_decompose",
             "sixdgs_densify_plan", "sixdgs_densify_apply", "sixdgs_bin",
@@ -322,8 +326,11 @@ class Context:
                                        _ptrs(dl_dimages),
                                        ctypes.c_void_p(grad.data_ptr()), dens, ctypes.c_void_p(_stream(stream))))
 
-    def backward_adam(self, params, dl_dimages, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, densify=None,
-                      stream=None):
+    def backward_adam(self, params, dl_dimages, m, v, lr, step=None, beta1=0.9, beta2=0.999, eps=1e-15,
+                      densify=None, stream=None, step_counter=None, advance=True):
+        """Backward fused with the Adam step: the host's step count (from 1),
+        or step_counter (int32 CUDA [1]: step = counter + 1, advanced by the
+        kernel when ``advance``)."""
         n = params.shape[1]
         for t in dl_dimages:
             _check_f32_cuda(t, "dl_dimage")
@@ -338,10 +345,16 @@ class Context:
                 raise ValueError("densify must hold [2, N] floats")
         lrs = (ctypes.c_float * 6)(*[float(x) for x in lr])
         dens = ctypes.c_void_p(densify.data_ptr()) if densify is not None else None
-        self._rc(lib().sixdgs_backward_adam(self._h, ctypes.c_void_p(params.data_ptr()), n, len(dl_dimages),
-                                            _ptrs(dl_dimages),
-                                            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), lrs,
-                                            beta1, beta2, eps, int(step), dens, ctypes.c_void_p(_stream(stream))))
+        head = (self._h, ctypes.c_void_p(params.data_ptr()), n, len(dl_dimages), _ptrs(dl_dimages),
+                ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), lrs, beta1, beta2, eps)
+        if step_counter is not None:
+            import torch
+            if not (step_counter.is_cuda and step_counter.dtype == torch.int32 and step_counter.numel() >= 1):
+                raise ValueError("step_counter must be an int32 CUDA tensor")
+            self._rc(lib().sixdgs_backward_adam_devstep(*head, ctypes.c_void_p(step_counter.data_ptr()),
+                                                        int(bool(advance)), dens, ctypes.c_void_p(_stream(stream))))
+        else:
+            self._rc(lib().sixdgs_backward_adam(*head, int(step), dens, ctypes.c_void_p(_stream(stream))))
         self._fwd_sizes = None  # the parameters moved: the forward's state is spent
         self.generation += 1
 

@@ -182,7 +182,8 @@ sixdgs_status fail(sixdgs_ctx* c, sixdgs_status st, const std::string& msg) {
 }
 
 // counters: [0] binned entries, [1] pairs, [2] pair overflow flag, [3] look-back
-// timeout flag, [4] backward work items, [5] density-control outputs
+// timeout flag, [4] backward work items, [5] density-control outputs, [6] the
+// fused backward + Adam's finished workgroups (zero between launches)
 constexpr int kCounters = 8;
 
 // Bound on entries and pairs: the radix sort's look-back words hold 30-bit counts.
@@ -783,9 +784,12 @@ sixdgs_status sixdgs_backward(sixdgs_ctx* c, const float* params, int64_t n, int
   return debug_after(c, stream, backward_body(c, params, n, ncam, dl_dimages, grad, densify, stream), 0);
 }
 
+// step >= 1, or step_counter (device) with step = *step_counter + 1, advanced
+// after the update when `advance`.
 static sixdgs_status backward_adam_body(sixdgs_ctx* c, float* params, int64_t n, int32_t ncam,
                                         const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
-                                        float beta2, float eps, int32_t step, float* densify, void* stream) {
+                                        float beta2, float eps, int32_t step, int32_t* step_counter, bool advance,
+                                        float* densify, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (!c->have_fwd) return fail(c, SIXDGS_ERR_STATE, "backward needs a forward on this context first");
@@ -794,7 +798,7 @@ static sixdgs_status backward_adam_body(sixdgs_ctx* c, float* params, int64_t n,
   if (ncam != c->vt.nview) return fail(c, SIXDGS_ERR_INVALID_ARG, "ncam differs from the last forward's");
   if (!dl_dimages || !lr) return fail(c, SIXDGS_ERR_INVALID_ARG, "NULL argument");
   if (n > 0 && (!m || !v)) return fail(c, SIXDGS_ERR_INVALID_ARG, "m or v is NULL");
-  if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+  if ((!step_counter && step < 1) || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
     return fail(c, SIXDGS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
   ViewTable vt = c->vt;
   for (int k = 0; k < vt.nview; k++) {
@@ -816,10 +820,12 @@ static sixdgs_status backward_adam_body(sixdgs_ctx* c, float* params, int64_t n,
   }
   sixdgs_status rc = check_launch(c, "blend backward");
   if (rc != SIXDGS_OK) return rc;
-  const AdamArgs a = make_adam_args(lr, beta1, beta2, eps, step);
+  const AdamArgs a = make_adam_args(lr, beta1, beta2, eps, step_counter ? 1 : step);
   {
     Timer t(c, SIXDGS_K_PREPROCESS_BWD, st);
-    launch_preprocess_bwd_adam(params, n, vt, ds, c->tiles.p, c->g2d.p, m, v, a, nullptr, densify, st);
+    // counters[6]: the finished-workgroup count with which the kernel advances the step
+    launch_preprocess_bwd_adam(params, n, vt, ds, c->tiles.p, c->g2d.p, m, v, a, step_counter,
+                               advance ? c->counters.p + 6 : nullptr, densify, st);
   }
   c->have_fwd = false;  // the parameters moved
   return check_launch(c, "preprocess backward + Adam");
@@ -829,9 +835,22 @@ sixdgs_status sixdgs_backward_adam(sixdgs_ctx* c, float* params, int64_t n, int3
                                    const float* const* dl_dimages, float* m, float* v, const float* lr, float beta1,
                                    float beta2, float eps, int32_t step, float* densify, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
-  return debug_after(
-      c, stream, backward_adam_body(c, params, n, ncam, dl_dimages, m, v, lr, beta1, beta2, eps, step, densify, stream),
-      0);
+  return debug_after(c, stream,
+                     backward_adam_body(c, params, n, ncam, dl_dimages, m, v, lr, beta1, beta2, eps, step, nullptr,
+                                        false, densify, stream),
+                     0);
+}
+
+sixdgs_status sixdgs_backward_adam_devstep(sixdgs_ctx* c, float* params, int64_t n, int32_t ncam,
+                                           const float* const* dl_dimages, float* m, float* v, const float* lr,
+                                           float beta1, float beta2, float eps, int32_t* step_counter,
+                                           int32_t advance, float* densify, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (!step_counter) return fail(c, SIXDGS_ERR_INVALID_ARG, "step_counter is NULL");
+  return debug_after(c, stream,
+                     backward_adam_body(c, params, n, ncam, dl_dimages, m, v, lr, beta1, beta2, eps, 1, step_counter,
+                                        advance != 0, densify, stream),
+                     0);
 }
 
 static sixdgs_status l1_loss_body(sixdgs_ctx* c, int32_t nimg, const float* const* images, const float* const* targets,

@@ -136,9 +136,11 @@ void launch_build_cache(const float* params, int64_t n, float* cache, hipStream_
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st);
 // The same chain rule with an Adam step applied to params/m/v in place of writing the gradient.
+// step_dev: nullptr (the step is in `a`), or the device step count (step = *step_dev + 1); then
+// done, if not nullptr, is a zeroed device word with which the last workgroup advances the count.
 void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                                 const uint32_t* tiles, const float* g2d, float* m, float* v, const AdamArgs& a,
-                                const int32_t* step_dev, float* densify, hipStream_t st);
+                                int32_t* step_dev, uint32_t* done, float* densify, hipStream_t st);
 
 // sort.hip -- the integer stage
 constexpr int kMaxPasses = 4;  // radix passes of at most 8 bits over a 32-bit key

@@ -512,13 +512,16 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
 // The chain rule with the gradient rows kept in LDS, then one Adam step over
 // this wavefront's 64 Gaussians: rows are streamed in groups of 19 (the
 // chain rule's registers are free by then), so each lane has 57 loads in
-// flight instead of the three of a per-row update.
+// flight instead of the three of a per-row update.  With step_dev the step is
+// *step_dev + 1; with `done` as well, the last workgroup to finish (counted
+// in *done, zero before the launch and again after it) moves the counter on,
+// once every workgroup has read it.
 constexpr int kAdamGroup = 19;  // kRows = 4 groups
 __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, int64_t n, ViewTable vt,
                                                                 DevSettings ds, const uint32_t* __restrict__ tiles,
                                                                 const float* __restrict__ g2d,
                                                                 float* __restrict__ m, float* __restrict__ v,
-                                                                AdamArgs a, const int32_t* step_dev,
+                                                                AdamArgs a, int32_t* step_dev, uint32_t* done,
                                                                 float* __restrict__ densify) {
   __shared__ float s_g[kBlock / 64][kRows * 64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -530,28 +533,37 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (g >= n) return;
-  static_assert(kRows % kAdamGroup == 0, "row groups");
-  for (int r0 = 0; r0 < kRows; r0 += kAdamGroup) {
-    float pp[kAdamGroup], mm[kAdamGroup], vv[kAdamGroup];
+  if (g < n) {
+    static_assert(kRows % kAdamGroup == 0, "row groups");
+    for (int r0 = 0; r0 < kRows; r0 += kAdamGroup) {
+      float pp[kAdamGroup], mm[kAdamGroup], vv[kAdamGroup];
 #pragma unroll
-    for (int j = 0; j < kAdamGroup; j++) {
-      const int64_t k = (int64_t)(r0 + j) * n + g;
-      pp[j] = params[k];
-      mm[j] = m[k];
-      vv[j] = v[k];
+      for (int j = 0; j < kAdamGroup; j++) {
+        const int64_t k = (int64_t)(r0 + j) * n + g;
+        pp[j] = params[k];
+        mm[j] = m[k];
+        vv[j] = v[k];
+      }
+#pragma unroll
+      for (int j = 0; j < kAdamGroup; j++) {
+        const int r = r0 + j;
+        const int64_t k = (int64_t)r * n + g;
+        const int grp = adam_row_group(r);  // selected, not indexed: keeps a.lr out of scratch memory
+        const float lr = grp == 0 ? a.lr[0] : grp == 1 ? a.lr[1] : grp == 2 ? a.lr[2] : grp == 3 ? a.lr[3]
+                       : grp == 4 ? a.lr[4] : a.lr[5];
+        adam_update(pp[j], s_g[wv][r * 64 + lane], mm[j], vv[j], lr, a);
+        params[k] = pp[j];
+        m[k] = mm[j];
+        v[k] = vv[j];
+      }
     }
-#pragma unroll
-    for (int j = 0; j < kAdamGroup; j++) {
-      const int r = r0 + j;
-      const int64_t k = (int64_t)r * n + g;
-      const int grp = adam_row_group(r);  // selected, not indexed: keeps a.lr out of scratch memory
-      const float lr = grp == 0 ? a.lr[0] : grp == 1 ? a.lr[1] : grp == 2 ? a.lr[2] : grp == 3 ? a.lr[3]
-                     : grp == 4 ? a.lr[4] : a.lr[5];
-      adam_update(pp[j], s_g[wv][r * 64 + lane], mm[j], vv[j], lr, a);
-      params[k] = pp[j];
-      m[k] = mm[j];
-      v[k] = vv[j];
+  }
+  if (done) {
+    // every thread of this workgroup has used the step count by now
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(done, 1u) == gridDim.x - 1) {
+      *step_dev += 1;
+      *done = 0u;
     }
   }
 }
@@ -586,11 +598,11 @@ void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, 
 
 void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                                 const uint32_t* tiles, const float* g2d, float* m, float* v, const AdamArgs& a,
-                                const int32_t* step_dev, float* densify, hipStream_t st) {
+                                int32_t* step_dev, uint32_t* done, float* densify, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_preprocess_bwd_adam, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, m, v, a,
-                     step_dev, densify);
+                     step_dev, step_dev ? done : nullptr, densify);
 }
 
 }  // namespace sixdgs

@@ -83,6 +83,44 @@ def test_fused_backward_adam_equals_backward_then_adam():
     assert not np.array_equal(outs[0][0], pn)  # the parameters moved
 
 
+def test_fused_step_count_on_the_device_matches_the_host_count():
+    """The fused backward + Adam with the step on the device (the training
+    default) against the same kernel given the host's step count: the
+    counter reads 3 after three steps, and the states agree."""
+    from paper_2410_04974_amd import Renderer, Trainer
+    w, pn = G.scene("c2", 20000)
+    cam = synth.default_camera(160, 128)
+    tgt = Renderer().forward(torch.from_numpy(synth.perturbed(pn)).to(G.DEV), [cam])
+    tr = Trainer(torch.from_numpy(pn).to(G.DEV), Renderer())
+    for _ in range(3):
+        tr.step([cam], tgt)
+    torch.cuda.synchronize()
+    assert int(tr.step_counter.item()) == 3 and tr.step_count == 3
+    # the host-count path of the same kernel, driven by hand
+    r = Renderer()
+    p = torch.from_numpy(pn).to(G.DEV)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    loss = torch.zeros(1, device=G.DEV)
+    img = [torch.empty(3, cam.height, cam.width, device=G.DEV)]
+    dl = [torch.empty_like(img[0])]
+    for k in range(3):
+        r.forward(p, [cam], out=img)
+        r.ctx.l1_loss(img, tgt, dl, loss)
+        r.ctx.backward_adam(p, dl, m, v, tr.lr, k + 1)
+    torch.cuda.synchronize()
+    for a, b in ((tr.params, p), (tr.m, m), (tr.v, v)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        close = np.isclose(a, b, rtol=1e-4, atol=1e-6 * max(1.0, np.abs(b).max()))
+        assert close.mean() > 1 - 1e-3, close.mean()
+    # advance = 0 leaves the counter to the caller
+    r.forward(p, [cam], out=img)
+    r.ctx.l1_loss(img, tgt, dl, loss)
+    cnt = torch.full((1,), 7, device=G.DEV, dtype=torch.int32)
+    r.ctx.backward_adam(p, dl, m, v, tr.lr, step_counter=cnt, advance=False)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 7
+
+
 def test_densify_statistics_match_oracle():
     w, pn = G.scene("c1", 15000)
     cams = [synth.default_camera(160, 128), synth.look_at_camera((0.0, -4.0, 1.0), 96, 80)]
