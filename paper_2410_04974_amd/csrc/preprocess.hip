@@ -259,7 +259,7 @@ struct GradToLDS {
 // parameters, summed over the views, handed to the sink row by row.  params
 // may be updated in place after this returns (by the fused Adam step), so it
 // is not declared __restrict__.
-template <class Sink>
+template <bool ONE_VIEW, class Sink>
 __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int64_t g, const ViewTable& vt,
                                              const DevSettings& ds, const uint32_t* __restrict__ tiles,
                                              const float* __restrict__ g2d, const Sink& sink,
@@ -296,12 +296,14 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
 
   // an invisible lane's rows are exact zeros whatever its parameters
   auto put = [&](int row, float v) { sink.put(row, n, g, any ? v : 0.f); };
-  // accumulators summed over views
-  float g_beta[16][3];
+  // accumulators summed over views; with one view the colour gradient is
+  // formed at the end from that view's three channel terms and SH direction
+  float g_beta[ONE_VIEW ? 1 : 16][3];
 #pragma unroll
-  for (int k = 0; k < 16; k++)
+  for (int k = 0; k < (ONE_VIEW ? 1 : 16); k++)
 #pragma unroll
     for (int c = 0; c < 3; c++) g_beta[k][c] = 0.f;
+  float dsc1[3] = {0.f, 0.f, 0.f}, sdir1[3] = {0.f, 0.f, 1.f};
   float g_mup[3] = {0, 0, 0}, g_mud[3] = {0, 0, 0}, g_alpha = 0.f;
   float g_Sc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dSigma_cond (symmetric)
   float g_Spd_mu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // mu_cond part of dL/dSigma_pd
@@ -319,6 +321,51 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     for (int k = 0; k < kG2D; k++) gp[k] = vi == 0 ? gp0[k] : g2d[e * kG2D + k];
     ViewState w;
     view_state<true>(s, vd, lam, ds.z_near, w);
+    // colour first (Sec. 4.2): its share of dL/dmu_c, after which the 48
+    // coefficients are dead while the geometry's chain rule runs
+    float gmu[3] = {0.f, 0.f, 0.f};
+    float dsc[3];
+    if (ds.rgb_color) {
+      // No-SH colour: rgb = sigmoid(c), no dependence on the viewing direction
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const float col = M::sigmoid(beta[0][c]);
+        dsc[c] = gp[6 + c] * col * (1.f - col);
+        if constexpr (!ONE_VIEW) g_beta[0][c] += dsc[c];
+      }
+    } else {
+      // SH colour: rgb = sigmoid(sum beta Y(s)), s = (mu_c - C)/|mu_c - C|
+      float Y[16];
+      sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
+      float wsum[16];
+#pragma unroll
+      for (int k = 0; k < 16; k++) wsum[k] = 0.f;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
+        const float col = M::sigmoid(acc);
+        dsc[c] = gp[6 + c] * col * (1.f - col);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+          if constexpr (!ONE_VIEW) g_beta[k][c] += dsc[c] * Y[k];
+          wsum[k] += dsc[c] * beta[k][c];
+        }
+      }
+      float gs[3];
+      sh_basis_vjp(w.sdir[0], w.sdir[1], w.sdir[2], wsum, gs);
+      const float sdot = w.sdir[0] * gs[0] + w.sdir[1] * gs[1] + w.sdir[2] * gs[2];
+#pragma unroll
+      for (int k = 0; k < 3; k++) gmu[k] = M::div(gs[k] - w.sdir[k] * sdot, w.ns);
+    }
+    if constexpr (ONE_VIEW) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        dsc1[c] = dsc[c];
+        sdir1[c] = w.sdir[c];
+      }
+    }
     const float gu = gp[0], gv = gp[1], gqxx = gp[2], gqxy = gp[3], gqyy = gp[4], gac = gp[5];
     const float z = w.p[2], fx = vd.fx, fy = vd.fy;
     dens_norm += M::sqrt((gu * 0.5f * vd.W) * (gu * 0.5f * vd.W) + (gv * 0.5f * vd.H) * (gv * 0.5f * vd.H));
@@ -371,42 +418,8 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     dp1 += gv * fy * iz;
     dp2 -= (gu * fx * w.p[0] + gv * fy * w.p[1]) * iz2;
     // p = R mu_c + t
-    float gmu[3];
 #pragma unroll
-    for (int k = 0; k < 3; k++) gmu[k] = vd.R[k] * dp0 + vd.R[3 + k] * dp1 + vd.R[6 + k] * dp2;
-    if (ds.rgb_color) {
-      // No-SH colour: rgb = sigmoid(c), no dependence on the viewing direction
-#pragma unroll
-      for (int c = 0; c < 3; c++) {
-        const float col = M::sigmoid(beta[0][c]);
-        g_beta[0][c] += gp[6 + c] * col * (1.f - col);
-      }
-    } else {
-      // SH colour (Sec. 4.2): rgb = sigmoid(sum beta Y(s)), s = (mu_c - C)/|mu_c - C|
-      float Y[16];
-      sh_basis(w.sdir[0], w.sdir[1], w.sdir[2], Y);
-      float wsum[16];
-#pragma unroll
-      for (int k = 0; k < 16; k++) wsum[k] = 0.f;
-#pragma unroll
-      for (int c = 0; c < 3; c++) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
-        const float col = M::sigmoid(acc);
-        const float dsc = gp[6 + c] * col * (1.f - col);
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-          g_beta[k][c] += dsc * Y[k];
-          wsum[k] += dsc * beta[k][c];
-        }
-      }
-      float gs[3];
-      sh_basis_vjp(w.sdir[0], w.sdir[1], w.sdir[2], wsum, gs);
-      const float sdot = w.sdir[0] * gs[0] + w.sdir[1] * gs[1] + w.sdir[2] * gs[2];
-#pragma unroll
-      for (int k = 0; k < 3; k++) gmu[k] += M::div(gs[k] - w.sdir[k] * sdot, w.ns);
-    }
+    for (int k = 0; k < 3; k++) gmu[k] += vd.R[k] * dp0 + vd.R[3 + k] * dp1 + vd.R[6 + k] * dp2;
     // slice (Sec. 3.2): mu_c = mu_p + K x, D = x^T A x, alpha_c = alpha exp(-lambda D)
     const float dD = -lam * w.ac * gac;
     g_lam -= w.D * w.ac * gac;  // d alpha_c / d lambda = -D alpha_c
@@ -489,10 +502,26 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     put(kRowMuP + k, g_mup[k]);
     put(kRowMuD + k, g_mud[k]);
   }
+  if constexpr (ONE_VIEW) {
+    if (ds.rgb_color) {
 #pragma unroll
-  for (int k = 0; k < 16; k++)
+      for (int c = 0; c < 3; c++) put(kRowSH + c, dsc1[c]);
 #pragma unroll
-    for (int c = 0; c < 3; c++) put(kRowSH + 3 * k + c, g_beta[k][c]);
+      for (int r = kRowSH + 3; r < kRowSH + 48; r++) put(r, 0.f);
+    } else {
+      float Y[16];
+      sh_basis(sdir1[0], sdir1[1], sdir1[2], Y);
+#pragma unroll
+      for (int k = 0; k < 16; k++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) put(kRowSH + 3 * k + c, dsc1[c] * Y[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) put(kRowSH + 3 * k + c, g_beta[k][c]);
+  }
   put(kRowOpa, g_alpha * s.alpha * (1.f - s.alpha));
   if (densify) {
     densify[g] += dens_norm;
@@ -501,12 +530,12 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
   if (ds.lambda_raw && ds.grad_lambda) ds.grad_lambda[g] = any ? g_lam * lam * (1.f - lam) : 0.f;
 }
 
-template <class Sink>
+template <bool ONE_VIEW, class Sink>
 __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, int64_t n, ViewTable vt,
                                                            DevSettings ds, const uint32_t* __restrict__ tiles,
                                                            const float* __restrict__ g2d, Sink sink,
                                                            float* __restrict__ densify) {
-  bwd_gaussian(params, n, (int64_t)blockIdx.x * kBlock + threadIdx.x, vt, ds, tiles, g2d, sink, densify);
+  bwd_gaussian<ONE_VIEW>(params, n, (int64_t)blockIdx.x * kBlock + threadIdx.x, vt, ds, tiles, g2d, sink, densify);
 }
 
 // The chain rule with the gradient rows kept in LDS, then one Adam step over
@@ -517,6 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd(const float* params, 
 // in *done, zero before the launch and again after it) moves the counter on,
 // once every workgroup has read it.
 constexpr int kAdamGroup = 19;  // kRows = 4 groups
+template <bool ONE_VIEW>
 __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, int64_t n, ViewTable vt,
                                                                 DevSettings ds, const uint32_t* __restrict__ tiles,
                                                                 const float* __restrict__ g2d,
@@ -526,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
   __shared__ float s_g[kBlock / 64][kRows * 64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  bwd_gaussian(params, n, g, vt, ds, tiles, g2d, GradToLDS{s_g[wv]}, densify);
+  bwd_gaussian<ONE_VIEW>(params, n, g, vt, ds, tiles, g2d, GradToLDS{s_g[wv]}, densify);
   if (step_dev) adam_device_step(a, *step_dev);
   // each lane reads back only what it wrote: ordering the wavefront's own LDS
   // accesses is enough
@@ -539,22 +569,20 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
       float pp[kAdamGroup], mm[kAdamGroup], vv[kAdamGroup];
 #pragma unroll
       for (int j = 0; j < kAdamGroup; j++) {
-        const int64_t k = (int64_t)(r0 + j) * n + g;
-        pp[j] = params[k];
-        mm[j] = m[k];
-        vv[j] = v[k];
+        pp[j] = row_ld(params, r0 + j, n, g);
+        mm[j] = row_ld(m, r0 + j, n, g);
+        vv[j] = row_ld(v, r0 + j, n, g);
       }
 #pragma unroll
       for (int j = 0; j < kAdamGroup; j++) {
         const int r = r0 + j;
-        const int64_t k = (int64_t)r * n + g;
         const int grp = adam_row_group(r);  // selected, not indexed: keeps a.lr out of scratch memory
         const float lr = grp == 0 ? a.lr[0] : grp == 1 ? a.lr[1] : grp == 2 ? a.lr[2] : grp == 3 ? a.lr[3]
                        : grp == 4 ? a.lr[4] : a.lr[5];
         adam_update(pp[j], s_g[wv][r * 64 + lane], mm[j], vv[j], lr, a);
-        params[k] = pp[j];
-        m[k] = mm[j];
-        v[k] = vv[j];
+        row_st(params, r, n, g, pp[j]);
+        row_st(m, r, n, g, mm[j]);
+        row_st(v, r, n, g, vv[j]);
       }
     }
   }
@@ -592,8 +620,9 @@ void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, 
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess_bwd<GradToBuffer>, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d,
-                     GradToBuffer{grad}, densify);
+  // one view: the colour gradient needs no accumulators over views
+  auto k = vt.nview == 1 ? k_preprocess_bwd<true, GradToBuffer> : k_preprocess_bwd<false, GradToBuffer>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, GradToBuffer{grad}, densify);
 }
 
 void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
@@ -601,7 +630,8 @@ void launch_preprocess_bwd_adam(float* params, int64_t n, const ViewTable& vt, c
                                 int32_t* step_dev, uint32_t* done, float* densify, hipStream_t st) {
   if (n <= 0) return;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess_bwd_adam, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, m, v, a,
+  auto k = vt.nview == 1 ? k_preprocess_bwd_adam<true> : k_preprocess_bwd_adam<false>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, params, n, vt, s, tiles, g2d, m, v, a,
                      step_dev, step_dev ? done : nullptr, densify);
 }
 
