@@ -74,16 +74,37 @@ constexpr uint32_t kStIncl = 2u << 30;
 constexpr uint32_t kStVal = kStAgg - 1u;
 constexpr int kMaxSpin = 1 << 20;
 
+// The global digit histograms are kept as kGhCopies copies that workgroups
+// add into by workgroup index: every workgroup adds its counts of every digit
+// at its end, and atomics on one word serialise (about 17 ns apart on MI355X:
+// 800 workgroups adding into 128 words took 16 us, 14 of them waiting), so
+// the copies cut each word's queue; readers sum the copies.
+constexpr int kGhCopies = 16;
+constexpr int kGhStride = kMaxPasses * 256;  // words from one copy to the next
+
+__device__ __forceinline__ uint32_t* ghist_copy(uint32_t* ghist, int64_t blk) {
+  return ghist + (blk % kGhCopies) * kGhStride;
+}
+// Total count of digit d in the histogram at g (one pass's row of copy 0).
+__device__ __forceinline__ uint32_t ghist_total(const uint32_t* g, int d) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int c = 0; c < kGhCopies; c++) s += g[c * kGhStride + d];
+  return s;
+}
+
 // Radix state of one sort: global digit histograms, tickets and look-back
 // status words, laid out in one buffer.
 struct RadixState {
-  uint32_t* ghist;        // [kMaxPasses][256]
+  uint32_t* ghist;        // [kGhCopies][kMaxPasses][256]
   uint32_t* tickets;      // [kMaxPasses] passes, then [2] scans (padded to 256 words)
   uint32_t* status;       // [kMaxPasses][nblk][256]: look-back words (depth sort), chunk tables (pair sort)
   uint64_t* scan_status;  // [2][nscan] look-back words of the two scans over entries
   int64_t nblk, nscan;
   int items;              // items per thread of the passes
-  __host__ __device__ int64_t words() const { return (int64_t)kMaxPasses * 256 * (nblk + 2) + 4 * nscan; }
+  __host__ __device__ int64_t words() const {
+    return (int64_t)kMaxPasses * 256 * (nblk + 1 + kGhCopies) + 4 * nscan;
+  }
 };
 
 inline int64_t radix_blocks(int64_t bound, int items) {
@@ -97,8 +118,8 @@ RadixState radix_state(uint32_t* base, int64_t bound, int items, bool with_scans
   r.nblk = radix_blocks(bound, items);
   r.nscan = with_scans ? (bound + kChunk - 1) / kChunk : 0;
   r.ghist = base;
-  r.tickets = base + kMaxPasses * 256;
-  r.status = base + 2 * kMaxPasses * 256;
+  r.tickets = base + kGhCopies * kGhStride;
+  r.status = base + (kGhCopies + 1) * kGhStride;
   r.scan_status = reinterpret_cast<uint64_t*>(r.status + (int64_t)kMaxPasses * r.nblk * 256);
   return r;
 }
@@ -242,9 +263,10 @@ __global__ void __launch_bounds__(kBlock) k_scan1(F f, G g, const uint32_t* coun
   }
   if (HIST) {
     __syncthreads();
+    uint32_t* gh = ghist_copy(ghist, blk);
 #pragma unroll
     for (int p = 0; p < kMaxPasses; p++)
-      if (s_h[p][t]) atomicAdd(&ghist[p * 256 + t], s_h[p][t]);
+      if (s_h[p][t]) atomicAdd(&gh[p * 256 + t], s_h[p][t]);
   }
 }
 
@@ -316,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
   if (base >= count) return;  // uniform; no later workgroup has items, so none waits on this one
   const uint32_t mask = (1u << dbits) - 1u;
   const bool own = (uint32_t)t <= mask;
-  const uint32_t gh = own ? ghist[t] : 0u;  // issued early: used after the look-back
+  const uint32_t gh = own ? ghist_total(ghist, t) : 0u;  // issued early: used after the look-back
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t wbase = base + (int64_t)wv * kWaveItems;  // each wavefront ranks consecutive items
   uint32_t key[ITEMS], val[ITEMS], loc[ITEMS];
@@ -490,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_digit_scan(uint32_t* __restrict__ ta
   const uint32_t count = load_count(count_ptr, cap, cap);
   const int64_t used = ((int64_t)count + chunk_items - 1) / chunk_items;
   uint32_t dbase;  // items of the digits below d: the total of this scan
-  block_scan_excl((uint32_t)t < (uint32_t)d ? ghist[t] : 0u, dbase);
+  block_scan_excl((uint32_t)t < (uint32_t)d ? ghist_total(ghist, t) : 0u, dbase);
   uint32_t* row = table + (int64_t)d * nblk;
   const int64_t per = (used + kBlock - 1) / kBlock;
   const int64_t b0 = min<int64_t>((int64_t)t * per, used), b1 = min<int64_t>(b0 + per, used);
@@ -658,6 +680,9 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
   __shared__ uint32_t s_ntx[kBlock];    // tiles per row of the entry's view
   __shared__ uint32_t s_h[kMaxPasses][256];
   const int t = threadIdx.x;
+  // blk_start holds an entry for every workgroup of the grid: read with the
+  // counts, not after them
+  uint32_t ib = blk_start[blockIdx.x];
   const uint32_t nb = counters[0];
   const uint32_t P = counters[1];
   if (P > pcap) {
@@ -670,7 +695,6 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
   const uint32_t mask = (1u << dbits) - 1u;
 #pragma unroll
   for (int p = 0; p < kMaxPasses; p++) s_h[p][t] = 0;
-  uint32_t ib = blk_start[blockIdx.x];
   for (;;) {
     const uint32_t i = ib + t;
     if (i < nb) {
@@ -722,8 +746,9 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
     if (done) break;
     ib += kBlock;
   }
+  uint32_t* gh = ghist_copy(ghist, blockIdx.x);
   for (int p = 0; p < npass; p++)
-    if (s_h[p][t]) atomicAdd(&ghist[p * 256 + t], s_h[p][t]);
+    if (s_h[p][t]) atomicAdd(&gh[p * 256 + t], s_h[p][t]);
   // this chunk's counts of the first pass's digits (the chunk is the pass's)
   if ((uint32_t)t <= mask) table0[(int64_t)t * gridDim.x + blockIdx.x] = s_h[0][t];
 }
@@ -919,7 +944,7 @@ void launch_bin_count(SortBuffers& b, hipStream_t st) {
   // sort's histograms, the tile ranges, the tile order's counts and the
   // backward work-item scan's state
   const ZeroList z{{b.order_state, b.chunk_state, b.rstate_pairs, nullptr},
-                   {(int64_t)kOrderStateWords, chunk_scan_words(b.total_tiles), 2 * kMaxPasses * 256, 0}};
+                   {(int64_t)kOrderStateWords, chunk_scan_words(b.total_tiles), (kGhCopies + 1) * kGhStride, 0}};
   int64_t prep = rs.words() / 4;
   for (int k = 0; k < 3; k++) prep = std::max(prep, z.n[k]);
   prep = std::max(prep, b.total_tiles);
@@ -947,7 +972,7 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bo
   if (regrown) {
     // the passes write every table entry they read: only the histograms (and
     // the unused tickets) start from zero
-    const int64_t zero_words = 2 * kMaxPasses * 256;
+    const int64_t zero_words = (kGhCopies + 1) * kGhStride;
     const ZeroList z{{nullptr, nullptr, nullptr, nullptr}, {0, 0, 0, 0}};
     const int64_t prep = std::max<int64_t>(zero_words / 4, b.E);
     hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
