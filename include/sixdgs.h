@@ -375,7 +375,7 @@ typedef struct {
   const uint32_t* keys;    /* [P] global tile id of each sorted pair */
   const uint32_t* values;  /* [P] entry id of each sorted pair */
   const uint32_t* ranges;  /* [2T] [start, end) of each tile's run of pairs, (0, 0) if none */
-  const uint32_t* order;   /* [T] the compositing order of the tiles, or NULL */
+  const uint32_t* order;   /* [T] the compositing order of the tiles, or NULL (not checked) */
   int32_t chunk;           /* the backward's chunk length (with nch and items) */
   const uint32_t* nch;     /* [T] backward chunks per tile, or NULL (no work items) */
   const uint32_t* items;   /* [2 n_items] (tile, chunk) work items */
@@ -393,7 +393,7 @@ typedef struct {
  *   - the order, if given, is a permutation with list lengths of
  *     non-increasing bit length;
  *   - each tile, if nch is given, has at most ceil(run / chunk) chunks, and
- *     the items are exactly (t, 0 .. nch[t] - 1) for t in the order.
+ *     the items hold every (t, c) with c < nch[t] exactly once, in any order.
  * Returns SIXDGS_OK, SIXDGS_ERR_DEBUG with the first violation written to
  * msg (NUL-terminated, at most msg_cap bytes, if msg is not NULL), or
  * SIXDGS_ERR_INVALID_ARG for a NULL or inconsistent state.  The debug mode

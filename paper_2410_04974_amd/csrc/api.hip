@@ -94,7 +94,7 @@ struct sixdgs_ctx {
   DevBuf<uint32_t> last, counts;
   // backward work items: chunk-boundary state, per-tile chunk counts, (tile, chunk) list
   DevBuf<float4> bound;
-  DevBuf<uint32_t> tile_nch, chunk_state;
+  DevBuf<uint32_t> tile_nch;
   DevBuf<uint2> items;
   int64_t bwd_grid = 0;
   int32_t fwd_chunk = 256;   // chunk length the last forward saved its boundary state for
@@ -156,7 +156,6 @@ void for_each_buf(sixdgs_ctx* c, F f) {
   f(c->counts, "contributor counts");
   f(c->bound, "chunk boundary state");
   f(c->tile_nch, "tile chunk counts");
-  f(c->chunk_state, "work item scan state");
   f(c->items, "work items");
   f(c->dens_dec, "density decisions");
   f(c->dens_cnt, "density counts");
@@ -347,7 +346,7 @@ void fill_sort_buffers(sixdgs_ctx* c, int64_t E) {
   b.tile_order = c->tile_order.p;
   b.order_state = c->order_state.p;
   b.g2d = c->bin_g2d;
-  b.chunk_state = c->chunk_state.p;
+  b.n_items = c->counters.p + 4;
   b.counters = c->counters.p;
 }
 
@@ -412,7 +411,6 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
   if (!ensure_scratch(c, E, std::max<int64_t>(c->pkey0.cap, fixed ? c->s.pair_capacity : 0)))
     return fail(c, SIXDGS_ERR_OOM, "sort scratch");
   if (!c->ranges.ensure(std::max<int64_t>(c->vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "tile ranges");
-  if (!c->chunk_state.ensure(chunk_scan_words(c->vt.total_tiles))) return fail(c, SIXDGS_ERR_OOM, "tile scan");
   if (!c->tile_order.ensure(std::max<int64_t>(c->vt.total_tiles, 1)) || !c->order_state.ensure(order_state_words()))
     return fail(c, SIXDGS_ERR_OOM, "tile order");
   fill_sort_buffers(c, E);
@@ -703,9 +701,6 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
     launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->fwd_batch, !inference, st);
   }
   if (inference) return check_launch(c, "blend forward");
-  launch_chunk_items(c->tile_nch.p, c->tile_order.p, vt.total_tiles, c->items.p, grid, c->chunk_state.p,
-                     c->counters.p + 4,
-                     c->counters.p + 3, st);
   rc = check_launch(c, "blend forward");
   if (rc != SIXDGS_OK) return rc;
   c->have_fwd = true;

@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
                                                       const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ pval, BlendState bs) {
   __shared__ FwdWaveLDS W[kWaves];
-  __shared__ uint32_t s_maxlast;
+  __shared__ uint32_t s_maxlast, s_ibase;
   const int tile = (int)bs.order[blockIdx.x];
   const int vi = find_view(vt, tile);
   const ViewDesc& vd = vt.v[vi];
@@ -365,7 +365,18 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
   const uint32_t wlast = wave_max(last);
   if (l == 0) atomicMax(&s_maxlast, wlast);
   __syncthreads();
-  if (threadIdx.x == 0) bs.tile_nch[tile] = (s_maxlast + chunk - 1) / chunk;
+  // the tile's backward work items (tile, 0 .. nch - 1), appended to the list
+  // where the tiles finished so far end (*n_items is zero before the launch)
+  const uint32_t nch = (s_maxlast + chunk - 1) / chunk;
+  if (threadIdx.x == 0) {
+    bs.tile_nch[tile] = nch;
+    s_ibase = nch ? atomicAdd(bs.n_items, nch) : 0u;
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < nch; k += kBlock) {
+    const int64_t slot = (int64_t)s_ibase + k;
+    if (slot < bs.items_cap) bs.items[slot] = make_uint2((uint32_t)tile, k);
+  }
 }
 
 // ------------------------------------------------------------- reductions
@@ -443,7 +454,11 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
   __shared__ BatchLDS L;
   __shared__ float s_g[kG2D][kBlock];  // per staged Gaussian, summed over the four wavefronts
   __shared__ uint32_t s_maxlast;
-  if (blockIdx.x >= *bs.n_items) return;  // uniform
+  // the list holds the items in the order the forward's tiles finished
+  // (measured: 5 us faster on c2 than taking it from the back, the long
+  // tiles' chunks first)
+  const uint32_t ni = (uint32_t)min<int64_t>(*bs.n_items, bs.items_cap);
+  if (blockIdx.x >= ni) return;  // uniform
   const uint2 item = bs.items[blockIdx.x];
   const int tile = (int)item.x;
   const uint32_t chunk = bs.chunk;

@@ -80,28 +80,28 @@ std::string check(const sixdgs_bin_state& s) {
         return at("order position", i) + ": a longer list after a shorter one";
     }
   }
-  // the backward's work items
+  // the backward's work items: every (t, c) with c < nch[t] exactly once, in any order
   if (s.nch) {
-    if (!s.order) return "work items need the order";
     if (s.chunk < 1) return "chunk must be positive";
-    int64_t total = 0;
+    std::vector<int64_t> item0(T + 1, 0);  // first item of each tile
     for (int64_t t = 0; t < T; t++) {
       const int64_t most = ((int64_t)run((uint32_t)t) + s.chunk - 1) / s.chunk;
       if ((int64_t)s.nch[t] > most)
         return at("tile", t) + ": " + std::to_string(s.nch[t]) + " chunks for a run of " +
                std::to_string(run((uint32_t)t)) + " pairs";
-      total += s.nch[t];
+      item0[t + 1] = item0[t] + s.nch[t];
     }
-    if (total != s.n_items)
-      return std::to_string(s.n_items) + " work items, but the tiles' chunks add up to " + std::to_string(total);
-    int64_t k = 0;
-    for (int64_t i = 0; i < T; i++) {
-      const uint32_t t = s.order[i];
-      for (uint32_t c = 0; c < s.nch[t]; c++, k++)
-        if (s.items[2 * k] != t || s.items[2 * k + 1] != c)
-          return at("work item", k) + " is (" + std::to_string(s.items[2 * k]) + ", " +
-                 std::to_string(s.items[2 * k + 1]) + "), expected (" + std::to_string(t) + ", " + std::to_string(c) +
-                 ")";
+    if (item0[T] != s.n_items)
+      return std::to_string(s.n_items) + " work items, but the tiles' chunks add up to " + std::to_string(item0[T]);
+    std::vector<uint8_t> hit((size_t)std::max<int64_t>(item0[T], 1), 0);
+    for (int64_t k = 0; k < s.n_items; k++) {
+      const uint32_t t = s.items[2 * k], c = s.items[2 * k + 1];
+      if ((int64_t)t >= T) return at("work item", k) + ": tile id " + std::to_string(t) + " out of range";
+      if (c >= s.nch[t])
+        return at("work item", k) + ": chunk " + std::to_string(c) + " of tile " + std::to_string(t) + ", which has " +
+               std::to_string(s.nch[t]);
+      if (hit[item0[t] + c]++)
+        return at("work item", k) + ": (" + std::to_string(t) + ", " + std::to_string(c) + ") listed twice";
     }
   }
   return "";

@@ -168,7 +168,7 @@ struct SortBuffers {
   uint32_t* tile_order;    // [total_tiles] tiles, longest lists first (the compositing order)
   float* g2d;              // [E][kG2D] screen-space gradient accumulators to clear, or nullptr
   uint32_t* order_state;   // [order_state_words()] bucket counts and cursors of the tile order
-  uint32_t* chunk_state;   // [chunk_scan_words(total_tiles)] state of the backward work-item scan
+  uint32_t* n_items;       // the backward work-item count, zeroed here and counted by the forward
   uint32_t* counters;      // [0] binned entries, [1] pairs, [2] overflow flag, [3] sort look-back timeout
   // where the sorted results ended up (index into the ping-pong pairs)
   int dsorted, psorted;
@@ -218,12 +218,8 @@ void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec,
 // `grid` bounds the number of backward work items (pairs / chunk + tiles).
 void launch_blend_bwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
                       const uint32_t* pval, BlendState bs, float* g2d, int batch, int64_t grid, hipStream_t st);
-// sort.hip: the backward work items (tile, chunk) of every tile, from the
-// forward's per-tile chunk counts.  `state` holds chunk_scan_words(tiles)
-// words zeroed by the stage's preparation.
-void launch_chunk_items(const uint32_t* tile_nch, const uint32_t* order, int64_t total_tiles, uint2* items,
-                        int64_t items_cap, uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st);
-int64_t chunk_scan_words(int64_t total_tiles);
+// Words of state of launch_count_scan over n counts.
+int64_t chunk_scan_words(int64_t n);
 // sort.hip: exclusive scan of n counts into off, the sum into *total (device);
 // `state` holds chunk_scan_words(n) words (zeroed here).
 void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* total, uint32_t* state,

@@ -942,9 +942,9 @@ void launch_bin_count(SortBuffers& b, hipStream_t st) {
   const RadixPlan plan{4, 8};
   // one preparation for the whole stage: the depth sort's state, the pair
   // sort's histograms, the tile ranges, the tile order's counts and the
-  // backward work-item scan's state
-  const ZeroList z{{b.order_state, b.chunk_state, b.rstate_pairs, nullptr},
-                   {(int64_t)kOrderStateWords, chunk_scan_words(b.total_tiles), (kGhCopies + 1) * kGhStride, 0}};
+  // backward work-item count
+  const ZeroList z{{b.order_state, b.n_items, b.rstate_pairs, nullptr},
+                   {(int64_t)kOrderStateWords, 1, (kGhCopies + 1) * kGhStride, 0}};
   int64_t prep = rs.words() / 4;
   for (int k = 0; k < 3; k++) prep = std::max(prep, z.n[k]);
   prep = std::max(prep, b.total_tiles);
@@ -1023,27 +1023,7 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bo
   }
 }
 
-namespace {
-// Work items in the tiles' compositing order: the chunks of the heaviest
-// tiles come first.
-struct TileChunks {
-  const uint32_t* nch;
-  const uint32_t* order;
-  __device__ uint32_t operator()(int64_t i) const { return nch[order[i]]; }
-};
-struct ExpandItems {
-  uint2* items;
-  const uint32_t* order;
-  uint32_t cap;
-  __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const {
-    const uint32_t tile = order[i];
-    for (uint32_t k = 0; k < v; k++)
-      if (pre + k < cap) items[pre + k] = make_uint2(tile, k);
-  }
-};
-}  // namespace
-
-int64_t chunk_scan_words(int64_t total_tiles) { return 2 + 2 * ((total_tiles + kChunk - 1) / kChunk + 1); }
+int64_t chunk_scan_words(int64_t n) { return 2 + 2 * ((n + kChunk - 1) / kChunk + 1); }
 
 namespace {
 struct CountVal {
@@ -1067,58 +1047,6 @@ void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* 
   const uint32_t N = (uint32_t)n;
   scan1<false>(CountVal{cnt}, CountOffset{off}, nullptr, N, N, n, state, reinterpret_cast<uint64_t*>(state + 2), total,
                (uint32_t*)nullptr, err, st);
-}
-
-namespace {
-// The work items of up to kOneGroupTiles tiles in one workgroup of 1024
-// threads: each thread takes a run of consecutive positions of the order,
-// a block scan gives the runs' item offsets, and each thread writes its items.
-// (A single launch with no look-back: the scan sits between the two
-// compositing kernels, so its latency is on the step's critical path.  Past
-// a few thousand tiles the serial runs per thread cost more than the
-// look-back of the many-workgroup scan: 213 us for 65k tiles in one
-// workgroup.)
-constexpr int kOneGroupThreads = 1024;
-constexpr int64_t kOneGroupTiles = 1 << 13;
-__global__ void __launch_bounds__(kOneGroupThreads) k_chunk_items(const uint32_t* __restrict__ nch,
-                                                                  const uint32_t* __restrict__ order, uint32_t T,
-                                                                  uint2* __restrict__ items, uint32_t cap,
-                                                                  uint32_t* __restrict__ n_items) {
-  __shared__ uint32_t s_w[kOneGroupThreads / 64];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const uint32_t per = (T + kOneGroupThreads - 1) / kOneGroupThreads;
-  const uint32_t i0 = min((uint32_t)t * per, T), i1 = min(i0 + per, T);
-  uint32_t sum = 0;
-  for (uint32_t i = i0; i < i1; i++) sum += nch[order[i]];
-  const uint32_t inc = wave_scan_incl(sum);
-  if (lane == 63) s_w[wv] = inc;
-  __syncthreads();
-  uint32_t pre = inc - sum, total = 0;
-  for (int w = 0; w < kOneGroupThreads / 64; w++) {
-    pre += (w < wv) ? s_w[w] : 0u;
-    total += s_w[w];
-  }
-  for (uint32_t i = i0; i < i1; i++) {
-    const uint32_t tile = order[i];
-    const uint32_t v = nch[tile];
-    for (uint32_t k = 0; k < v; k++)
-      if (pre + k < cap) items[pre + k] = make_uint2(tile, k);
-    pre += v;
-  }
-  if (t == 0) *n_items = total;
-}
-}  // namespace
-
-void launch_chunk_items(const uint32_t* tile_nch, const uint32_t* order, int64_t total_tiles, uint2* items,
-                        int64_t items_cap, uint32_t* state, uint32_t* n_items, uint32_t* err, hipStream_t st) {
-  const uint32_t T = (uint32_t)total_tiles;
-  if (total_tiles <= kOneGroupTiles) {
-    hipLaunchKernelGGL(k_chunk_items, dim3(1), dim3(kOneGroupThreads), 0, st, tile_nch, order, T, items,
-                       (uint32_t)items_cap, n_items);
-    return;
-  }
-  scan1<false>(TileChunks{tile_nch, order}, ExpandItems{items, order, (uint32_t)items_cap}, nullptr, T, T,
-               total_tiles, state, reinterpret_cast<uint64_t*>(state + 2), n_items, (uint32_t*)nullptr, err, st);
 }
 
 int64_t sort_state_words(int64_t bound, bool pairs) {

@@ -49,9 +49,11 @@ def _check(b):
 def test_consistent_binning_passes(seed):
     b = _binning(seed)
     assert _check(b) == (L.OK, "")
-    # also without the work items, and without the order
+    # also without the work items, without the order, and with the items in any order
     assert _check(dict(b, nch=None, items=None))[0] == L.OK
     assert _check(dict(b, order=None, nch=None, items=None))[0] == L.OK
+    perm = np.random.default_rng(seed).permutation(len(b["items"]))
+    assert _check(dict(b, items=b["items"][perm], order=None))[0] == L.OK
 
 
 def _first_tile_with(b, at_least):
@@ -109,6 +111,10 @@ def _plant(b, what):
         b["items"] = b["items"][:-1]
     elif what == "item":
         b["items"][len(b["items"]) // 2, 1] += 1
+    elif what == "item twice":
+        b["items"][1] = b["items"][0]
+    elif what == "item tile":
+        b["items"][0, 0] = len(b["ranges"])
     return b
 
 
@@ -117,7 +123,7 @@ PLANTS = {"depth order": "order", "tie order": "order", "tile count": "sum to", 
           "tile id": "tile id", "tile order": "tile id", "multiplicity": "appears in", "range end": "range",
           "range start": "range", "empty range": "no pairs", "order duplicate": "twice",
           "order weight": "longer list", "chunk count": "chunks for a run", "item count": "work items",
-          "item": "work item"}
+          "item": "work item", "item twice": "twice", "item tile": "out of range"}
 
 
 @pytest.mark.parametrize("what", list(PLANTS))
