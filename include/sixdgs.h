@@ -146,6 +146,21 @@ const char* sixdgs_last_error(const sixdgs_ctx* ctx);
 sixdgs_status sixdgs_forward(sixdgs_ctx* ctx, const float* params, int64_t n, const sixdgs_camera* cams,
                              int32_t ncam, float* const* images, void* stream);
 
+/* sixdgs_forward with the training step's L1 loss (the L1 term of the 3DGS
+ * loss that Sec. 4.4 and Sec. 5.1 keep) formed as each pixel is written,
+ * instead of by a separate sixdgs_l1_loss over the rendered images:
+ * targets[k] (device [3][H][W], read only) are the reference images,
+ * dl_dimages[k] (device [3][H][W], overwritten) receive dL/dI = sign(I - I*) /
+ * total_count, and the device float `loss` receives mean |I - I*| over every
+ * element of every view, the same values sixdgs_l1_loss gives for the
+ * rendered images (the loss summed per tile, so its last bits may differ).
+ * The state for the backward is kept as by sixdgs_forward.  INVALID_ARG as
+ * sixdgs_forward, or for a NULL targets, dl_dimages, loss or per-view
+ * pointer. */
+sixdgs_status sixdgs_forward_l1(sixdgs_ctx* ctx, const float* params, int64_t n, const sixdgs_camera* cams,
+                                int32_t ncam, float* const* images, const float* const* targets,
+                                float* const* dl_dimages, float* loss, void* stream);
+
 /* Inference cache (Algorithm 1's caption notes that the slice's
  * direction-independent part can be computed once per Gaussian): writes, for
  * each of the n Gaussians in params (device [76][n]), the rows of

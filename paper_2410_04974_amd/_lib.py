@@ -81,6 +81,7 @@ def lib():
         L.sixdgs_last_error.argtypes = [P]
         L.sixdgs_last_error.restype = ctypes.c_char_p
         L.sixdgs_forward.argtypes = [P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
+        L.sixdgs_forward_l1.argtypes = [P, P, I64, ctypes.POINTER(Camera), I32, PP, PP, PP, P, P]
         L.sixdgs_build_cache.argtypes = [P, I64, P, P]
         L.sixdgs_forward_cached.argtypes = [P, P, P, I64, ctypes.POINTER(Camera), I32, PP, P]
         L.sixdgs_backward.argtypes = [P, P, I64, I32, PP, P, P, P]
@@ -104,7 +105,7 @@ def lib():
         L.sixdgs_debug_buffer.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P), ctypes.POINTER(I64)]
         L.sixdgs_set_timing.argtypes = [P, I32]
         L.sixdgs_kernel_time.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
-        for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_backward",
+        for name in ("sixdgs_create", "sixdgs_set_settings", "sixdgs_forward", "sixdgs_forward_l1", "sixdgs_backward",
                      "sixdgs_build_cache", "sixdgs_forward_cached",
                      "sixdgs_backward_adam", "sixdgs_backward_adam_devstep", "sixdgs_l1_loss",
                      "sixdgs_l1_loss_noalloc",
@@ -117,7 +118,7 @@ def lib():
 
 
 EXPORTED = ["sixdgs_default_settings", "sixdgs_create", "sixdgs_destroy", "sixdgs_set_settings",
-            "sixdgs_last_error", "sixdgs_forward", "sixdgs_build_cache", "sixdgs_forward_cached",
+            "sixdgs_last_error", "sixdgs_forward", "sixdgs_forward_l1", "sixdgs_build_cache", "sixdgs_forward_cached",
             "sixdgs_backward", "sixdgs_backward_adam", "sixdgs_backward_adam_devstep", "sixdgs_l1_loss",
             "sixdgs_l1_loss_noalloc",
             "sixdgs_l1_dssim_loss",
@@ -257,7 +258,9 @@ class Context:
         self._rc(lib().sixdgs_set_settings(self._h, ctypes.byref(self.settings)))
 
     # -- rendering -------------------------------------------------------------
-    def forward(self, params, cams, images, stream=None):
+    def forward(self, params, cams, images, stream=None, targets=None, dl_dimages=None, loss=None):
+        """Renders into images; with targets (and dl_dimages, loss) also the L1
+        loss and its dL/dI, formed as the pixels are written."""
         n = params.shape[1]
         _check_f32_cuda(params, "params")
         if params.dim() != 2 or params.shape[0] != 76:
@@ -268,10 +271,24 @@ class Context:
             _check_f32_cuda(im, "image")
             if im.numel() != 3 * int(c.width) * int(c.height):
                 raise ValueError("each image must hold 3*H*W floats")
+        if targets is not None:
+            if dl_dimages is None or loss is None or len(targets) != len(cams) or len(dl_dimages) != len(cams):
+                raise ValueError("targets, dl_dimages and loss: one target and gradient per camera, and the loss")
+            for im, t, g in zip(images, targets, dl_dimages):
+                _check_f32_cuda(t, "target")
+                _check_f32_cuda(g, "dl_dimage")
+                if not (t.numel() == g.numel() == im.numel()):
+                    raise ValueError("image, target and gradient sizes differ")
+            _check_f32_cuda(loss, "loss")
         ccams = (Camera * len(cams))(*[to_camera(c) for c in cams])
         self._fwd_sizes = None
-        self._rc(lib().sixdgs_forward(self._h, ctypes.c_void_p(params.data_ptr()), n, ccams, len(cams),
-                                      _ptrs(images), ctypes.c_void_p(_stream(stream))))
+        if targets is None:
+            self._rc(lib().sixdgs_forward(self._h, ctypes.c_void_p(params.data_ptr()), n, ccams, len(cams),
+                                          _ptrs(images), ctypes.c_void_p(_stream(stream))))
+        else:
+            self._rc(lib().sixdgs_forward_l1(self._h, ctypes.c_void_p(params.data_ptr()), n, ccams, len(cams),
+                                             _ptrs(images), _ptrs(targets), _ptrs(dl_dimages),
+                                             ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(_stream(stream))))
         self.generation += 1
         self._fwd_sizes = [3 * int(c.width) * int(c.height) for c in cams]
 

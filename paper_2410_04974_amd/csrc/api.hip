@@ -312,6 +312,8 @@ BlendState blend_state(sixdgs_ctx* c) {
   bs.items = c->items.p;
   bs.items_cap = c->items.cap;
   bs.n_items = c->counters.p + 4;
+  bs.l1_partial = nullptr;
+  bs.l1_inv = 0.f;
   return bs;
 }
 
@@ -637,7 +639,8 @@ namespace {
 // backward is kept).
 sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cache, int64_t n,
                            const sixdgs_camera* cams, int32_t ncam, float* const* images, bool inference,
-                           void* stream) {
+                           void* stream, const float* const* targets = nullptr, float* const* dl_dimages = nullptr,
+                           float* loss = nullptr) {
   hipStream_t st = (hipStream_t)stream;
   if (n < 0) return fail(c, SIXDGS_ERR_INVALID_ARG, "n must be >= 0");
   if (n > 0 && !params) return fail(c, SIXDGS_ERR_INVALID_ARG, "params is NULL");
@@ -649,6 +652,15 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
   for (int k = 0; k < ncam; k++) {
     if (!images[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "an image pointer is NULL");
     vt.v[k].img = images[k];
+  }
+  const bool with_l1 = targets != nullptr;
+  if (with_l1) {
+    if (!dl_dimages || !loss) return fail(c, SIXDGS_ERR_INVALID_ARG, "targets, dl_dimages and loss: all three");
+    for (int k = 0; k < ncam; k++) {
+      if (!targets[k] || !dl_dimages[k]) return fail(c, SIXDGS_ERR_INVALID_ARG, "a target or dL/dI pointer is NULL");
+      vt.v[k].tgt = targets[k];
+      vt.v[k].dl = dl_dimages[k];
+    }
   }
   const int64_t E = n * ncam;
   if (E > kMaxItems) return fail(c, SIXDGS_ERR_INVALID_ARG, "n * cameras must stay below 2^30");
@@ -696,10 +708,17 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
   c->bwd_grid = grid;
   BlendState bs = blend_state(c);
   bs.counts = want_counts ? c->counts.p : nullptr;
+  if (with_l1) {
+    // each tile's sum of |I - I*|, then their total
+    if (!c->l1_partial.ensure(std::max<int64_t>(vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "loss partials");
+    bs.l1_partial = c->l1_partial.p;
+    bs.l1_inv = 1.0f / (float)(3 * total_px);
+  }
   {
     Timer t(c, SIXDGS_K_BLEND_FWD, st);
     launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->fwd_batch, !inference, st);
   }
+  if (with_l1) launch_l1_final(c->l1_partial.p, vt.total_tiles, bs.l1_inv, loss, st);
   if (inference) return check_launch(c, "blend forward");
   rc = check_launch(c, "blend forward");
   if (rc != SIXDGS_OK) return rc;
@@ -720,6 +739,16 @@ sixdgs_status sixdgs_forward(sixdgs_ctx* c, const float* params, int64_t n, cons
                              float* const* images, void* stream) {
   if (!c) return SIXDGS_ERR_INVALID_ARG;
   return debug_after(c, stream, forward_impl(c, params, nullptr, n, cams, ncam, images, false, stream), 2);
+}
+
+sixdgs_status sixdgs_forward_l1(sixdgs_ctx* c, const float* params, int64_t n, const sixdgs_camera* cams,
+                                int32_t ncam, float* const* images, const float* const* targets,
+                                float* const* dl_dimages, float* loss, void* stream) {
+  if (!c) return SIXDGS_ERR_INVALID_ARG;
+  if (!targets) return fail(c, SIXDGS_ERR_INVALID_ARG, "targets is NULL");
+  return debug_after(c, stream,
+                     forward_impl(c, params, nullptr, n, cams, ncam, images, false, stream, targets, dl_dimages, loss),
+                     2);
 }
 
 sixdgs_status sixdgs_build_cache(const float* params, int64_t n, float* cache, void* stream) {

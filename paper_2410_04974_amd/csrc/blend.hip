@@ -211,6 +211,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
                                                       const uint32_t* __restrict__ pval, BlendState bs) {
   __shared__ FwdWaveLDS W[kWaves];
   __shared__ uint32_t s_maxlast, s_ibase;
+  __shared__ float s_l1[kWaves];
   const int tile = (int)bs.order[blockIdx.x];
   const int vi = find_view(vt, tile);
   const ViewDesc& vd = vt.v[vi];
@@ -351,16 +352,32 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
     S1 += v.z;
     S2 += v.w;
   }
+  float l1 = 0.f;  // this pixel's |I - I*| summed over the channels
   if (inside) {
     const int64_t HW = (int64_t)vd.W * vd.H;
     const int64_t pix = (int64_t)py * vd.W + px;
     // the running sum, whose rounding does not depend on where chunks begin
-    vd.img[pix] = C0 + T * ds.bg[0];
-    vd.img[HW + pix] = C1 + T * ds.bg[1];
-    vd.img[2 * HW + pix] = C2 + T * ds.bg[2];
+    const float o[3] = {C0 + T * ds.bg[0], C1 + T * ds.bg[1], C2 + T * ds.bg[2]};
+#pragma unroll
+    for (int c = 0; c < 3; c++) vd.img[c * HW + pix] = o[c];
     bs.T_final[vd.pix_base + pix] = T;
     bs.last[vd.pix_base + pix] = last;
     if constexpr (COUNTS) bs.counts[vd.pix_base + pix] = cnt;
+    if (bs.l1_partial) {
+      // the L1 loss of the step (Sec. 4.4, Sec. 5.1): dL/dI = sign(I - I*) / count
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const float d = o[c] - vd.tgt[c * HW + pix];
+        l1 += fabsf(d);
+        vd.dl[c * HW + pix] = (d > 0.f) ? bs.l1_inv : ((d < 0.f) ? -bs.l1_inv : 0.f);
+      }
+    }
+  }
+  if (bs.l1_partial) {
+    // the tile's sum in a fixed order: lanes, then wavefronts
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) l1 += __shfl_xor(l1, off);
+    if (l == 0) s_l1[wv] = l1;
   }
   const uint32_t wlast = wave_max(last);
   if (l == 0) atomicMax(&s_maxlast, wlast);
@@ -371,6 +388,11 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
   if (threadIdx.x == 0) {
     bs.tile_nch[tile] = nch;
     s_ibase = nch ? atomicAdd(bs.n_items, nch) : 0u;
+    if (bs.l1_partial) {
+      float sum = 0.f;
+      for (int w = 0; w < kWaves; w++) sum += s_l1[w];
+      bs.l1_partial[tile] = sum;
+    }
   }
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < nch; k += kBlock) {

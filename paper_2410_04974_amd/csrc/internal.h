@@ -37,6 +37,8 @@ struct ViewDesc {
   int64_t pix_base;   // offset of this view in the per-pixel state arrays
   float* img;         // [3][H][W] output (forward)
   const float* dimg;  // [3][H][W] upstream gradient (backward)
+  const float* tgt;   // [3][H][W] L1 target of a forward with the loss, or nullptr
+  float* dl;          // [3][H][W] its dL/dI output
 };
 
 struct ViewTable {
@@ -211,6 +213,8 @@ struct BlendState {
   uint2* items;        // [items_cap] (tile, chunk) backward work items
   int64_t items_cap;
   uint32_t* n_items;   // device count of items
+  float* l1_partial;   // [total_tiles] each tile's sum of |I - I*| when the views carry L1 targets, or nullptr
+  float l1_inv;        // 1 / (elements of all images): dL/dI = sign(I - I*) * l1_inv
 };
 // save = false: the image only, none of the state a backward needs
 void launch_blend_fwd(const ViewTable& vt, const DevSettings& s, const Rec* rec, const uint2* ranges,
@@ -237,6 +241,8 @@ void launch_density_apply(const float* params, const float* m, const float* v, c
 // train.hip
 // Workgroups of the L1 kernel per image at most (one partial sum each).
 constexpr int kL1MaxBlocks = 1024;
+// The loss from per-tile partial sums of |I - I*| (the forward with the L1 loss): loss = sum * inv.
+void launch_l1_final(const float* partial, int64_t count, float inv, float* loss, hipStream_t st);
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,
                float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
 int64_t l1_partial_count(int nimg, const int64_t* numel);

@@ -296,6 +296,10 @@ void launch_l1(int nimg, const float* const* img, const float* const* tgt, const
   hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, off, inv, loss);
 }
 
+void launch_l1_final(const float* partial, int64_t count, float inv, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, count, inv, loss);
+}
+
 int64_t ssim_blocks(int H, int W) {
   return (int64_t)((W + kSsimTile - 1) / kSsimTile) * ((H + kSsimTile - 1) / kSsimTile) * 3;
 }

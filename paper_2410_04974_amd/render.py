@@ -35,10 +35,12 @@ class Renderer:
             kw["tile_w"], kw["tile_h"] = kw.pop("tile")
         self.ctx.set_settings(**kw)
 
-    def forward(self, params, cams, out=None):
+    def forward(self, params, cams, out=None, targets=None, dl_dimages=None, loss=None):
+        """Images of the cameras; with targets, dl_dimages and loss (a float32
+        CUDA [1]) also the L1 loss against the targets and its dL/dI."""
         imgs = out if out is not None else [
             torch.empty((3, c.height, c.width), device=params.device, dtype=torch.float32) for c in cams]
-        self.ctx.forward(params, cams, imgs)
+        self.ctx.forward(params, cams, imgs, targets=targets, dl_dimages=dl_dimages, loss=loss)
         return imgs
 
     def forward_cached(self, params, cache, cams, out=None):
@@ -146,11 +148,13 @@ class Trainer:
         if self._imgs is None or [tuple(i.shape) for i in self._imgs] != [(3, c.height, c.width) for c in cams]:
             self._imgs = [torch.empty((3, c.height, c.width), device=self.params.device) for c in cams]
             self._dl = [torch.empty_like(i) for i in self._imgs]
-        self.renderer.forward(self.params, cams, out=self._imgs)
         if self.lambda_dssim > 0:
+            self.renderer.forward(self.params, cams, out=self._imgs)
             self.renderer.ctx.l1_dssim_loss(self._imgs, targets, self._dl, self.loss, self.lambda_dssim)
         else:
-            self.renderer.ctx.l1_loss(self._imgs, targets, self._dl, self.loss)
+            # the L1 loss and its gradient formed as the forward writes the pixels
+            self.renderer.forward(self.params, cams, out=self._imgs, targets=targets, dl_dimages=self._dl,
+                                  loss=self.loss)
         self.step_count += 1
         if fused:
             # a trained lambda shares the step: its Adam runs after this one, then the count moves on

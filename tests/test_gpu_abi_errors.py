@@ -100,6 +100,31 @@ def test_forward_rejects_bad_arguments_before_any_launch(L):
     assert rc == L.ERR_STATE
 
 
+def test_forward_with_l1_rejects_missing_pointers(L):
+    w, pn = G.scene("c0", 200)
+    p = G.to_dev(pn)
+    cam = synth.default_camera(48, 32)
+    ctx = L.Context()
+    img = torch.full((3, 32, 48), 7.0, device=G.DEV)
+    tgt, dl, loss = torch.zeros_like(img), torch.zeros_like(img), torch.zeros(1, device=G.DEV)
+    cams = _cams(L, [cam])
+    st = ctypes.c_void_p(L._stream(None))
+    pp = ctypes.c_void_p(p.data_ptr())
+    n = pn.shape[1]
+    for targets, dls, lo in ((None, L._ptrs([dl]), loss), (L._ptrs([tgt]), None, loss),
+                             (L._ptrs([tgt]), L._ptrs([dl]), None), ((ctypes.c_void_p * 1)(None), L._ptrs([dl]), loss),
+                             (L._ptrs([tgt]), (ctypes.c_void_p * 1)(None), loss)):
+        rc = L.lib().sixdgs_forward_l1(ctx._h, pp, n, cams, 1, L._ptrs([img]), targets, dls,
+                                       None if lo is None else ctypes.c_void_p(lo.data_ptr()), st)
+        assert rc == L.ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((img == 7.0).all())
+    assert L.lib().sixdgs_forward_l1(ctx._h, pp, n, cams, 1, L._ptrs([img]), L._ptrs([tgt]), L._ptrs([dl]),
+                                     ctypes.c_void_p(loss.data_ptr()), st) == L.OK
+    torch.cuda.synchronize()
+    assert float(loss.item()) == pytest.approx(float(img.abs().mean()), rel=1e-5)
+
+
 def test_backward_view_count_must_match_the_forward(L):
     w, pn = G.scene("c0", 300)
     p = G.to_dev(pn)

@@ -83,6 +83,43 @@ def test_fused_backward_adam_equals_backward_then_adam():
     assert not np.array_equal(outs[0][0], pn)  # the parameters moved
 
 
+@pytest.mark.parametrize("views", [1, 3])
+def test_forward_with_l1_equals_forward_then_l1(views):
+    """The L1 loss formed as the forward writes the pixels: the same images and
+    dL/dI bit for bit as a forward followed by sixdgs_l1_loss, the same loss up
+    to the order of the sum, and the same backward state."""
+    from paper_2410_04974_amd import Renderer, _lib
+    w, pn = G.scene("c2", 20000)
+    cams = [synth.default_camera(160, 128), synth.default_camera(97, 61), synth.default_camera(40, 200)][:views]
+    p = torch.from_numpy(pn).to(G.DEV)
+    tgt = Renderer().forward(torch.from_numpy(synth.perturbed(pn)).to(G.DEV), cams)
+    tgt = [t.clone() for t in tgt]
+    out = []
+    for fused in (False, True):
+        r = Renderer()
+        dl = [torch.full_like(t, 5.0) for t in tgt]
+        loss = torch.full((1,), -1.0, device=G.DEV)
+        if fused:
+            imgs = r.forward(p, cams, targets=tgt, dl_dimages=dl, loss=loss)
+        else:
+            imgs = r.forward(p, cams)
+            r.ctx.l1_loss(imgs, tgt, dl, loss)
+        T = r.ctx.export(_lib.EXPORT_T_FINAL)
+        g = r.backward(p, dl)
+        torch.cuda.synchronize()
+        out.append(([i.clone() for i in imgs], [d.clone() for d in dl], float(loss.item()), T, g.clone()))
+    (i0, d0, l0, T0, g0), (i1, d1, l1, T1, g1) = out
+    assert all(torch.equal(a, b) for a, b in zip(i0, i1))
+    assert all(torch.equal(a, b) for a, b in zip(d0, d1))
+    assert np.array_equal(T0, T1)
+    assert l1 > 0 and abs(l1 - l0) <= 1e-6 * l0
+    assert torch.allclose(g0, g1, rtol=1e-5, atol=1e-6 * float(g0.abs().max()))
+    # an incomplete request is refused before any launch
+    r = Renderer()
+    with pytest.raises(ValueError):
+        r.forward(p, cams, targets=tgt, loss=torch.zeros(1, device=G.DEV))
+
+
 def test_fused_step_count_on_the_device_matches_the_host_count():
     """The fused backward + Adam with the step on the device (the training
     default) against the same kernel given the host's step count: the
