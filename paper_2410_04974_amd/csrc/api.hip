@@ -710,7 +710,8 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
   bs.counts = want_counts ? c->counts.p : nullptr;
   if (with_l1) {
     // each tile's sum of |I - I*|, then their total
-    if (!c->l1_partial.ensure(std::max<int64_t>(vt.total_tiles, 1))) return fail(c, SIXDGS_ERR_OOM, "loss partials");
+    const int64_t parts = std::max<int64_t>(vt.total_tiles, 1);
+    if (!c->l1_partial.ensure(parts + l1_final_scratch(parts))) return fail(c, SIXDGS_ERR_OOM, "loss partials");
     bs.l1_partial = c->l1_partial.p;
     bs.l1_inv = 1.0f / (float)(3 * total_px);
   }
@@ -718,7 +719,7 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
     Timer t(c, SIXDGS_K_BLEND_FWD, st);
     launch_blend_fwd(vt, ds, c->rec.p, c->ranges.p, c->sb.pval[c->sb.psorted], bs, c->fwd_batch, !inference, st);
   }
-  if (with_l1) launch_l1_final(c->l1_partial.p, vt.total_tiles, bs.l1_inv, loss, st);
+  if (with_l1) launch_l1_final(c->l1_partial.p, vt.total_tiles, bs.l1_inv, loss, c->l1_partial.p + vt.total_tiles, st);
   if (inference) return check_launch(c, "blend forward");
   rc = check_launch(c, "blend forward");
   if (rc != SIXDGS_OK) return rc;

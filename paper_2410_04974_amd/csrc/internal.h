@@ -242,7 +242,9 @@ void launch_density_apply(const float* params, const float* m, const float* v, c
 // Workgroups of the L1 kernel per image at most (one partial sum each).
 constexpr int kL1MaxBlocks = 1024;
 // The loss from per-tile partial sums of |I - I*| (the forward with the L1 loss): loss = sum * inv.
-void launch_l1_final(const float* partial, int64_t count, float inv, float* loss, hipStream_t st);
+// scratch: l1_final_scratch(count) floats (none for up to 4,096 partials).
+int64_t l1_final_scratch(int64_t count);
+void launch_l1_final(const float* partial, int64_t count, float inv, float* loss, float* scratch, hipStream_t st);
 void launch_l1(int nimg, const float* const* img, const float* const* tgt, const int64_t* numel,
                float* const* dimg, float* partial, int64_t partial_cap, float* loss, hipStream_t st);
 int64_t l1_partial_count(int nimg, const int64_t* numel);

@@ -49,12 +49,36 @@ __global__ void __launch_bounds__(kBlock) k_l1(L1Images im, float inv_count, flo
   if (threadIdx.x == 0) partial[im.off[k] + blockIdx.x] = t;
 }
 
+// Sum of partial[0, count) by one workgroup, each thread taking kSumRun
+// consecutive values per round with as many loads in flight.
+constexpr int kSumRun = 16;
+constexpr int64_t kSumSpan = (int64_t)kBlock * kSumRun;  // values per round
+__device__ __forceinline__ float block_sum_of(const float* __restrict__ partial, int64_t count) {
+  float acc[kSumRun];
+#pragma unroll
+  for (int u = 0; u < kSumRun; u++) acc[u] = 0.f;
+  for (int64_t i0 = (int64_t)threadIdx.x * kSumRun; i0 < count; i0 += kSumSpan) {
+#pragma unroll
+    for (int u = 0; u < kSumRun; u++) acc[u] += i0 + u < count ? partial[i0 + u] : 0.f;
+  }
+  float a = 0.f;
+#pragma unroll
+  for (int u = 0; u < kSumRun; u++) a += acc[u];
+  return block_sum(a);
+}
+
 __global__ void __launch_bounds__(kBlock) k_l1_final(const float* __restrict__ partial, int64_t count,
                                                      float inv_count, float* __restrict__ loss) {
-  float acc = 0.f;
-  for (int64_t i = threadIdx.x; i < count; i += kBlock) acc += partial[i];
-  const float t = block_sum(acc);
+  const float t = block_sum_of(partial, count);
   if (threadIdx.x == 0) *loss = t * inv_count;
+}
+
+// First level of a long sum: workgroup b sums partial[b kSumSpan, (b + 1) kSumSpan).
+__global__ void __launch_bounds__(kBlock) k_sum_level(const float* __restrict__ partial, int64_t count,
+                                                      float* __restrict__ out) {
+  const int64_t b0 = (int64_t)blockIdx.x * kSumSpan;
+  const float t = block_sum_of(partial + b0, min<int64_t>(kSumSpan, count - b0));
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 int l1_blocks(int64_t numel) {
@@ -296,7 +320,16 @@ void launch_l1(int nimg, const float* const* img, const float* const* tgt, const
   hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, off, inv, loss);
 }
 
-void launch_l1_final(const float* partial, int64_t count, float inv, float* loss, hipStream_t st) {
+int64_t l1_final_scratch(int64_t count) { return count > kSumSpan ? (count + kSumSpan - 1) / kSumSpan : 0; }
+
+void launch_l1_final(const float* partial, int64_t count, float inv, float* loss, float* scratch, hipStream_t st) {
+  if (count > kSumSpan) {
+    // many tiles (several large views): one level of workgroup sums first
+    const int64_t nb = l1_final_scratch(count);
+    hipLaunchKernelGGL(k_sum_level, dim3((unsigned)nb), dim3(kBlock), 0, st, partial, count, scratch);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, (const float*)scratch, nb, inv, loss);
+    return;
+  }
   hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kBlock), 0, st, partial, count, inv, loss);
 }
 

@@ -83,14 +83,17 @@ def test_fused_backward_adam_equals_backward_then_adam():
     assert not np.array_equal(outs[0][0], pn)  # the parameters moved
 
 
-@pytest.mark.parametrize("views", [1, 3])
+@pytest.mark.parametrize("views", [1, 3, "two_1080p"])
 def test_forward_with_l1_equals_forward_then_l1(views):
     """The L1 loss formed as the forward writes the pixels: the same images and
     dL/dI bit for bit as a forward followed by sixdgs_l1_loss, the same loss up
     to the order of the sum, and the same backward state."""
     from paper_2410_04974_amd import Renderer, _lib
     w, pn = G.scene("c2", 20000)
-    cams = [synth.default_camera(160, 128), synth.default_camera(97, 61), synth.default_camera(40, 200)][:views]
+    if views == "two_1080p":  # 16,200 tiles: the loss is summed in two levels
+        cams = [synth.default_camera(1920, 1080), synth.default_camera(1920, 1080)]
+    else:
+        cams = [synth.default_camera(160, 128), synth.default_camera(97, 61), synth.default_camera(40, 200)][:views]
     p = torch.from_numpy(pn).to(G.DEV)
     tgt = Renderer().forward(torch.from_numpy(synth.perturbed(pn)).to(G.DEV), cams)
     tgt = [t.clone() for t in tgt]
@@ -112,7 +115,7 @@ def test_forward_with_l1_equals_forward_then_l1(views):
     assert all(torch.equal(a, b) for a, b in zip(i0, i1))
     assert all(torch.equal(a, b) for a, b in zip(d0, d1))
     assert np.array_equal(T0, T1)
-    assert l1 > 0 and abs(l1 - l0) <= 1e-6 * l0
+    assert l1 > 0 and abs(l1 - l0) <= 1e-5 * l0
     assert torch.allclose(g0, g1, rtol=1e-5, atol=1e-6 * float(g0.abs().max()))
     # an incomplete request is refused before any launch
     r = Renderer()
