@@ -245,14 +245,20 @@ __global__ void __launch_bounds__(kBlock) k_build_cache(const float* __restrict_
 // Where the per-parameter gradient goes: to a gradient buffer, or straight into
 // an Adam step on the parameters (the gradient then never reaches memory).
 struct GradToBuffer {
+  static constexpr bool kAccumulates = false;
   float* grad;
   __device__ void put(int row, int64_t n, int64_t g, float v) const { row_st(grad, row, n, g, v); }
+  __device__ void add(int, float) const {}
 };
 // ... or to this wavefront's rows in LDS ([kRows][64]), for an Adam step
-// that streams the parameter and moment rows afterwards.
+// that streams the parameter and moment rows afterwards.  Rows there can also
+// be summed in place (the colour rows over the views of a several-view call:
+// 48 fewer registers than accumulators).
 struct GradToLDS {
+  static constexpr bool kAccumulates = true;
   float* rows;
   __device__ void put(int row, int64_t, int64_t, float v) const { rows[row * 64 + (threadIdx.x & 63)] = v; }
+  __device__ void add(int row, float v) const { rows[row * 64 + (threadIdx.x & 63)] += v; }
 };
 
 // The chain rule from the screen-space gradients of Gaussian g back to its 76
@@ -271,11 +277,20 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
   // view's tile count and screen-space gradients.
   RawGeom raw;
   load_raw_geom(params, n, g, raw);
-  float beta[16][3];
+  // the colour coefficients: with one view up front with the rest; with
+  // several, read per view (from the cache after the first) rather than held
+  // in 48 registers through the whole view loop
+  float beta[ONE_VIEW ? 16 : 1][3];
+  if constexpr (ONE_VIEW) {
 #pragma unroll
-  for (int k = 0; k < 16; k++)
+    for (int k = 0; k < 16; k++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) beta[k][c] = row_ld(params, kRowSH + 3 * k + c, n, g);
+      for (int c = 0; c < 3; c++) beta[k][c] = row_ld(params, kRowSH + 3 * k + c, n, g);
+  }
+  auto coef = [&](int k, int c) {
+    if constexpr (ONE_VIEW) return beta[k][c];
+    else return row_ld(params, kRowSH + 3 * k + c, n, g);
+  };
   const uint32_t tiles0 = row_ld(tiles, 0, n, g);
   float gp0[kG2D];
 #pragma unroll
@@ -298,11 +313,17 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
   auto put = [&](int row, float v) { sink.put(row, n, g, any ? v : 0.f); };
   // accumulators summed over views; with one view the colour gradient is
   // formed at the end from that view's three channel terms and SH direction
-  float g_beta[ONE_VIEW ? 1 : 16][3];
+  // (or, when the sink sums rows in place, in the sink's colour rows)
+  constexpr bool kInSink = !ONE_VIEW && Sink::kAccumulates;
+  float g_beta[ONE_VIEW || kInSink ? 1 : 16][3];
 #pragma unroll
-  for (int k = 0; k < (ONE_VIEW ? 1 : 16); k++)
+  for (int k = 0; k < (ONE_VIEW || kInSink ? 1 : 16); k++)
 #pragma unroll
     for (int c = 0; c < 3; c++) g_beta[k][c] = 0.f;
+  if constexpr (kInSink) {
+#pragma unroll
+    for (int r = kRowSH; r < kRowSH + 48; r++) sink.put(r, n, g, 0.f);
+  }
   float dsc1[3] = {0.f, 0.f, 0.f}, sdir1[3] = {0.f, 0.f, 1.f};
   float g_mup[3] = {0, 0, 0}, g_mud[3] = {0, 0, 0}, g_alpha = 0.f;
   float g_Sc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dSigma_cond (symmetric)
@@ -329,9 +350,10 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
       // No-SH colour: rgb = sigmoid(c), no dependence on the viewing direction
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        const float col = M::sigmoid(beta[0][c]);
+        const float col = M::sigmoid(coef(0, c));
         dsc[c] = gp[6 + c] * col * (1.f - col);
-        if constexpr (!ONE_VIEW) g_beta[0][c] += dsc[c];
+        if constexpr (kInSink) sink.add(kRowSH + c, dsc[c]);
+        else if constexpr (!ONE_VIEW) g_beta[0][c] += dsc[c];
       }
     } else {
       // SH colour: rgb = sigmoid(sum beta Y(s)), s = (mu_c - C)/|mu_c - C|
@@ -342,15 +364,19 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
       for (int k = 0; k < 16; k++) wsum[k] = 0.f;
 #pragma unroll
       for (int c = 0; c < 3; c++) {
+        float bc[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) bc[k] = coef(k, c);
         float acc = 0.f;
 #pragma unroll
-        for (int k = 0; k < 16; k++) acc += beta[k][c] * Y[k];
+        for (int k = 0; k < 16; k++) acc += bc[k] * Y[k];
         const float col = M::sigmoid(acc);
         dsc[c] = gp[6 + c] * col * (1.f - col);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
-          if constexpr (!ONE_VIEW) g_beta[k][c] += dsc[c] * Y[k];
-          wsum[k] += dsc[c] * beta[k][c];
+          if constexpr (kInSink) sink.add(kRowSH + 3 * k + c, dsc[c] * Y[k]);
+          else if constexpr (!ONE_VIEW) g_beta[k][c] += dsc[c] * Y[k];
+          wsum[k] += dsc[c] * bc[k];
         }
       }
       float gs[3];
@@ -484,15 +510,20 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
       G6[a][3 + b] = 0.5f * GSpd[a][b];
       G6[3 + b][a] = 0.5f * GSpd[a][b];
     }
+  // the factor: kept from the start with one view; with several, formed
+  // again from its rows rather than held through the view loop
+  float Lt[ONE_VIEW ? 1 : 21];
+  if constexpr (!ONE_VIEW) load_cholesky<true>(params, n, g, Lt);
+  const float* L = ONE_VIEW ? s.L : Lt;
 #pragma unroll
   for (int i = 0; i < 6; i++)
 #pragma unroll
     for (int j = 0; j <= i; j++) {
       float acc = 0.f;
 #pragma unroll
-      for (int k = j; k < 6; k++) acc += G6[i][k] * Lget(s.L, k, j);
+      for (int k = j; k < 6; k++) acc += G6[i][k] * Lget(L, k, j);
       const float gl = 2.f * acc;
-      const float Lij = s.L[tri(i, j)];
+      const float Lij = L[tri(i, j)];
       // exp on the diagonal; 2 sigmoid(r) - 1 elsewhere, whose derivative is (1 - L)(1 + L)/2
       const float graw = (i == j) ? gl * Lij : gl * 0.5f * (1.f - Lij) * (1.f + Lij);
       put(kRowL + tri(i, j), graw);
@@ -516,7 +547,7 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
 #pragma unroll
         for (int c = 0; c < 3; c++) put(kRowSH + 3 * k + c, dsc1[c] * Y[k]);
     }
-  } else {
+  } else if constexpr (!kInSink) {
 #pragma unroll
     for (int k = 0; k < 16; k++)
 #pragma unroll
