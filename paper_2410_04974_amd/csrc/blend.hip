@@ -544,15 +544,15 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
     const uint32_t lw = list4[l];
     const int ng = (int)((wn + 3) >> 2);
     // A group of four list slots, back to front.  What does not depend on the
-    // walk's state -- offsets, exponent, take flag, alpha and 1 / (1 - alpha)
-    // -- is formed for all four first, branch-free, so the exponentials and
-    // reciprocals overlap; then the reverse steps run in pairs, each pair's
+    // walk's state -- offsets, exponent, take flag -- is formed for all four
+    // first, branch-free; alpha and 1 / (1 - alpha) only for a pair some lane
+    // takes (c2 backward 209 -> 206 us); then the reverse steps run in pairs, each pair's
     // 18 per-lane values summed in one straight-line reduction (a Gaussian no
     // lane took adds zeros; a pair no lane took is skipped).  The one
     // reduction for both needs no register copies for the in-place lane
     // swaps, which a choice between a joint and two single reductions did.
     auto grad = [&](const Group4& G, int g) {
-      float dxs[4], dys[4], ars[4], as[4], ros[4];
+      float dxs[4], dys[4], ars[4], as[4], ros[4];  // ars: the exponent until the pair is taken
       bool cs[4];
 #pragma unroll
       for (int u = 0; u < 4; u++) {
@@ -563,9 +563,7 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
         dys[u] = fy - G.a[u].y;
         const float p = log2_alpha(G.a[u], make_float4(G.b[u].x, G.b[u].y, 0.f, 0.f), dxs[u], dys[u]);
         cs[u] = in && pos < last && p >= kLog2AlphaMin;
-        ars[u] = exp2_fast(p);
-        as[u] = fminf(kAlphaMax, ars[u]);
-        ros[u] = rcp_fast(1.0f - as[u]);
+        ars[u] = p;
       }
       // one reverse step: updates T and D and fills the per-lane values to sum
       auto step = [&](int u, float (&gv)[kG2D]) {
@@ -595,6 +593,12 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
 #pragma unroll
       for (int h = 1; h >= 0; h--) {
         if (__ballot(cs[2 * h + 1] || cs[2 * h]) == 0) continue;
+#pragma unroll
+        for (int u = 2 * h; u < 2 * h + 2; u++) {
+          ars[u] = exp2_fast(ars[u]);
+          as[u] = fminf(kAlphaMax, ars[u]);
+          ros[u] = rcp_fast(1.0f - as[u]);
+        }
         float ga[kG2D], gb[kG2D];
         step(2 * h + 1, ga);
         step(2 * h, gb);
