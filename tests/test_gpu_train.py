@@ -58,20 +58,38 @@ def test_adam_matches_oracle_over_steps(n):
     assert np.allclose(vd.cpu().numpy(), ref_v, rtol=1e-5, atol=1e-9)
 
 
-def test_fused_backward_adam_equals_backward_then_adam():
+@pytest.mark.parametrize("case", ["one_view", "three_views_lambda", "three_views_rgb"])
+def test_fused_backward_adam_equals_backward_then_adam(case):
+    """Adam inside the chain rule's kernel (the training default) against the
+    gradient written out and the streaming Adam kernel, over three steps.  With
+    several views the fused kernel sums the colour rows in LDS and reads the
+    coefficients per view; a learnable lambda shares the step's count; the
+    densification statistics are accumulated by both."""
     from paper_2410_04974_amd import Renderer, Trainer
     w, pn = G.scene("c2", 20000)
-    cam = synth.default_camera(200, 160)
-    tgt = Renderer().forward(torch.from_numpy(synth.perturbed(pn)).to(G.DEV), [cam])
+    if case == "one_view":
+        cams = [synth.default_camera(200, 160)]
+    else:
+        cams = [synth.default_camera(200, 160), synth.default_camera(97, 61), synth.default_camera(64, 150)]
+    rgb = case == "three_views_rgb"
+    tgt = Renderer(rgb_color=rgb).forward(torch.from_numpy(synth.perturbed(pn)).to(G.DEV), cams)
+    tgt = [t.clone() for t in tgt]
     outs = []
     for fused in (True, False):
         p = torch.from_numpy(pn).to(G.DEV)
-        tr = Trainer(p, Renderer())
+        lam = None
+        if case == "three_views_lambda":
+            lam = torch.from_numpy(np.random.default_rng(7).normal(0.0, 0.5, pn.shape[1]).astype(np.float32)).to(G.DEV)
+        tr = Trainer(p, Renderer(rgb_color=rgb), lambda_raw=lam)
         dens = torch.zeros((2, pn.shape[1]), device=G.DEV)
         for _ in range(3):
-            tr.step([cam], tgt, densify=dens, fused=fused)
+            tr.step(cams, tgt, densify=dens, fused=fused)
         torch.cuda.synchronize()
-        outs.append((tr.params.cpu().numpy(), tr.m.cpu().numpy(), tr.v.cpu().numpy(), dens.cpu().numpy()))
+        assert int(tr.step_counter.item()) == 3
+        o = [tr.params.cpu().numpy(), tr.m.cpu().numpy(), tr.v.cpu().numpy(), dens.cpu().numpy()]
+        if lam is not None:
+            o.append(tr.lambda_raw.cpu().numpy())
+        outs.append(o)
     for a, b in zip(outs[0], outs[1]):
         # The two paths differ in the order of the backward's float atomics (and
         # in where Adam's bias correction is formed).  Adam's update is close to
