@@ -402,8 +402,9 @@ sixdgs_status check_launch(sixdgs_ctx* c, const char* where) {
   return SIXDGS_OK;
 }
 
-// Integer stage after the records and tile counts of E entries exist.
-sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
+// The integer stage's buffers for E entries of the views in c->vt, and its
+// buffer table (before the launch that prepares the stage).
+sixdgs_status prepare_binning(sixdgs_ctx* c, int64_t E) {
   const bool fixed = c->s.pair_capacity > 0;
   if (fixed) {
     if (!ensure_pairs(c, c->s.pair_capacity, 1.0)) return fail(c, SIXDGS_ERR_OOM, "pair buffers");
@@ -416,8 +417,15 @@ sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, hipStream_t st) {
   if (!c->tile_order.ensure(std::max<int64_t>(c->vt.total_tiles, 1)) || !c->order_state.ensure(order_state_words()))
     return fail(c, SIXDGS_ERR_OOM, "tile order");
   fill_sort_buffers(c, E);
+  return SIXDGS_OK;
+}
+
+// Integer stage after the records and tile counts of E entries exist
+// (prepare_binning first; prepped: bin_prep was done by the launch before).
+sixdgs_status run_binning(sixdgs_ctx* c, int64_t E, bool prepped, hipStream_t st) {
+  const bool fixed = c->s.pair_capacity > 0;
   Timer t(c, SIXDGS_K_SORT, st);
-  launch_bin_count(c->sb, st);
+  launch_bin_count(c->sb, prepped, st);
   int64_t hint = c->sb.pcap;
   bool regrown = false;
   if (!fixed) {
@@ -673,16 +681,23 @@ sixdgs_status forward_impl(sixdgs_ctx* c, const float* params, const float* cach
   DevSettings ds = dev_settings(c->s);
   ds.lambda_raw = c->lambda_raw;
   c->fwd_lambda = c->lambda_raw;
-  {
-    Timer t(c, SIXDGS_K_PREPROCESS, st);
-    launch_preprocess(params, cache, n, vt, ds, c->rec.p, c->tiles.p, c->depth.p, st);
-  }
-  sixdgs_status rc = check_launch(c, "preprocess");
-  if (rc != SIXDGS_OK) return rc;
   c->g2d_clean = false;
   if (!inference && !c->g2d.ensure(E * kG2D)) return fail(c, SIXDGS_ERR_OOM, "gradient accumulators");
   c->bin_g2d = inference ? nullptr : c->g2d.p;  // cleared by the binning for the backward
-  rc = run_binning(c, E, st);
+  sixdgs_status rc = prepare_binning(c, E);
+  if (rc != SIXDGS_OK) {
+    c->bin_g2d = nullptr;
+    return rc;
+  }
+  bool prepped;
+  {
+    // the projection also prepares the integer stage
+    const BinPrep bp = bin_prep(c->sb);
+    Timer t(c, SIXDGS_K_PREPROCESS, st);
+    prepped = launch_preprocess(params, cache, n, vt, ds, c->rec.p, c->tiles.p, c->depth.p, &bp, st);
+  }
+  rc = check_launch(c, "preprocess");
+  if (rc == SIXDGS_OK) rc = run_binning(c, E, prepped, st);
   c->bin_g2d = nullptr;
   if (rc != SIXDGS_OK) return rc;
   c->g2d_clean = !inference;
@@ -1098,7 +1113,8 @@ static sixdgs_status bin_body(sixdgs_ctx* c, int64_t n, const sixdgs_camera* cam
   c->vt = vt;
   launch_import_records(u, v, ex, ey, depth, alive, vt, c->rec.p, c->tiles.p, st);
   c->bin_depth = depth;
-  sixdgs_status rc = run_binning(c, E, st);
+  sixdgs_status rc = prepare_binning(c, E);
+  if (rc == SIXDGS_OK) rc = run_binning(c, E, false, st);
   c->bin_depth = nullptr;
   c->fwd_E = E;
   c->fwd_px = 0;

@@ -132,8 +132,27 @@ __device__ __forceinline__ void adam_update(float& p, float g, float& m, float& 
 // preprocess.hip
 // cache: nullptr, or the inference cache of params (then the slice's
 // direction-independent part is read instead of computed)
-void launch_preprocess(const float* params, const float* cache, int64_t n, const ViewTable& vt,
-                       const DevSettings& s, Rec* rec, uint32_t* tiles, float* depth, hipStream_t st);
+// The integer stage's preparation -- state words to zero and the tile ranges
+// set to (UINT_MAX, 0) -- done by the threads of the launch before the stage
+// (thread i takes word i of every region), which saves the stage a launch.
+struct BinPrep {
+  uint32_t* p[4];
+  int64_t n[4];      // words of each region
+  uint2* ranges;
+  int64_t nranges;
+  int64_t threads;   // the largest region: the launch runs at least this many threads
+};
+__device__ __forceinline__ void bin_prep_at(const BinPrep& bp, int64_t i) {
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    if (bp.p[k] && i < bp.n[k]) bp.p[k][i] = 0u;
+  if (bp.ranges && i < bp.nranges) bp.ranges[i] = make_uint2(0xFFFFFFFFu, 0u);  // merged by min / max
+}
+// With bp, the launch also does the integer stage's preparation (then the
+// return value is true and launch_bin_count is told so).
+bool launch_preprocess(const float* params, const float* cache, int64_t n, const ViewTable& vt,
+                       const DevSettings& s, Rec* rec, uint32_t* tiles, float* depth, const BinPrep* bp,
+                       hipStream_t st);
 void launch_build_cache(const float* params, int64_t n, float* cache, hipStream_t st);
 void launch_preprocess_bwd(const float* params, int64_t n, const ViewTable& vt, const DevSettings& s,
                            const uint32_t* tiles, const float* g2d, float* grad, float* densify, hipStream_t st);
@@ -181,7 +200,10 @@ int64_t sort_block_starts(int64_t pcap);
 int64_t order_state_words();
 // Stage 1: compaction of binned entries and their depth sort, then the pair
 // offsets; leaves counters[0] = binned entries, counters[1] = pairs.
-void launch_bin_count(SortBuffers& b, hipStream_t st);
+// The preparation of the integer stage over b (for launch_preprocess).
+BinPrep bin_prep(const SortBuffers& b);
+// prepped: bin_prep(b) has been done by an earlier launch on the stream.
+void launch_bin_count(SortBuffers& b, bool prepped, hipStream_t st);
 // Stage 2: emission of (tile, entry) pairs, their stable tile sort and the
 // per-tile ranges; `pairs_hint` bounds the launch sizes (the capacity in
 // fixed mode, the exact count otherwise).  `regrown`: the pair buffers and

@@ -166,8 +166,10 @@ template <bool CACHED>
 __global__ void __launch_bounds__(kBlock) k_preprocess(const float* __restrict__ params,
                                                        const float* __restrict__ cache, int64_t n, ViewTable vt,
                                                        DevSettings ds, Rec* __restrict__ rec,
-                                                       uint32_t* __restrict__ tiles, float* __restrict__ depth) {
+                                                       uint32_t* __restrict__ tiles, float* __restrict__ depth,
+                                                       BinPrep bp) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bin_prep_at(bp, g);
   if (g >= n) return;
   Static s;
   if constexpr (CACHED)
@@ -629,16 +631,20 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
 
 }  // namespace
 
-void launch_preprocess(const float* params, const float* cache, int64_t n, const ViewTable& vt,
-                       const DevSettings& s, Rec* rec, uint32_t* tiles, float* depth, hipStream_t st) {
-  if (n <= 0) return;
-  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+bool launch_preprocess(const float* params, const float* cache, int64_t n, const ViewTable& vt,
+                       const DevSettings& s, Rec* rec, uint32_t* tiles, float* depth, const BinPrep* bp,
+                       hipStream_t st) {
+  if (n <= 0) return false;
+  BinPrep none{};
+  const BinPrep& p = bp ? *bp : none;
+  const unsigned grid = (unsigned)((std::max<int64_t>(n, p.threads) + kBlock - 1) / kBlock);
   if (cache)
     hipLaunchKernelGGL(k_preprocess<true>, dim3(grid), dim3(kBlock), 0, st, params, cache, n, vt, s, rec, tiles,
-                       depth);
+                       depth, p);
   else
     hipLaunchKernelGGL(k_preprocess<false>, dim3(grid), dim3(kBlock), 0, st, params, cache, n, vt, s, rec, tiles,
-                       depth);
+                       depth, p);
+  return bp != nullptr;
 }
 
 void launch_build_cache(const float* params, int64_t n, float* cache, hipStream_t st) {

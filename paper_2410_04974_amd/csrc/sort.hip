@@ -935,22 +935,43 @@ __global__ void __launch_bounds__(kBlock) k_import(const float* __restrict__ u, 
 
 }  // namespace
 
-void launch_bin_count(SortBuffers& b, hipStream_t st) {
-  const uint32_t E = (uint32_t)b.E;
+namespace {
+RadixState depth_state(const SortBuffers& b) {
   // short sorts take small workgroups (more of them in flight); long ones the pairs' size
-  const RadixState rs = radix_state(b.rstate_depth, b.E, b.E >= kLargeSort ? kRItems : kRItemsSmall, true);
+  return radix_state(b.rstate_depth, b.E, b.E >= kLargeSort ? kRItems : kRItemsSmall, true);
+}
+}  // namespace
+
+// One preparation for the whole stage: the depth sort's state, the pair
+// sort's histograms, the tile ranges, the tile order's counts and the
+// backward work-item count.
+BinPrep bin_prep(const SortBuffers& b) {
+  const RadixState rs = depth_state(b);
+  BinPrep bp{{b.rstate_depth, b.order_state, b.n_items, b.rstate_pairs},
+             {rs.words(), (int64_t)kOrderStateWords, 1, (kGhCopies + 1) * kGhStride},
+             b.ranges,
+             b.total_tiles,
+             0};
+  bp.threads = bp.nranges;
+  for (int k = 0; k < 4; k++) bp.threads = std::max(bp.threads, bp.n[k]);
+  return bp;
+}
+
+void launch_bin_count(SortBuffers& b, bool prepped, hipStream_t st) {
+  const uint32_t E = (uint32_t)b.E;
+  const RadixState rs = depth_state(b);
   const RadixPlan plan{4, 8};
-  // one preparation for the whole stage: the depth sort's state, the pair
-  // sort's histograms, the tile ranges, the tile order's counts and the
-  // backward work-item count
-  const ZeroList z{{b.order_state, b.n_items, b.rstate_pairs, nullptr},
-                   {(int64_t)kOrderStateWords, 1, (kGhCopies + 1) * kGhStride, 0}};
-  int64_t prep = rs.words() / 4;
-  for (int k = 0; k < 3; k++) prep = std::max(prep, z.n[k]);
-  prep = std::max(prep, b.total_tiles);
-  hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
-                     rs.words(), z, b.ranges, b.total_tiles, (const uint32_t*)b.counters, (const uint32_t*)nullptr,
-                     (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0u, (uint32_t*)nullptr, (int64_t)0);
+  if (!prepped) {
+    const ZeroList z{{b.order_state, b.n_items, b.rstate_pairs, nullptr},
+                     {(int64_t)kOrderStateWords, 1, (kGhCopies + 1) * kGhStride, 0}};
+    int64_t prep = rs.words() / 4;
+    for (int k = 0; k < 3; k++) prep = std::max(prep, z.n[k]);
+    prep = std::max(prep, b.total_tiles);
+    hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
+                       rs.words(), z, b.ranges, b.total_tiles, (const uint32_t*)b.counters,
+                       (const uint32_t*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0u,
+                       (uint32_t*)nullptr, (int64_t)0);
+  }
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
   scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.depth, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
               rs.tickets + kMaxPasses, rs.scan_status, &b.counters[0], rs.ghist, &b.counters[3], st);
