@@ -135,6 +135,13 @@ def main():
     dom_ms, dom_launches = r.ctx.kernel_time(dom)
     dom_avg_ms = dom_ms / max(dom_launches, 1)
 
+    # the same step captured as one graph and replayed (context: the timed
+    # region above launches every kernel from the host)
+    r.ctx.set_timing(0)
+    tr.capture([cam], target, warmup=1)
+    ms_graph = _timed(tr.replay, args.steps)
+    r.ctx.check()
+
     # sizes of this workload for the algorithmic byte / flop counts
     sz = r.ctx.sizes()
     nb, P = sz["binned"], sz["pairs"]
@@ -160,6 +167,7 @@ def main():
                    "binned": nb, "pairs": P, "tiles": tiles, "tile": [r.ctx.settings.tile_w, r.ctx.settings.tile_h],
                    "batch": sz["batch"], "chunk": sz["chunk"]},
         "train_steps_per_s": round(1e3 / ms_step, 2),
+        "graph_replay": {"ms_per_step": round(ms_graph, 4), "mpixels_per_s": round(px / (ms_graph * 1e-3) / 1e6, 3)},
         "wall_s_timed": round(wall, 3),
         "kernel_ms": {_lib.KERNEL_NAMES[k]: round(v, 4) for k, v in kt.items()},
         "roofline": roof,
