@@ -302,6 +302,7 @@ bool ensure_scratch(sixdgs_ctx* c, int64_t E, int64_t pcap) {
 BlendState blend_state(sixdgs_ctx* c) {
   BlendState bs{};
   bs.chunk = (uint32_t)c->fwd_chunk;
+  bs.chunk_shift = (uint32_t)__builtin_ctz((unsigned)c->fwd_chunk);
   bs.T_final = c->T_final.p;
   bs.last = c->last.p;
   bs.counts = nullptr;

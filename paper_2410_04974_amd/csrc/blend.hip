@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
       // pixel's transmittance and the colour of the chunk that ends here
       composite(nh);
       nh = 0;
-      const int64_t slot = ((int64_t)rg.x + s0) / chunk;
+      const int64_t slot = ((int64_t)rg.x + s0) >> bs.chunk_shift;
       if (slot < bs.nbound) bs.bound[slot * kBlock + threadIdx.x] = make_float4(T, K0, K1, K2);
       K0 = K1 = K2 = 0.f;
       nbd++;
@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
   // positive terms from the back, so no cancellation against the total
   float S0 = K0, S1 = K1, S2 = K2;
   for (uint32_t m = nbd; m >= 1; m--) {
-    const int64_t slot = ((int64_t)rg.x + (int64_t)m * chunk) / chunk;
+    const int64_t slot = ((int64_t)rg.x + (int64_t)m * chunk) >> bs.chunk_shift;
     if (slot >= bs.nbound) continue;
     float4* q = bs.bound + slot * kBlock + threadIdx.x;
     const float4 v = *q;
@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
   __syncthreads();
   // the tile's backward work items (tile, 0 .. nch - 1), appended to the list
   // where the tiles finished so far end (*n_items is zero before the launch)
-  const uint32_t nch = (s_maxlast + chunk - 1) / chunk;
+  const uint32_t nch = (s_maxlast + chunk - 1) >> bs.chunk_shift;
   if (threadIdx.x == 0) {
     bs.tile_nch[tile] = nch;
     s_ibase = nch ? atomicAdd(bs.n_items, nch) : 0u;
@@ -524,7 +524,7 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
   if (cstart + chunk < last) {
     // the pixel takes Gaussians past this chunk: resume from the state saved
     // where the next chunk begins (otherwise its final state is that state)
-    const int64_t slot = (int64_t)(rg.x + cstart + chunk) / chunk;
+    const int64_t slot = ((int64_t)rg.x + cstart + chunk) >> bs.chunk_shift;
     const float4 st = slot < bs.nbound ? bs.bound[slot * kBlock + threadIdx.x] : make_float4(1.f, 0.f, 0.f, 0.f);
     T = st.x;
     S0 += st.y;

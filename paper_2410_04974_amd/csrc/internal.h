@@ -223,6 +223,7 @@ void launch_import_records(const float* u, const float* v, const float* ex, cons
 // begins.
 struct BlendState {
   uint32_t chunk;
+  uint32_t chunk_shift;  // log2(chunk)
   float* T_final;      // [pixels]
   uint32_t* last;      // [pixels] 1-based list position of the last contributor (0: none)
   uint32_t* counts;    // [pixels] or nullptr
