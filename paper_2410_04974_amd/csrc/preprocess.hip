@@ -248,6 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_build_cache(const float* __restrict_
 // an Adam step on the parameters (the gradient then never reaches memory).
 struct GradToBuffer {
   static constexpr bool kAccumulates = false;
+  static constexpr bool kColourOut = false;
   float* grad;
   __device__ void put(int row, int64_t n, int64_t g, float v) const { row_st(grad, row, n, g, v); }
   __device__ void add(int, float) const {}
@@ -258,20 +259,40 @@ struct GradToBuffer {
 // 48 fewer registers than accumulators).
 struct GradToLDS {
   static constexpr bool kAccumulates = true;
+  static constexpr bool kColourOut = false;
   float* rows;
   __device__ void put(int row, int64_t, int64_t, float v) const { rows[row * 64 + (threadIdx.x & 63)] = v; }
   __device__ void add(int row, float v) const { rows[row * 64 + (threadIdx.x & 63)] += v; }
+};
+// ... or, with one view, only the 28 rows that are not colour coefficients to
+// LDS ([kGeomRows][64]: rows 0..26, then the opacity): the 48 colour rows are
+// the products of three channel terms and the 16 SH basis values of the view
+// direction, handed back (kColourOut) for the Adam step to form row by row.
+constexpr int kGeomRows = kRowSH + 1;
+struct GeomToLDS {
+  static constexpr bool kAccumulates = false;
+  static constexpr bool kColourOut = true;
+  float* rows;
+  __device__ void put(int row, int64_t, int64_t, float v) const {
+    if (row < kRowSH) rows[row * 64 + (threadIdx.x & 63)] = v;
+    else if (row == kRowOpa) rows[kRowSH * 64 + (threadIdx.x & 63)] = v;
+  }
+  __device__ void add(int, float) const {}
 };
 
 // The chain rule from the screen-space gradients of Gaussian g back to its 76
 // parameters, summed over the views, handed to the sink row by row.  params
 // may be updated in place after this returns (by the fused Adam step), so it
 // is not declared __restrict__.
+// With a kColourOut sink (one view), colour_out receives the three channel
+// terms of the colour gradient and the view direction (zeros for an invisible
+// lane) instead of the 48 colour rows going to the sink.
 template <bool ONE_VIEW, class Sink>
 __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int64_t g, const ViewTable& vt,
                                              const DevSettings& ds, const uint32_t* __restrict__ tiles,
                                              const float* __restrict__ g2d, const Sink& sink,
-                                             float* __restrict__ densify) {
+                                             float* __restrict__ densify, float* colour_out = nullptr) {
+  static_assert(ONE_VIEW || !Sink::kColourOut, "the colour terms are handed back for one view only");
   using M = SliceMath<true>;  // the backward differentiates at recomputed values
   if (g >= n) return;
   // Every load that depends on no other is issued before the first branch, so
@@ -535,7 +556,13 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
     put(kRowMuP + k, g_mup[k]);
     put(kRowMuD + k, g_mud[k]);
   }
-  if constexpr (ONE_VIEW) {
+  if constexpr (Sink::kColourOut) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      colour_out[c] = any ? dsc1[c] : 0.f;
+      colour_out[3 + c] = sdir1[c];
+    }
+  } else if constexpr (ONE_VIEW) {
     if (ds.rgb_color) {
 #pragma unroll
       for (int c = 0; c < 3; c++) put(kRowSH + c, dsc1[c]);
@@ -586,10 +613,18 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
                                                                 float* __restrict__ m, float* __restrict__ v,
                                                                 AdamArgs a, int32_t* step_dev, uint32_t* done,
                                                                 float* __restrict__ densify) {
-  __shared__ float s_g[kBlock / 64][kRows * 64];
+  constexpr int kLdsRows = ONE_VIEW ? kGeomRows : kRows;
+  __shared__ float s_g[kBlock / 64][kLdsRows * 64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  bwd_gaussian<ONE_VIEW>(params, n, g, vt, ds, tiles, g2d, GradToLDS{s_g[wv]}, densify);
+  // one view: the colour rows' gradients are formed during the update from
+  // the channel terms and the SH basis of the view direction, so the LDS
+  // holds 28 rows per lane instead of 76 (more resident workgroups)
+  float col[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 1.f};
+  if constexpr (ONE_VIEW)
+    bwd_gaussian<true>(params, n, g, vt, ds, tiles, g2d, GeomToLDS{s_g[wv]}, densify, col);
+  else
+    bwd_gaussian<false>(params, n, g, vt, ds, tiles, g2d, GradToLDS{s_g[wv]}, densify);
   if (step_dev) adam_device_step(a, *step_dev);
   // each lane reads back only what it wrote: ordering the wavefront's own LDS
   // accesses is enough
@@ -597,7 +632,25 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (g < n) {
+    float Y[16];  // colour row 3k + c has gradient col[c] Y[k] (the No-SH colour: Y = (1, 0, ...))
+    if constexpr (ONE_VIEW) {
+      if (ds.rgb_color) {
+#pragma unroll
+        for (int k = 0; k < 16; k++) Y[k] = k == 0 ? 1.f : 0.f;
+      } else {
+        sh_basis(col[3], col[4], col[5], Y);
+      }
+    }
+    auto grad_of = [&](int r) {
+      if constexpr (ONE_VIEW) {
+        if (r >= kRowSH && r < kRowOpa) return col[(r - kRowSH) % 3] * Y[(r - kRowSH) / 3];
+        return s_g[wv][(r == kRowOpa ? kRowSH : r) * 64 + lane];
+      } else {
+        return s_g[wv][r * 64 + lane];
+      }
+    };
     static_assert(kRows % kAdamGroup == 0, "row groups");
+#pragma unroll
     for (int r0 = 0; r0 < kRows; r0 += kAdamGroup) {
       float pp[kAdamGroup], mm[kAdamGroup], vv[kAdamGroup];
 #pragma unroll
@@ -612,7 +665,7 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
         const int grp = adam_row_group(r);  // selected, not indexed: keeps a.lr out of scratch memory
         const float lr = grp == 0 ? a.lr[0] : grp == 1 ? a.lr[1] : grp == 2 ? a.lr[2] : grp == 3 ? a.lr[3]
                        : grp == 4 ? a.lr[4] : a.lr[5];
-        adam_update(pp[j], s_g[wv][r * 64 + lane], mm[j], vv[j], lr, a);
+        adam_update(pp[j], grad_of(r), mm[j], vv[j], lr, a);
         row_st(params, r, n, g, pp[j]);
         row_st(m, r, n, g, mm[j]);
         row_st(v, r, n, g, vv[j]);
