@@ -241,13 +241,17 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
   bool done = !inside;
 
   auto composite = [&](uint32_t nh) {
-    // the group that ends past nh reads stale slots: give them a zero colour
-    // so that their (never used) weight of zero multiplies finite values
-    if ((uint32_t)l < ((4u - (nh & 3u)) & 3u)) B.c[nh + l] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the group that ends past nh would read stale slots: fill them with a
+    // Gaussian no pixel takes (exponent -1e30) and a zero colour, so that
+    // every slot of a group is evaluated alike
+    if ((uint32_t)l < ((4u - (nh & 3u)) & 3u)) {
+      B.a[nh + l] = make_float4(0.f, 0.f, 0.f, 0.f);
+      B.b[nh + l] = make_float2(0.f, -1e30f);
+      B.c[nh + l] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     wave_lds_sync();
     for (uint32_t g = 0; 4 * g < nh; g++) {
       if (__ballot(!done) == 0) break;
-      const uint32_t nu = min(4u, nh - 4 * g);
       float4 A[4], Cc[4];
       float2 Bq[4];
 #pragma unroll
@@ -264,8 +268,8 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const float p = log2_alpha(A[u], make_float4(Bq[u].x, Bq[u].y, 0.f, 0.f), fx - A[u].x, fy - A[u].y);
-        const bool take = (uint32_t)u < nu && !done && p >= kLog2AlphaMin;
-        // the clamp doubles as the mask: min(0, .) is 0 even for a stale slot's inf or NaN
+        const bool take = !done && p >= kLog2AlphaMin;
+        // the clamp doubles as the mask: min(0, .) is 0 whatever the exponent gives
         const float a = fminf(take ? kAlphaMax : 0.f, exp2_fast(p));
         const float Tn = __fmaf_rn(-T, a, T);  // T (1 - a)
         const bool stop = Tn < kTMin;
