@@ -42,7 +42,7 @@ __device__ __forceinline__ Staged stage(const Rec& r, uint32_t e) {
 // arithmetic.
 __device__ __forceinline__ float log2_alpha(const float4& A, const float4& B, float dx, float dy) {
   const float t = __fmaf_rn(A.z, dx, __fmul_rn(A.w, dy));
-  return __fadd_rn(__fmaf_rn(t, dx, __fmul_rn(__fmul_rn(B.x, dy), dy)), B.y);
+  return __fmaf_rn(t, dx, __fmaf_rn(__fmul_rn(B.x, dy), dy, B.y));
 }
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
         const float Tn = __fmaf_rn(-T, a, T);  // T (1 - a)
         const bool stop = Tn < kTMin;
         done = done || stop;
-        const float wgt = stop ? 0.f : a * T;
+        const bool took = take && !stop;  // the same as wgt != 0: a >= 1/255 and T >= 1e-4 when taken
+        const float wgt = took ? a * T : 0.f;
         C0 += Cc[u].x * wgt;
         C1 += Cc[u].y * wgt;
         C2 += Cc[u].z * wgt;
@@ -283,9 +284,9 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
           K0 += Cc[u].x * wgt;
           K1 += Cc[u].y * wgt;
           K2 += Cc[u].z * wgt;
-          last = wgt != 0.f ? __float_as_uint(Cc[u].w) : last;
+          last = took ? __float_as_uint(Cc[u].w) : last;
         }
-        if constexpr (COUNTS) cnt += wgt != 0.f ? 1u : 0u;
+        if constexpr (COUNTS) cnt += took ? 1u : 0u;
       }
     }
   };
