@@ -574,12 +574,12 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
       auto step = [&](int u, float (&gv)[kG2D]) {
         const bool contrib = cs[u];
         const float a = as[u], ro = ros[u], dx = dxs[u], dy = dys[u];
-        const float Tb = T * ro;  // transmittance in front of this Gaussian
-        const float wgt = contrib ? a * Tb : 0.f;
+        const float Tb = T * ro;  // transmittance in front of this Gaussian (T where not taken)
+        const float wgt = a * Tb;
         const float dc = dC0 * G.c[u].x + dC1 * G.c[u].y + dC2 * G.c[u].z;
         const float dl_da = Tb * dc - ro * D;  // dL/dC . (c T_front - S_behind / (1 - alpha))
         D += dc * wgt;
-        T = contrib ? Tb : T;
+        T = Tb;
         // d alpha / d(exponent) = alpha while alpha is below its clamp, zero above
         const float dl_dp = (contrib && ars[u] <= kAlphaMax) ? dl_da * ars[u] : 0.f;
         const float e0 = dl_dp * dx, e1 = dl_dp * dy;
@@ -601,7 +601,9 @@ __global__ void __launch_bounds__(kBlock, 7) k_blend_bwd(ViewTable vt, DevSettin
 #pragma unroll
         for (int u = 2 * h; u < 2 * h + 2; u++) {
           ars[u] = exp2_fast(ars[u]);
-          as[u] = fminf(kAlphaMax, ars[u]);
+          // a lane that does not take the Gaussian gets alpha 0: 1 / (1 - 0) is
+          // exactly 1, so its step leaves T and D exactly as they are
+          as[u] = fminf(cs[u] ? kAlphaMax : 0.f, ars[u]);
           ros[u] = rcp_fast(1.0f - as[u]);
         }
         float ga[kG2D], gb[kG2D];
