@@ -451,11 +451,15 @@ __device__ __forceinline__ void wave_sum18_to_lds(const float (&a)[kG2D], const 
   const float h6 = swap32_add(b[2], b[3]);
   const float h7 = swap32_add(b[4], b[5]);
   const float h8 = swap32_add(b[6], b[7]);
-  const float k0 = row_sum(swap16_add(h0, h1));
-  const float k1 = row_sum(swap16_add(h2, h3));
-  const float k2 = row_sum(swap16_add(h4, h5));
-  const float k3 = row_sum(swap16_add(h6, h7));
-  const float k4 = row_sum(swap16_add(h8, h8));
+  float k0 = row_sum(swap16_add(h0, h1));
+  float k1 = row_sum(swap16_add(h2, h3));
+  float k2 = row_sum(swap16_add(h4, h5));
+  float k3 = row_sum(swap16_add(h6, h7));
+  float k4 = row_sum(swap16_add(h8, h8));
+  // the row sums complete on every lane here: left to itself the compiler
+  // moves each last add into the branch below, which then needs the rotated
+  // value copied out first (three instructions per sum instead of one)
+  asm volatile("" : "+v"(k0), "+v"(k1), "+v"(k2), "+v"(k3), "+v"(k4));
   if ((lane & 15) == 0) {
     const int row = lane >> 4;
     const int f0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
