@@ -62,11 +62,14 @@ __device__ __forceinline__ bool box_hits(const Rec& r, float x0, float y0) {
 // whose line separates m from the rectangle, and along an edge q is a 1D
 // quadratic minimised by clamping.  A relative margin keeps the test
 // conservative under float32 rounding, so it only skips Gaussians that no
-// pixel of the block would take.
+// pixel of the block would take.  The margins (0.1% and 1e-3) are far wider
+// than the errors of the hardware log and reciprocal used here: q_max is off
+// by about 1e-7, and an edge minimiser off by a relative 1e-7 moves q by its
+// square (q is flat there).
 __device__ __forceinline__ bool ellipse_hits(const Rec& r, float x0, float y0) {
   if (!box_hits(r, x0, y0)) return false;
   const float qa = r.a.z, qb = r.a.w, qc = r.b.x;
-  const float lim = 2.0f * logf(255.0f * r.b.y) * 1.001f + 1e-3f;
+  const float lim = (2.0f * kLn2) * __builtin_amdgcn_logf(255.0f * r.b.y) * 1.001f + 1e-3f;
   const float xl = x0 - r.a.x, xh = xl + 7.0f;
   const float yl = y0 - r.a.y, yh = yl + 7.0f;
   const bool inx = xl <= 0.f && xh >= 0.f, iny = yl <= 0.f && yh >= 0.f;
@@ -74,12 +77,12 @@ __device__ __forceinline__ bool ellipse_hits(const Rec& r, float x0, float y0) {
   float best = 3.0e38f;
   if (!inx) {
     const float dx = xl > 0.f ? xl : xh;
-    const float dy = fminf(fmaxf(-qb * dx / qc, yl), yh);
+    const float dy = fminf(fmaxf(-qb * dx * __builtin_amdgcn_rcpf(qc), yl), yh);
     best = fminf(best, qa * dx * dx + 2.0f * qb * dx * dy + qc * dy * dy);
   }
   if (!iny) {
     const float dy = yl > 0.f ? yl : yh;
-    const float dx = fminf(fmaxf(-qb * dy / qa, xl), xh);
+    const float dx = fminf(fmaxf(-qb * dy * __builtin_amdgcn_rcpf(qa), xl), xh);
     best = fminf(best, qa * dx * dx + 2.0f * qb * dx * dy + qc * dy * dy);
   }
   return best <= lim;
