@@ -32,7 +32,7 @@ struct Staged {
 __device__ __forceinline__ Staged stage(const Rec& r, uint32_t e) {
   Staged s;
   s.a = make_float4(r.a.x, r.a.y, -0.5f * kLog2e * r.a.z, -kLog2e * r.a.w);
-  s.b = make_float4(-0.5f * kLog2e * r.b.x, __log2f(r.b.y), 1.0f / r.b.y, __uint_as_float(e));
+  s.b = make_float4(-0.5f * kLog2e * r.b.x, __log2f(r.b.y), __builtin_amdgcn_rcpf(r.b.y), __uint_as_float(e));
   s.c = make_float4(r.c.x, r.c.y, r.c.z, 0.f);
   return s;
 }
@@ -295,17 +295,19 @@ __global__ void __launch_bounds__(kBlock, 5) k_blend_fwd(ViewTable vt, DevSettin
   };
 
   // software pipeline: entry ids two steps ahead, records one step ahead
+  // (past the list the ids stay 0, an entry that exists whenever the list is
+  // not empty: every lane loads a record and the ones past the list go
+  // unused, which spares zeroing the twelve registers every step)
   uint32_t e_cur = 0, e_nxt = 0;
-  Rec r_cur{};
   if ((uint32_t)l < n) e_cur = pv[l];
   if ((uint32_t)(kFwdStep + l) < n) e_nxt = pv[kFwdStep + l];
-  if ((uint32_t)l < n) r_cur = rec[e_cur];
+  Rec r_cur;
+  if (n > 0) r_cur = rec[e_cur];
   uint32_t nh = 0;  // pending hits in B (uniform)
   for (uint32_t s0 = 0; s0 < n; s0 += kFwdStep) {
     if (__ballot(!done) == 0) break;
-    Rec r_nxt{};
+    const Rec r_nxt = rec[e_nxt];
     uint32_t e_nn = 0;
-    if (s0 + kFwdStep + l < n) r_nxt = rec[e_nxt];
     if (s0 + 2 * kFwdStep + l < n) e_nn = pv[s0 + 2 * kFwdStep + l];
     if (SAVE && s0 != 0 && (s0 & (chunk - 1)) == 0) {
       // a backward work item starts here: finish the chunk, then keep this
