@@ -278,6 +278,9 @@ struct GeomToLDS {
     else if (row == kRowOpa) rows[kRowSH * 64 + (threadIdx.x & 63)] = v;
   }
   __device__ void add(int, float) const {}
+  // the 48 colour coefficients the chain rule read, kept for the update
+  // (rows kGeomRows ..): the Adam step does not read them again from memory
+  __device__ void keep(int i, float v) const { rows[(kGeomRows + i) * 64 + (threadIdx.x & 63)] = v; }
 };
 
 // The chain rule from the screen-space gradients of Gaussian g back to its 76
@@ -324,13 +327,23 @@ __device__ __forceinline__ void bwd_gaussian(const float* params, int64_t n, int
   // together.  Otherwise invisible lanes run along with zero accumulators
   // (every view is skipped), so each gradient row is written by one store
   // of the whole wavefront instead of two partial ones.
+  auto keep_coefs = [&]() {
+    if constexpr (Sink::kColourOut) {
+#pragma unroll
+      for (int k = 0; k < 16; k++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) sink.keep(3 * k + c, beta[k][c]);
+    }
+  };
   if (__ballot(any) == 0) {
     for (int r = 0; r < kRows; r++) sink.put(r, n, g, 0.f);
+    keep_coefs();
     if (ds.lambda_raw && ds.grad_lambda) ds.grad_lambda[g] = 0.f;
     return;
   }
   Static s;
   static_from_raw<true>(raw, s);
+  keep_coefs();
 
   // an invisible lane's rows are exact zeros whatever its parameters
   auto put = [&](int row, float v) { sink.put(row, n, g, any ? v : 0.f); };
@@ -613,13 +626,14 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
                                                                 float* __restrict__ m, float* __restrict__ v,
                                                                 AdamArgs a, int32_t* step_dev, uint32_t* done,
                                                                 float* __restrict__ densify) {
-  constexpr int kLdsRows = ONE_VIEW ? kGeomRows : kRows;
+  constexpr int kLdsRows = ONE_VIEW ? kGeomRows + 48 : kRows;
   __shared__ float s_g[kBlock / 64][kLdsRows * 64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   // one view: the colour rows' gradients are formed during the update from
   // the channel terms and the SH basis of the view direction, so the LDS
-  // holds 28 rows per lane instead of 76 (more resident workgroups)
+  // holds 28 gradient rows per lane, and the 48 colour coefficients the chain
+  // rule read, which the update then takes from there instead of memory
   float col[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 1.f};
   if constexpr (ONE_VIEW)
     bwd_gaussian<true>(params, n, g, vt, ds, tiles, g2d, GeomToLDS{s_g[wv]}, densify, col);
@@ -655,7 +669,11 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
       float pp[kAdamGroup], mm[kAdamGroup], vv[kAdamGroup];
 #pragma unroll
       for (int j = 0; j < kAdamGroup; j++) {
-        pp[j] = row_ld(params, r0 + j, n, g);
+        const int r = r0 + j;
+        if (ONE_VIEW && r >= kRowSH && r < kRowOpa)
+          pp[j] = s_g[wv][(kGeomRows + r - kRowSH) * 64 + lane];  // kept by the chain rule
+        else
+          pp[j] = row_ld(params, r, n, g);
         mm[j] = row_ld(m, r0 + j, n, g);
         vv[j] = row_ld(v, r0 + j, n, g);
       }
