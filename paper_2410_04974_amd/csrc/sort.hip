@@ -66,9 +66,13 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t& total)
 // are already running; the wait is bounded and reports a timeout in the error
 // word instead of spinning forever.
 constexpr int kRItems = 16;
-constexpr int kRChunk = kBlock * kRItems;  // items per workgroup and pass over the pairs
-constexpr int kRItemsSmall = 8;           // short depth sorts: 2048 items per workgroup, 2x the workgroups
+constexpr int kRItemsSmall = 8;           // short sorts: 2048 items per workgroup, 2x the workgroups
 constexpr int64_t kLargeSort = 1 << 20;    // from this many entries the depth sort uses kRItems
+constexpr int64_t kLargePairs = 1 << 24;   // from this pair capacity on the pair sort uses kRItems
+// Items per thread of the pair sort's workgroups (and pairs per emission
+// block: kBlock times this).  Measured: 2,048-pair blocks 5 us faster on one
+// 800x800 view (3.2M pairs), 4,096 6% faster on eight 1080p views.
+inline int pair_items(int64_t pcap) { return pcap >= kLargePairs ? kRItems : kRItemsSmall; }
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStIncl = 2u << 30;
 constexpr uint32_t kStVal = kStAgg - 1u;
@@ -287,7 +291,7 @@ struct ZeroList {
 
 // Zeroes the first zero_words words of a radix state, the regions of z and
 // the tile ranges; when given the depth-sorted entries, records for every
-// 4096-pair block the sorted entry whose pairs contain the block's first pair
+// emission block the sorted entry whose pairs contain the block's first pair
 // (normally the pair-offset scan records them; this is for pair buffers that
 // were regrown after it).
 __global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, int64_t zero_words, ZeroList z,
@@ -296,7 +300,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, int64_t ze
                                                        const uint32_t* __restrict__ tiles,
                                                        const uint32_t* __restrict__ dval,
                                                        const uint32_t* __restrict__ poff, uint32_t pcap,
-                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start) {
+                                                       uint32_t* __restrict__ blk_start, int64_t nblk_start,
+                                                       uint32_t chunk) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < zero_words / 4) reinterpret_cast<uint4*>(rs.ghist)[i] = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
@@ -306,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_prep(RadixState rs, int64_t ze
   if (blk_start && i < (int64_t)counters[0] && counters[1] <= pcap) {
     const uint32_t o = poff[i];
     const uint32_t end = o + tiles[dval[i]];
-    for (uint32_t b = (o + kRChunk - 1) / kRChunk; (int64_t)b * kRChunk < end && b < nblk_start; b++)
+    for (uint32_t b = (o + chunk - 1) / chunk; (int64_t)b * chunk < end && b < nblk_start; b++)
       blk_start[b] = (uint32_t)i;
   }
 }
@@ -433,8 +438,9 @@ __global__ void __launch_bounds__(kBlock) k_onesweep(const uint32_t* __restrict_
 // (the wait on earlier workgroups' counts dominated the one-kernel passes at
 // a few thousand workgroups, and the emission counts the first pass's chunks
 // for free):
-// each 4,096-item chunk's digit counts (k_digit_count; for the first pass the
-// emission writes them), one scan per digit over the chunks, offset by the
+// each chunk's digit counts (2,048 or 4,096 items, pair_items; k_digit_count;
+// for the first pass the emission writes them), one scan per digit over the
+// chunks, offset by the
 // counts of the smaller digits (k_digit_scan), and the stable scatter
 // (k_digit_scatter), where chunk b's items of digit d start at the scanned
 // table entry (d, b).  The tables are [digit][chunk]; chunks past the item
@@ -646,20 +652,21 @@ struct SortedTiles {
   const uint32_t* dval;
   __device__ uint32_t operator()(int64_t i) const { return tiles[dval[i]]; }
 };
-// The pair offset of each depth-sorted entry, and for every 4096-pair
-// emission block that starts inside the entry's pairs, the entry.
+// The pair offset of each depth-sorted entry, and for every emission block
+// that starts inside the entry's pairs, the entry.
 struct StoreOffset {
   uint32_t* poff;
   uint32_t* blk_start;
   int64_t nblk_start;
+  int64_t chunk;  // pairs per emission block
   __device__ void operator()(int64_t i, uint32_t pre, uint32_t n) const {
     poff[i] = pre;
-    for (int64_t b = ((int64_t)pre + kRChunk - 1) / kRChunk; b * kRChunk < (int64_t)pre + n && b < nblk_start; b++)
+    for (int64_t b = ((int64_t)pre + chunk - 1) / chunk; b * chunk < (int64_t)pre + n && b < nblk_start; b++)
       blk_start[b] = (uint32_t)i;
   }
 };
 
-// Load-balanced pair emission: workgroup b writes pairs [4096 b, 4096 (b + 1))
+// Load-balanced pair emission: workgroup b writes pairs [chunk b, chunk (b + 1))
 // in depth order.  It walks the depth-sorted entries from the one holding its
 // first pair, 256 entries per step; each thread finds the entry of a pair by
 // binary search over the entries' pair offsets in LDS and the pair's tile from
@@ -672,7 +679,8 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
                                                  const uint32_t* __restrict__ blk_start,
                                                  uint32_t* __restrict__ counters, uint32_t pcap, int npass, int dbits,
                                                  uint32_t* __restrict__ ghist, uint32_t* __restrict__ pkey,
-                                                 uint32_t* __restrict__ pval, uint32_t* __restrict__ table0) {
+                                                 uint32_t* __restrict__ pval, uint32_t* __restrict__ table0,
+                                                 uint32_t chunk) {
   __shared__ uint32_t s_o[kBlock + 1];  // pair offset of each entry of the step; [kBlock]: the next step's
   __shared__ uint32_t s_e[kBlock];      // entry id
   __shared__ uint32_t s_base[kBlock];   // global id of the rectangle's first tile
@@ -689,9 +697,9 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
     if (blockIdx.x == 0 && t == 0) counters[2] = 1u;
     return;
   }
-  const int64_t p0 = (int64_t)blockIdx.x * kRChunk;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
   if (p0 >= P) return;  // uniform
-  const uint32_t p1 = (uint32_t)min<int64_t>(p0 + kRChunk, (int64_t)P);
+  const uint32_t p1 = (uint32_t)min<int64_t>(p0 + chunk, (int64_t)P);
   const uint32_t mask = (1u << dbits) - 1u;
 #pragma unroll
   for (int p = 0; p < kMaxPasses; p++) s_h[p][t] = 0;
@@ -970,7 +978,7 @@ void launch_bin_count(SortBuffers& b, bool prepped, hipStream_t st) {
     hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
                        rs.words(), z, b.ranges, b.total_tiles, (const uint32_t*)b.counters,
                        (const uint32_t*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0u,
-                       (uint32_t*)nullptr, (int64_t)0);
+                       (uint32_t*)nullptr, (int64_t)0, 0u);
   }
   // compaction of the binned entries with their depth keys, and the depth keys' digit histograms
   scan1<true>(BinnedFlag{b.tiles}, CompactDepth{b.depth, b.dkey[0], b.dval[0]}, nullptr, E, E, b.E,
@@ -978,7 +986,8 @@ void launch_bin_count(SortBuffers& b, bool prepped, hipStream_t st) {
   // depth order (stable: equal depths keep entry order)
   b.dsorted = radix_sort(b.dkey, b.dval, &b.counters[0], b.E, plan, rs, &b.counters[3], st);
   // pair offsets in depth order
-  scan1<false>(SortedTiles{b.tiles, b.dval[b.dsorted]}, StoreOffset{b.poff, b.blk_start, b.nblk_start},
+  scan1<false>(SortedTiles{b.tiles, b.dval[b.dsorted]},
+               StoreOffset{b.poff, b.blk_start, b.nblk_start, (int64_t)kBlock * pair_items(b.pcap)},
                &b.counters[0], 0u, E, b.E,
                rs.tickets + kMaxPasses + 1, rs.scan_status + rs.nscan, &b.counters[1], (uint32_t*)nullptr,
                &b.counters[3], st);
@@ -989,7 +998,9 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bo
   while ((1ll << bits) < (int64_t)vt.total_tiles) bits++;
   const RadixPlan plan = radix_plan(bits);
   const int64_t bound = pairs_hint < b.pcap ? pairs_hint : b.pcap;
-  const RadixState rs = radix_state(b.rstate_pairs, bound, kRItems, false);
+  const int items = pair_items(b.pcap);
+  const uint32_t chunk = (uint32_t)(kBlock * items);
+  const RadixState rs = radix_state(b.rstate_pairs, bound, items, false);
   if (regrown) {
     // the passes write every table entry they read: only the histograms (and
     // the unused tickets) start from zero
@@ -999,7 +1010,7 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bo
     hipLaunchKernelGGL(k_stage_prep, dim3((unsigned)((prep + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rs,
                        zero_words, z, (uint2*)nullptr, (int64_t)0, (const uint32_t*)b.counters,
                        (const uint32_t*)b.tiles, (const uint32_t*)b.dval[b.dsorted], (const uint32_t*)b.poff,
-                       (uint32_t)b.pcap, b.blk_start, rs.nblk);
+                       (uint32_t)b.pcap, b.blk_start, rs.nblk, chunk);
   }
   // the pairs, with every pass's digit histogram and the first pass's per-chunk
   // counts; then the passes, each a scan of the chunk counts and a scatter
@@ -1010,17 +1021,19 @@ void launch_bin_emit(SortBuffers& b, const ViewTable& vt, int64_t pairs_hint, bo
     const uint32_t cap = (uint32_t)bound;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kBlock), 0, st, vt, b.rec, b.dval[b.dsorted], b.poff,
                        b.blk_start, b.counters, (uint32_t)b.pcap, plan.npass, plan.dbits, rs.ghist, b.pkey[0],
-                       b.pval[0], rs.status);
+                       b.pval[0], rs.status, chunk);
     for (int p = 0; p < plan.npass; p++) {
       uint32_t* table = rs.status + (int64_t)p * nb * 256;
       const int shift = p * plan.dbits;
       if (p > 0)
-        hipLaunchKernelGGL(k_digit_count<kRItems>, dim3((unsigned)nb), dim3(kBlock), 0, st, b.pkey[cur],
+        hipLaunchKernelGGL(items == kRItems ? k_digit_count<kRItems> : k_digit_count<kRItemsSmall>, dim3((unsigned)nb),
+                           dim3(kBlock), 0, st, b.pkey[cur],
                            (const uint32_t*)&b.counters[1], cap, shift, plan.dbits, table, nb);
       hipLaunchKernelGGL(k_digit_scan, dim3(1u << plan.dbits), dim3(kBlock), 0, st, table, nb,
-                         (const uint32_t*)&b.counters[1], cap, kRChunk, (const uint32_t*)(rs.ghist + p * 256));
+                         (const uint32_t*)&b.counters[1], cap, (int)chunk, (const uint32_t*)(rs.ghist + p * 256));
       const bool last = p == plan.npass - 1;
-      hipLaunchKernelGGL(k_digit_scatter<kRItems>, dim3((unsigned)nb), dim3(kBlock), 0, st, b.pkey[cur],
+      hipLaunchKernelGGL(items == kRItems ? k_digit_scatter<kRItems> : k_digit_scatter<kRItemsSmall>,
+                         dim3((unsigned)nb), dim3(kBlock), 0, st, b.pkey[cur],
                          b.pval[cur], b.pkey[cur ^ 1], b.pval[cur ^ 1], (const uint32_t*)&b.counters[1], cap, shift,
                          plan.dbits, (const uint32_t*)table, nb, last ? b.ranges : nullptr,
                          (uint32_t)vt.total_tiles, (const uint32_t*)b.counters, (uint32_t)b.pcap);
@@ -1071,9 +1084,10 @@ void launch_count_scan(const uint32_t* cnt, int64_t n, uint32_t* off, uint32_t* 
 }
 
 int64_t sort_state_words(int64_t bound, bool pairs) {
-  return radix_state(nullptr, bound, pairs ? kRItems : kRItemsSmall, !pairs).words();
+  // the pair state sized for the smaller blocks, whichever pair_items picks
+  return radix_state(nullptr, bound, kRItemsSmall, !pairs).words();
 }
-int64_t sort_block_starts(int64_t pcap) { return radix_blocks(pcap, kRItems) + 1; }
+int64_t sort_block_starts(int64_t pcap) { return radix_blocks(pcap, kRItemsSmall) + 1; }
 int64_t order_state_words() { return kOrderStateWords; }
 
 void launch_zero_g2d(const SortBuffers& b, float* g2d, hipStream_t st) {
