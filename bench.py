@@ -204,11 +204,16 @@ def roofline(r, dom, avg_ms, n, nb, P, px, tiles, params, cam, target):
         counts = float(cnt_r.ctx.export(_lib.EXPORT_COUNTS).astype(np.float64).sum())
         per = FWD_FLOPS_PER_CONTRIB if dom == _lib.K_BLEND_FWD else BWD_FLOPS_PER_CONTRIB
         achieved = per * counts / (avg_ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic(name, settings),
-                "peak_nonpacked": round(ALU_NONPACKED_TFLOPS, 2),
-                "frac_nonpacked": round(achieved / ALU_NONPACKED_TFLOPS, 4),
-                "avg_ms": round(avg_ms, 4), "contributions_per_launch": counts, "flops_per_contribution": per}
+        out = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic(name, settings),
+               "peak_nonpacked": round(ALU_NONPACKED_TFLOPS, 2),
+               "frac_nonpacked": round(achieved / ALU_NONPACKED_TFLOPS, 4),
+               "avg_ms": round(avg_ms, 4), "contributions_per_launch": counts, "flops_per_contribution": per}
+        if dom == _lib.K_BLEND_BWD:
+            visited = visited_block_pairs(cnt_r.ctx, cam)
+            out["visited_block_pairs"] = visited
+            out["lane_utilisation"] = round(counts / (64.0 * visited), 4) if visited else None
+        return out
     if dom == _lib.K_PREPROCESS:
         bytes_ = 304 * n + 4 * n + 52 * nb
     elif dom == _lib.K_PREPROCESS_BWD:
@@ -496,6 +501,56 @@ def bench_render(args):
            "ms_per_step": res["r2"]["ms_per_frame"], "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "vs_baseline": None, "config": {"workload": "r2: " + res["r2"]["description"]}, "scenes": res}
     print(json.dumps(out), flush=True)
+
+
+def visited_block_pairs(ctx, cam):
+    """(8x8 block, Gaussian) pairs the backward evaluates on one view: a
+    Gaussian of the tile's list whose alpha >= 1/255 ellipse meets the block
+    (the kernels' conservative test), at a list position before the block's
+    last contributor.  64 lanes evaluate each such pair, so contributions over
+    64 of these is the share of lanes doing work that counts."""
+    import numpy as np
+    from paper_2410_04974_amd import _lib
+
+    s = ctx.settings
+    tw, th = int(s.tile_w), int(s.tile_h)
+    W, H = int(cam.width), int(cam.height)
+    rec = ctx.export(_lib.EXPORT_RECORDS).astype(np.float64)
+    vals = ctx.export(_lib.EXPORT_VALUES).astype(np.int64)
+    rng = ctx.export(_lib.EXPORT_RANGES).astype(np.int64)
+    last = ctx.export(_lib.EXPORT_LAST)[: W * H].reshape(H, W).astype(np.int64)
+    ntx, nty = -(-W // tw), -(-H // th)
+    T = ntx * nty
+    n_t = rng[:T, 1] - rng[:T, 0]
+    idx = np.concatenate([np.arange(a, b) for a, b in rng[:T]] + [np.zeros(0, np.int64)])
+    t_of = np.repeat(np.arange(T), n_t)
+    j_of = idx - np.repeat(rng[:T, 0], n_t)  # list position within the tile
+    r = rec[vals[idx]]
+    u, v, qa, qb, qc, al, ex, ey = (r[:, k] for k in range(8))
+    lim = 2.0 * np.log(np.maximum(255.0 * al, 1e-30)) * 1.001 + 1e-3
+    pad = np.zeros((nty * th, ntx * tw), np.int64)
+    pad[:H, :W] = last
+    total = 0
+    for by in range(0, th, 8):
+        for bx in range(0, tw, 8):
+            blk = pad.reshape(nty, th, ntx, tw)[:, by:by + 8, :, bx:bx + 8].max(axis=(1, 3)).reshape(-1)
+            x0 = (t_of % ntx) * tw + bx + 0.5
+            y0 = (t_of // ntx) * th + by + 0.5
+            box = (u + ex >= x0 - 1) & (u - ex <= x0 + 8) & (v + ey >= y0 - 1) & (v - ey <= y0 + 8)
+            xl, yl = x0 - u, y0 - v
+            xh, yh = xl + 7, yl + 7
+            inx, iny = (xl <= 0) & (xh >= 0), (yl <= 0) & (yh >= 0)
+            best = np.full(u.shape, np.inf)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                dx = np.where(xl > 0, xl, xh)
+                dy = np.clip(-qb * dx / qc, yl, yh)
+                best = np.where(~inx, np.minimum(best, qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy), best)
+                dy = np.where(yl > 0, yl, yh)
+                dx = np.clip(-qb * dy / qa, xl, xh)
+                best = np.where(~iny, np.minimum(best, qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy), best)
+            hit = box & ((inx & iny) | (best <= lim))
+            total += int(np.count_nonzero(hit & (j_of < blk[t_of])))
+    return total
 
 
 def Renderer_with_counts(r):
