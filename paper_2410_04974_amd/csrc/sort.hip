@@ -706,16 +706,22 @@ __global__ void __launch_bounds__(kBlock) k_emit(ViewTable vt, const Rec* __rest
   for (;;) {
     const uint32_t i = ib + t;
     if (i < nb) {
-      const uint32_t e = dval[i];
-      const ViewDesc& vd = vt.v[e / (uint64_t)vt.n];
-      const float4 ra = rec[e].a, rb = rec[e].b;
-      int x0, y0, x1, y1;
-      tile_rect(ra.x, ra.y, rb.z, rb.w, vt.tile_shift_x, vt.tile_shift_y, vd.ntx, vd.nty, x0, y0, x1, y1);
-      s_o[t] = poff[i];
-      s_e[t] = e;
-      s_base[t] = (uint32_t)(vd.tile_base + y0 * vd.ntx + x0);
-      s_w[t] = (uint32_t)(x1 - x0);
-      s_ntx[t] = (uint32_t)vd.ntx;
+      const uint32_t o = poff[i];
+      s_o[t] = o;
+      // an entry whose pairs start past this block is never chosen by the
+      // search below: its record is not read (a block of 2,048 pairs needs
+      // about a hundred of the step's entries)
+      if (o < p1) {
+        const uint32_t e = dval[i];
+        const ViewDesc& vd = vt.v[e / (uint64_t)vt.n];
+        const float4 ra = rec[e].a, rb = rec[e].b;
+        int x0, y0, x1, y1;
+        tile_rect(ra.x, ra.y, rb.z, rb.w, vt.tile_shift_x, vt.tile_shift_y, vd.ntx, vd.nty, x0, y0, x1, y1);
+        s_e[t] = e;
+        s_base[t] = (uint32_t)(vd.tile_base + y0 * vd.ntx + x0);
+        s_w[t] = (uint32_t)(x1 - x0);
+        s_ntx[t] = (uint32_t)vd.ntx;
+      }
     } else {
       s_o[t] = P;  // past the last entry: never chosen by the search below
     }
