@@ -674,8 +674,10 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
           pp[j] = s_g[wv][(kGeomRows + r - kRowSH) * 64 + lane];  // kept by the chain rule
         else
           pp[j] = row_ld(params, r, n, g);
-        mm[j] = row_ld(m, r0 + j, n, g);
-        vv[j] = row_ld(v, r0 + j, n, g);
+        // the moments are touched once per step: streamed past the caches,
+        // which keep the parameters for the next step's preprocess instead
+        mm[j] = __builtin_nontemporal_load(row_ptr(m, r0 + j, n, g));
+        vv[j] = __builtin_nontemporal_load(row_ptr(v, r0 + j, n, g));
       }
 #pragma unroll
       for (int j = 0; j < kAdamGroup; j++) {
@@ -685,8 +687,8 @@ __global__ void __launch_bounds__(kBlock) k_preprocess_bwd_adam(float* params, i
                        : grp == 4 ? a.lr[4] : a.lr[5];
         adam_update(pp[j], grad_of(r), mm[j], vv[j], lr, a);
         row_st(params, r, n, g, pp[j]);
-        row_st(m, r, n, g, mm[j]);
-        row_st(v, r, n, g, vv[j]);
+        __builtin_nontemporal_store(mm[j], row_ptr(m, r, n, g));
+        __builtin_nontemporal_store(vv[j], row_ptr(v, r, n, g));
       }
     }
   }
