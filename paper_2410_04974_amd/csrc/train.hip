@@ -250,6 +250,8 @@ __device__ __forceinline__ void device_bias(AdamArgs& a, const int32_t* step_dev
 
 __global__ void k_step_inc(int32_t* step_dev) { *step_dev += 1; }
 
+typedef float F4 __attribute__((ext_vector_type(4)));  // a native vector for the non-temporal builtins
+
 // grid.y = parameter row, grid.x covers the row (float4 when n % 4 == 0)
 __global__ void __launch_bounds__(kBlock) k_adam4(float4* __restrict__ p, const float4* __restrict__ g,
                                                   float4* __restrict__ m, float4* __restrict__ v, int64_t n4,
@@ -260,14 +262,20 @@ __global__ void __launch_bounds__(kBlock) k_adam4(float4* __restrict__ p, const 
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n4) return;
   const int64_t k = (int64_t)r * n4 + i;
-  float4 pp = p[k], gg = g[k], mm = m[k], vv = v[k];
+  // the moments are touched once per step: streamed past the caches, which
+  // keep the parameters for the next step's preprocess instead
+  const F4 m0 = __builtin_nontemporal_load(reinterpret_cast<const F4*>(m + k));
+  const F4 v0 = __builtin_nontemporal_load(reinterpret_cast<const F4*>(v + k));
+  float4 pp = p[k], gg = g[k];
+  float4 mm = make_float4(m0.x, m0.y, m0.z, m0.w), vv = make_float4(v0.x, v0.y, v0.z, v0.w);
   adam_update(pp.x, gg.x, mm.x, vv.x, lr, a);
   adam_update(pp.y, gg.y, mm.y, vv.y, lr, a);
   adam_update(pp.z, gg.z, mm.z, vv.z, lr, a);
   adam_update(pp.w, gg.w, mm.w, vv.w, lr, a);
   p[k] = pp;
-  m[k] = mm;
-  v[k] = vv;
+  const F4 m1 = {mm.x, mm.y, mm.z, mm.w}, v1 = {vv.x, vv.y, vv.z, vv.w};
+  __builtin_nontemporal_store(m1, reinterpret_cast<F4*>(m + k));
+  __builtin_nontemporal_store(v1, reinterpret_cast<F4*>(v + k));
 }
 
 __global__ void __launch_bounds__(kBlock) k_adam1(float* __restrict__ p, const float* __restrict__ g,
@@ -279,11 +287,11 @@ __global__ void __launch_bounds__(kBlock) k_adam1(float* __restrict__ p, const f
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int64_t k = (int64_t)r * n + i;
-  float pp = p[k], mm = m[k], vv = v[k];
+  float pp = p[k], mm = __builtin_nontemporal_load(m + k), vv = __builtin_nontemporal_load(v + k);
   adam_update(pp, g[k], mm, vv, lr, a);
   p[k] = pp;
-  m[k] = mm;
-  v[k] = vv;
+  __builtin_nontemporal_store(mm, m + k);
+  __builtin_nontemporal_store(vv, v + k);
 }
 
 }  // namespace
